@@ -1,0 +1,239 @@
+"""ctypes harness around the oracle's C numerical core.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+from .mesh import OracleMesh
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wlseno_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+FLUX = {"advection": 0, "burgers": 1, "euler": 2}
+
+
+def build(force: bool = False) -> str:
+    """Compile the C core with gcc (-O2 -ffp-contract=off, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int)
+        _lib.or_num_coeffs.argtypes = [C.c_int, C.c_int]
+        _lib.or_basis.argtypes = [C.c_int, C.c_int, ip]
+        _lib.or_simplex_avg_monomial.argtypes = [C.c_int, dp, dp, ip]
+        _lib.or_simplex_avg_monomial.restype = C.c_double
+        _lib.or_wls_qrcp_solve.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_double, dp, dp, ip]
+        _lib.or_eval_taylor.argtypes = [C.c_int, C.c_int, ip, dp, dp]
+        _lib.or_eval_taylor.restype = C.c_double
+        pp = C.POINTER(_Problem)
+        _lib.or_cell_matrix.argtypes = [pp, C.c_int, dp]
+        _lib.or_cell_weights.argtypes = [pp, C.c_int, dp, dp]
+        _lib.or_reconstruct.argtypes = [pp, dp, dp, dp, ip, C.POINTER(C.c_ubyte)]
+        _lib.or_reconstruct_cells.argtypes = [pp, dp, C.c_int, ip, dp, dp, ip, C.POINTER(C.c_ubyte)]
+        _lib.or_rhs.argtypes = [pp, dp, dp, dp]
+        _lib.or_rk3.argtypes = [pp, dp, C.c_double, C.c_int]
+    return _lib
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("p", C.c_int), ("m", C.c_int), ("nvars", C.c_int),
+        ("flux", C.c_int), ("weight_mode", C.c_int),
+        ("nc", C.c_int), ("nq", C.c_int), ("periodic", C.c_int),
+        ("period", C.c_double), ("eps", C.c_double), ("alpha_w", C.c_double),
+        ("rank_tol", C.c_double), ("h", C.c_double), ("gamma", C.c_double),
+        ("adv", C.c_double * 3),
+        ("exps", C.POINTER(C.c_int)),
+        ("cv", C.POINTER(C.c_double)),
+        ("cent", C.POINTER(C.c_double)),
+        ("vol", C.POINTER(C.c_double)),
+        ("nbr", C.POINTER(C.c_int)),
+        ("row_ptr", C.POINTER(C.c_int)),
+        ("col", C.POINTER(C.c_int)),
+        ("qx", C.POINTER(C.c_double)),
+        ("qw", C.POINTER(C.c_double)),
+        ("normal", C.POINTER(C.c_double)),
+        ("area", C.POINTER(C.c_double)),
+    ]
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def num_coeffs(dim: int, p: int) -> int:
+    return int(lib().or_num_coeffs(dim, p))
+
+
+def basis(dim: int, p: int) -> np.ndarray:
+    m = num_coeffs(dim, p)
+    exps = np.zeros((m, 3), dtype=np.int32)
+    lib().or_basis(dim, p, _ip(exps))
+    return exps
+
+
+def simplex_avg_monomial(verts, center, a) -> float:
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    dim = verts.shape[1]
+    c = np.ascontiguousarray(center, dtype=np.float64)
+    a = np.ascontiguousarray(list(a) + [0] * (3 - len(a)), dtype=np.int32)
+    return float(lib().or_simplex_avg_monomial(dim, _dp(verts), _dp(c), _ip(a)))
+
+
+def wls_qrcp_solve(A, w, b, rank_tol: float = 1e-12):
+    """Column-scaled weighted LS by Householder QRCP; returns (v, rank, rdiag, perm)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n, m = A.shape
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    v = np.zeros(m)
+    rd = np.zeros(min(n, m))
+    perm = np.zeros(m, dtype=np.int32)
+    r = lib().or_wls_qrcp_solve(n, m, _dp(A), _dp(w), _dp(b), rank_tol, _dp(v), _dp(rd), _ip(perm))
+    return v, int(r), rd, perm
+
+
+def eval_taylor(dim, exps, v, dx) -> float:
+    exps = np.ascontiguousarray(exps, dtype=np.int32)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    dx = np.ascontiguousarray(list(dx) + [0.0] * (3 - len(dx)), dtype=np.float64)
+    return float(lib().or_eval_taylor(dim, exps.shape[0], _ip(exps), _dp(v), _dp(dx)))
+
+
+class Oracle:
+    """FP64 reference of the WLS-ENO finite-volume right-hand side and RK3 step."""
+
+    def __init__(self, dim, verts, cells, periodic=False, *, p=3, n_lo=None, n_hi=None,
+                 flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2, alpha_w=1.5,
+                 rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None):
+        self.mesh = OracleMesh(dim, verts, cells, periodic, p=p)
+        om = self.mesh
+        self.dim, self.p, self.nc = om.dim, int(p), om.nc
+        self.exps = basis(dim, p)
+        self.m = self.exps.shape[0]
+        self.nvars = dim + 2 if flux == "euler" else 1
+        if n_lo is None:
+            n_lo = self.m
+        if n_hi is None:
+            n_hi = 2 * self.m
+        self.n_lo, self.n_hi = int(n_lo), int(n_hi)
+        if stencil is None:
+            stencil = om.stencils(self.n_lo, self.n_hi)
+        self.row_ptr = np.ascontiguousarray(stencil[0], dtype=np.int32)
+        self.col = np.ascontiguousarray(stencil[1], dtype=np.int32)
+        self.h = om.h if h is None else float(h)
+        self._keep = dict(
+            exps=np.ascontiguousarray(self.exps, dtype=np.int32),
+            cv=np.ascontiguousarray(om.cv, dtype=np.float64),
+            cent=np.ascontiguousarray(om.cent, dtype=np.float64),
+            vol=np.ascontiguousarray(om.vol, dtype=np.float64),
+            nbr=np.ascontiguousarray(om.nbr, dtype=np.int32),
+            qx=np.ascontiguousarray(om.qx, dtype=np.float64),
+            qw=np.ascontiguousarray(om.qw, dtype=np.float64),
+            normal=np.ascontiguousarray(om.normal, dtype=np.float64),
+            area=np.ascontiguousarray(om.area, dtype=np.float64),
+        )
+        k = self._keep
+        P = _Problem()
+        P.dim, P.p, P.m, P.nvars = om.dim, self.p, self.m, self.nvars
+        P.flux, P.weight_mode = FLUX[flux], int(weight_mode)
+        P.nc, P.nq, P.periodic = om.nc, om.nq, int(om.periodic)
+        P.period, P.eps, P.alpha_w, P.rank_tol = om.period, eps, alpha_w, rank_tol
+        P.h, P.gamma = self.h, gamma
+        for d in range(3):
+            P.adv[d] = float(velocity[d]) if d < len(velocity) else 0.0
+        P.exps = _ip(k["exps"])
+        P.cv, P.cent, P.vol = _dp(k["cv"]), _dp(k["cent"]), _dp(k["vol"])
+        P.nbr = _ip(k["nbr"])
+        P.row_ptr, P.col = _ip(self.row_ptr), _ip(self.col)
+        P.qx, P.qw = _dp(k["qx"]), _dp(k["qw"])
+        P.normal, P.area = _dp(k["normal"]), _dp(k["area"])
+        self._P = P
+        self.flux = flux
+        self.nq = om.nq
+        self.nf = dim + 1
+
+    # -------------------------------------------------------------- pieces
+    def stencil_of(self, i):
+        return self.col[self.row_ptr[i]:self.row_ptr[i + 1]]
+
+    def cell_matrix(self, i):
+        n = int(self.row_ptr[i + 1] - self.row_ptr[i])
+        A = np.zeros((n, self.m))
+        lib().or_cell_matrix(C.byref(self._P), int(i), _dp(A))
+        return A
+
+    def cell_weights(self, i, u):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        n = int(self.row_ptr[i + 1] - self.row_ptr[i])
+        w = np.zeros(n)
+        lib().or_cell_weights(C.byref(self._P), int(i), _dp(u), _dp(w))
+        return w
+
+    def _u(self, u):
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(self.nvars, self.nc))
+        return u
+
+    def reconstruct(self, u, cells=None):
+        """Coefficients (V, nc, m), facet values (V, nc, F, Q), ranks (V, nc), fallback (nc)."""
+        u = self._u(u)
+        coef = np.zeros((self.nvars, self.nc, self.m))
+        fval = np.zeros((self.nvars, self.nc, self.nf, self.nq))
+        rank = np.zeros((self.nvars, self.nc), dtype=np.int32)
+        fb = np.zeros(self.nc, dtype=np.uint8)
+        fbp = fb.ctypes.data_as(C.POINTER(C.c_ubyte))
+        if cells is None:
+            lib().or_reconstruct(C.byref(self._P), _dp(u), _dp(coef), _dp(fval), _ip(rank), fbp)
+        else:
+            cells = np.ascontiguousarray(cells, dtype=np.int32)
+            lib().or_reconstruct_cells(C.byref(self._P), _dp(u), len(cells), _ip(cells),
+                                       _dp(coef), _dp(fval), _ip(rank), fbp)
+        return dict(coef=coef, fval=fval, rank=rank, fallback=fb)
+
+    def rhs(self, u):
+        u = self._u(u)
+        out = np.zeros_like(u)
+        alpha = C.c_double(0.0)
+        if lib().or_rhs(C.byref(self._P), _dp(u), _dp(out), C.byref(alpha)):
+            raise MemoryError("oracle rhs allocation failed")
+        return out, alpha.value
+
+    def step(self, u, dt, nsteps):
+        u = self._u(u).copy()
+        if lib().or_rk3(C.byref(self._P), _dp(u), float(dt), int(nsteps)):
+            raise MemoryError("oracle rk3 allocation failed")
+        return u
+
+
+def from_workload(wl, **kw) -> Oracle:
+    s = dict(wl.settings)
+    args = dict(p=s["p"], n_lo=s["n_lo"], n_hi=s["n_hi"], flux=s["flux"],
+                velocity=s.get("velocity", (1.0, 0.0, 0.0)), gamma=s.get("gamma", 1.4))
+    args.update(kw)
+    return Oracle(wl.mesh.dim, wl.mesh.verts, wl.mesh.cells, wl.mesh.periodic, **args)

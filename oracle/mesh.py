@@ -1,0 +1,288 @@
+"""Oracle mesh topology, geometry, facet quadrature and k-ring stencils.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  Plain numpy / Python
+sets, written for clarity rather than speed.
+
+Paper passages followed:
+
+* facets, sibling half-facets and vertex neighbourhoods: Sec. 3.3.1 (the
+  array-based half-facet idea: two cells share a facet when their facets carry
+  the same vertex set);
+* k-ring neighbourhoods with 1/2-ring increments in 2-D and 1/3-ring
+  increments in 3-D, and the adaptive stencil size: Sec. 3.2 (the two bullet
+  lists and the paragraph after them);
+* the cell-average system is expanded about the centroid: Sec. 3.2;
+* the values used in the flux are taken at quadrature points on the facets:
+  end of Sec. 3.2 and Sec. 1, eq. (fvm).
+
+Readings where the paper is silent (each listed in the design notes):
+
+* stencil size rule: grow through the fractional ring levels until the
+  stencil has at least ``n_lo`` cells; if it has more than ``n_hi``, keep the
+  centre and the ``n_hi - 1`` cells whose centroids are nearest (squared
+  distance, ties to the lower cell id);
+* rows are ordered centre first, then by (squared centroid distance, id);
+* the squared distance is ``sum_d (c_jd - c_id)^2`` in coordinate order with
+  centroids ``(sum_v x_v) / (dim+1)`` summed in vertex order, no fused
+  multiply-add; 1-D periodic differences use the nearest image;
+* facet quadrature: 1-D the facet point; 2-D Gauss-Legendre with
+  ``ceil(p/2)`` points per edge; 3-D the 3-point degree-2 triangle rule;
+* ``h`` in the indicator is the mean edge length of the mesh (1-D: mean width).
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def _seq_sum(arrs):
+    out = arrs[0].copy()
+    for a in arrs[1:]:
+        out = out + a
+    return out
+
+
+class OracleMesh:
+    def __init__(self, dim: int, verts, cells, periodic: bool = False, p: int = 3):
+        self.dim = int(dim)
+        self.verts = np.ascontiguousarray(np.asarray(verts, dtype=np.float64).reshape(-1, dim))
+        self.cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).reshape(-1, dim + 1))
+        self.periodic = bool(periodic) and dim == 1
+        self.nc = self.cells.shape[0]
+        self.nv = self.verts.shape[0]
+        self.period = float(self.verts[-1, 0] - self.verts[0, 0]) if self.periodic else 0.0
+        self.p = int(p)
+        self._geometry()
+        self._topology()
+        self._facets()
+
+    # ------------------------------------------------------------ geometry
+    def _geometry(self):
+        d = self.dim
+        cv = self.verts[self.cells]                       # (nc, d+1, d)
+        self.cv = np.ascontiguousarray(cv)
+        if d == 1:
+            vol = cv[:, 1, 0] - cv[:, 0, 0]
+        elif d == 2:
+            e1 = cv[:, 1] - cv[:, 0]
+            e2 = cv[:, 2] - cv[:, 0]
+            vol = 0.5 * (e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
+        else:
+            e = np.stack([cv[:, k + 1] - cv[:, 0] for k in range(3)], axis=1)
+            vol = np.linalg.det(e) / 6.0
+        if np.any(~(vol > 0)):
+            bad = int(np.argmax(~(vol > 0)))
+            raise ValueError(f"cell {bad} has non-positive measure {vol[bad]}")
+        self.vol = np.ascontiguousarray(vol)
+        self.cent = np.ascontiguousarray(_seq_sum([cv[:, v] for v in range(d + 1)]) / (d + 1))
+
+    def vid(self, v):
+        """Vertex id with the periodic end node identified with node 0."""
+        if self.periodic and v == self.nv - 1:
+            return 0
+        return int(v)
+
+    def _topology(self):
+        d = self.dim
+        cells = self.cells.copy()
+        if self.periodic:
+            cells[cells == self.nv - 1] = 0
+        self.cells_id = cells
+        # vertex -> incident cells
+        v2c = [[] for _ in range(self.nv)]
+        for c in range(self.nc):
+            for v in cells[c]:
+                v2c[v].append(c)
+        self.v2c = [set(s) for s in v2c]
+        # facet neighbours: facet lf is opposite vertex lf
+        nf = d + 1
+        keys = {}
+        nbr = -np.ones((self.nc, nf), dtype=np.int64)
+        for c in range(self.nc):
+            for lf in range(nf):
+                key = tuple(sorted(int(cells[c, v]) for v in range(nf) if v != lf))
+                if key in keys:
+                    c2, lf2 = keys.pop(key)
+                    nbr[c, lf] = c2
+                    nbr[c2, lf2] = c
+                else:
+                    keys[key] = (c, lf)
+        self.nbr = nbr
+        # edge -> cells (3-D 2/3-ring)
+        if d == 3:
+            e2c = {}
+            for c in range(self.nc):
+                vs = cells[c]
+                for a in range(4):
+                    for b in range(a + 1, 4):
+                        key = (min(vs[a], vs[b]), max(vs[a], vs[b]))
+                        e2c.setdefault(key, set()).add(c)
+            self.e2c = e2c
+        # mean edge length h
+        if d == 1:
+            self.h = float(np.mean(self.vol))
+        else:
+            pairs = set()
+            for c in range(self.nc):
+                vs = cells[c]
+                for a in range(d + 1):
+                    for b in range(a + 1, d + 1):
+                        pairs.add((min(vs[a], vs[b]), max(vs[a], vs[b])))
+            pairs = np.array(sorted(pairs))
+            lens = np.linalg.norm(self.verts[pairs[:, 0]] - self.verts[pairs[:, 1]], axis=1)
+            self.h = float(np.mean(lens))
+
+    def _facets(self):
+        d = self.dim
+        nf = d + 1
+        cv = self.cv
+        if d == 1:
+            self.nq = 1
+            self.qw = np.array([1.0])
+            normal = np.zeros((self.nc, 2, 1))
+            normal[:, 0, 0] = 1.0
+            normal[:, 1, 0] = -1.0
+            area = np.ones((self.nc, 2))
+            qx = np.zeros((self.nc, 2, 1, 1))
+            qx[:, 0, 0, 0] = cv[:, 1, 0]
+            qx[:, 1, 0, 0] = cv[:, 0, 0]
+        elif d == 2:
+            nq = max(1, math.ceil(self.p / 2))
+            g, w = np.polynomial.legendre.leggauss(nq)
+            t = 0.5 * (g + 1.0)
+            self.nq = nq
+            self.qw = 0.5 * w
+            normal = np.zeros((self.nc, 3, 2))
+            area = np.zeros((self.nc, 3))
+            qx = np.zeros((self.nc, 3, nq, 2))
+            for lf in range(3):
+                a = cv[:, (lf + 1) % 3]
+                b = cv[:, (lf + 2) % 3]
+                tv = b - a
+                ln = np.sqrt(tv[:, 0] ** 2 + tv[:, 1] ** 2)
+                normal[:, lf, 0] = tv[:, 1] / ln
+                normal[:, lf, 1] = -tv[:, 0] / ln
+                area[:, lf] = ln
+                for q in range(nq):
+                    qx[:, lf, q] = a + t[q] * tv
+        else:
+            if self.p > 3:
+                raise NotImplementedError("3-D facet rule implemented for p <= 3")
+            self.nq = 3
+            self.qw = np.full(3, 1.0 / 3.0)
+            bary = np.array([[2 / 3, 1 / 6, 1 / 6], [1 / 6, 2 / 3, 1 / 6], [1 / 6, 1 / 6, 2 / 3]])
+            normal = np.zeros((self.nc, 4, 3))
+            area = np.zeros((self.nc, 4))
+            qx = np.zeros((self.nc, 4, 3, 3))
+            for lf in range(4):
+                a = cv[:, (lf + 1) % 4]
+                b = cv[:, (lf + 2) % 4]
+                c = cv[:, (lf + 3) % 4]
+                n = np.cross(b - a, c - a)
+                away = np.einsum("cd,cd->c", n, cv[:, lf] - a) > 0
+                n[away] = -n[away]
+                ln = np.linalg.norm(n, axis=1)
+                normal[:, lf] = n / ln[:, None]
+                area[:, lf] = 0.5 * ln
+                for q in range(3):
+                    qx[:, lf, q] = bary[q, 0] * a + bary[q, 1] * b + bary[q, 2] * c
+        self.normal = np.ascontiguousarray(normal)
+        self.area = np.ascontiguousarray(area)
+        self.qx = np.ascontiguousarray(qx)
+
+    # ------------------------------------------------------------- rings
+    def _facet_ring(self, i):
+        return {i} | {int(j) for j in self.nbr[i] if j >= 0}
+
+    def _vertex_ring(self, i):
+        out = set()
+        for v in self.cells_id[i]:
+            out |= self.v2c[v]
+        return out
+
+    def _edge_ring(self, i):
+        vs = self.cells_id[i]
+        out = set()
+        for a in range(4):
+            for b in range(a + 1, 4):
+                out |= self.e2c[(min(vs[a], vs[b]), max(vs[a], vs[b]))]
+        return out
+
+    def _ring(self, i, kind):
+        if kind == "facet":
+            return self._facet_ring(i)
+        if kind == "edge":
+            return self._edge_ring(i)
+        return self._vertex_ring(i)
+
+    def ring_kinds(self):
+        return {1: ["vertex"], 2: ["facet", "vertex"], 3: ["facet", "edge", "vertex"]}[self.dim]
+
+    def ring_levels(self, i, max_level: int = 6):
+        """Neighbourhoods of cell i level by level: [(level, set), ...]."""
+        kinds = self.ring_kinds()
+        frac = len(kinds)
+        out = []
+        for t, kind in enumerate(kinds):
+            out.append(((t + 1) / frac, self._ring(i, kind)))
+        cur = out[-1][1]
+        for k in range(1, max_level):
+            nxt = None
+            for t, kind in enumerate(kinds):
+                s = set(cur)
+                for j in cur:
+                    s |= self._ring(j, kind)
+                out.append((k + (t + 1) / frac, s))
+                nxt = s
+            cur = nxt
+        return out
+
+    def sqdist(self, i, j):
+        d = 0.0
+        for k in range(self.dim):
+            dx = float(self.cent[j, k]) - float(self.cent[i, k])
+            if self.periodic:
+                L = self.period
+                if dx > 0.5 * L:
+                    dx -= L
+                elif dx < -0.5 * L:
+                    dx += L
+            d = d + dx * dx
+        return d
+
+    def stencil(self, i, n_lo, n_hi):
+        kinds = self.ring_kinds()
+        frac = len(kinds)
+        S = None
+        # base levels
+        for kind in kinds:
+            S = self._ring(i, kind)
+            if len(S) >= n_lo:
+                break
+        else:
+            cur = S
+            while True:
+                grown = None
+                for kind in kinds:
+                    s = set(cur)
+                    for j in cur:
+                        s |= self._ring(j, kind)
+                    grown = s
+                    if len(s) >= n_lo:
+                        break
+                S = grown
+                if len(S) >= n_lo or len(S) == len(cur):
+                    break
+                cur = S
+        others = sorted((self.sqdist(i, j), j) for j in S if j != i)
+        others = others[: max(0, n_hi - 1)]
+        return [i] + [j for _, j in others]
+
+    def stencils(self, n_lo, n_hi):
+        rows = [self.stencil(i, n_lo, n_hi) for i in range(self.nc)]
+        row_ptr = np.zeros(self.nc + 1, dtype=np.int32)
+        row_ptr[1:] = np.cumsum([len(r) for r in rows])
+        col = np.fromiter((j for r in rows for j in r), dtype=np.int32, count=int(row_ptr[-1]))
+        return row_ptr, col
