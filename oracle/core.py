@@ -16,28 +16,35 @@ from .mesh import OracleMesh
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wlseno_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_LD = os.path.join(_HERE, "liboracle_ld.so")
 
 FLUX = {"advection": 0, "burgers": 1, "euler": 2}
 
 
-def build(force: bool = False) -> str:
-    """Compile the C core with gcc (-O2 -ffp-contract=off, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-               "-o", tmp, _SRC, "-lm"]
+def build(force: bool = False, extended: bool = False) -> str:
+    """Compile the C core with gcc (-O2 -ffp-contract=off, OpenMP).  The
+    extended build runs the same algorithm in x87 long double; it is used only
+    to measure the FP64 rounding floor of individual cells."""
+    out = _LIB_LD if extended else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99"]
+        if extended:
+            cmd.append("-DOR_REAL=long double")
+        cmd += ["-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
+def lib(extended: bool = False):
+    _lib = _libs.get(extended)
     if _lib is None:
-        _lib = C.CDLL(build())
+        _lib = C.CDLL(build(extended=extended))
+        _libs[extended] = _lib
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int)
         _lib.or_num_coeffs.argtypes = [C.c_int, C.c_int]
@@ -54,7 +61,12 @@ def lib():
         _lib.or_reconstruct_cells.argtypes = [pp, dp, C.c_int, ip, dp, dp, ip, C.POINTER(C.c_ubyte)]
         _lib.or_rhs.argtypes = [pp, dp, dp, dp]
         _lib.or_rk3.argtypes = [pp, dp, C.c_double, C.c_int]
+        _lib.or_num_threads.argtypes = []
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
 
 
 class _Problem(C.Structure):
@@ -131,7 +143,8 @@ class Oracle:
 
     def __init__(self, dim, verts, cells, periodic=False, *, p=3, n_lo=None, n_hi=None,
                  flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2, alpha_w=1.5,
-                 rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None):
+                 rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None, extended=False):
+        self.extended = bool(extended)
         self.mesh = OracleMesh(dim, verts, cells, periodic, p=p)
         om = self.mesh
         self.dim, self.p, self.nc = om.dim, int(p), om.nc
@@ -175,6 +188,7 @@ class Oracle:
         P.qx, P.qw = _dp(k["qx"]), _dp(k["qw"])
         P.normal, P.area = _dp(k["normal"]), _dp(k["area"])
         self._P = P
+        self._lib = lib(self.extended)
         self.flux = flux
         self.nq = om.nq
         self.nf = dim + 1
@@ -186,14 +200,14 @@ class Oracle:
     def cell_matrix(self, i):
         n = int(self.row_ptr[i + 1] - self.row_ptr[i])
         A = np.zeros((n, self.m))
-        lib().or_cell_matrix(C.byref(self._P), int(i), _dp(A))
+        self._lib.or_cell_matrix(C.byref(self._P), int(i), _dp(A))
         return A
 
     def cell_weights(self, i, u):
         u = np.ascontiguousarray(u, dtype=np.float64)
         n = int(self.row_ptr[i + 1] - self.row_ptr[i])
         w = np.zeros(n)
-        lib().or_cell_weights(C.byref(self._P), int(i), _dp(u), _dp(w))
+        self._lib.or_cell_weights(C.byref(self._P), int(i), _dp(u), _dp(w))
         return w
 
     def _u(self, u):
@@ -209,10 +223,10 @@ class Oracle:
         fb = np.zeros(self.nc, dtype=np.uint8)
         fbp = fb.ctypes.data_as(C.POINTER(C.c_ubyte))
         if cells is None:
-            lib().or_reconstruct(C.byref(self._P), _dp(u), _dp(coef), _dp(fval), _ip(rank), fbp)
+            self._lib.or_reconstruct(C.byref(self._P), _dp(u), _dp(coef), _dp(fval), _ip(rank), fbp)
         else:
             cells = np.ascontiguousarray(cells, dtype=np.int32)
-            lib().or_reconstruct_cells(C.byref(self._P), _dp(u), len(cells), _ip(cells),
+            self._lib.or_reconstruct_cells(C.byref(self._P), _dp(u), len(cells), _ip(cells),
                                        _dp(coef), _dp(fval), _ip(rank), fbp)
         return dict(coef=coef, fval=fval, rank=rank, fallback=fb)
 
@@ -220,13 +234,13 @@ class Oracle:
         u = self._u(u)
         out = np.zeros_like(u)
         alpha = C.c_double(0.0)
-        if lib().or_rhs(C.byref(self._P), _dp(u), _dp(out), C.byref(alpha)):
+        if self._lib.or_rhs(C.byref(self._P), _dp(u), _dp(out), C.byref(alpha)):
             raise MemoryError("oracle rhs allocation failed")
         return out, alpha.value
 
     def step(self, u, dt, nsteps):
         u = self._u(u).copy()
-        if lib().or_rk3(C.byref(self._P), _dp(u), float(dt), int(nsteps)):
+        if self._lib.or_rk3(C.byref(self._P), _dp(u), float(dt), int(nsteps)):
             raise MemoryError("oracle rk3 allocation failed")
         return u
 

@@ -22,10 +22,17 @@
  *   - third-order TVD Runge-Kutta: Sec. 4.2.1, eq. (3rd-order-Runge-Kutta).
  *
  * Compiled with -O2 -ffp-contract=off; per-cell loops may run under OpenMP.
+ * The arithmetic type `real` is double; building with -DOR_REAL='long double'
+ * gives the same algorithm in x87 extended precision, used only to measure
+ * the FP64 rounding floor of individual cells.  Arrays crossing the API are
+ * double in both builds.
  */
-#include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <tgmath.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_MAXDIM 3
 #define OR_MAXM 35
@@ -33,6 +40,12 @@
 #define OR_MAXV 5
 #define OR_MAXF 4
 #define OR_MAXQ 8
+#define OR_PIVOT_TIE 1e-10
+
+#ifndef OR_REAL
+#define OR_REAL double
+#endif
+typedef OR_REAL real;
 
 enum { OR_ADVECTION = 0, OR_BURGERS = 1, OR_EULER = 2 };
 
@@ -54,12 +67,22 @@ typedef struct {
     const double *area;   /* nc x (dim+1) facet measures */
 } or_problem;
 
+/* Threads the per-cell loops use (1 without OpenMP). */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------ basis */
 
-static double factorial(int k)
+static real factorial(int k)
 {
-    double f = 1.0;
-    for (int i = 2; i <= k; ++i) f *= (double)i;
+    real f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= (real)i;
     return f;
 }
 
@@ -97,10 +120,10 @@ int or_basis(int dim, int p, int *exps)
 }
 
 /* Nearest periodic image of a 1-D difference. */
-static double wrap(const or_problem *P, double d)
+static real wrap(const or_problem *P, real d)
 {
     if (P->periodic) {
-        double L = P->period;
+        real L = P->period;
         if (d > 0.5 * L) d -= L;
         else if (d < -0.5 * L) d += L;
     }
@@ -115,7 +138,7 @@ static double wrap(const or_problem *P, double d)
  *   prod_t l_t(x) = sum over maps s:{1..q}->{0..dim} of prod_t lambda_{s(t)} l_t(V_{s(t)}),
  * and the simplex integral of lambda^alpha is |T| dim! alpha! / (dim+|alpha|)!.
  * The sum runs over all (dim+1)^q maps. */
-double or_simplex_avg_monomial(int dim, const double *verts, const double *c, const int *a)
+static real simplex_avg(int dim, const real *verts, const real *c, const int *a)
 {
     int q = 0, fac_dim[8];
     for (int d = 0; d < dim; ++d)
@@ -124,25 +147,33 @@ double or_simplex_avg_monomial(int dim, const double *verts, const double *c, co
     int nv = dim + 1;
     long total = 1;
     for (int t = 0; t < q; ++t) total *= nv;
-    double sum = 0.0;
+    real sum = 0.0;
     int s[8];
     for (long code = 0; code < total; ++code) {
         long rem = code;
         for (int t = 0; t < q; ++t) { s[t] = (int)(rem % nv); rem /= nv; }
         int mult[4] = {0, 0, 0, 0};
-        double prod = 1.0;
+        real prod = 1.0;
         for (int t = 0; t < q; ++t) {
             mult[s[t]] += 1;
             prod *= verts[s[t] * dim + fac_dim[t]] - c[fac_dim[t]];
         }
-        double mf = 1.0;
+        real mf = 1.0;
         for (int v = 0; v < nv; ++v) mf *= factorial(mult[v]);
         sum += mf * prod;
     }
-    double avg = sum * factorial(dim) / factorial(dim + q);
-    double af = 1.0;
+    real avg = sum * factorial(dim) / factorial(dim + q);
+    real af = 1.0;
     for (int d = 0; d < dim; ++d) af *= factorial(a[d]);
     return avg / af;
+}
+
+double or_simplex_avg_monomial(int dim, const double *verts, const double *c, const int *a)
+{
+    real vr[(OR_MAXDIM + 1) * OR_MAXDIM], cr[OR_MAXDIM];
+    for (int t = 0; t < (dim + 1) * dim; ++t) vr[t] = verts[t];
+    for (int d = 0; d < dim; ++d) cr[d] = c[d];
+    return (double)simplex_avg(dim, vr, cr, a);
 }
 
 /* ---------------------------------------------------- per-cell pieces */
@@ -150,35 +181,41 @@ double or_simplex_avg_monomial(int dim, const double *verts, const double *c, co
 static int stencil_size(const or_problem *P, int i) { return P->row_ptr[i + 1] - P->row_ptr[i]; }
 
 /* Vertices of cell j shifted to the periodic image nearest cell i (1-D). */
-static void image_vertices(const or_problem *P, int i, int j, double *out)
+static void image_vertices(const or_problem *P, int i, int j, real *out)
 {
     int nv = P->dim + 1;
-    double shift = 0.0;
+    real shift = 0.0;
     if (P->periodic) {
-        double d = P->cent[j] - P->cent[i];
+        real d = (real)P->cent[j] - (real)P->cent[i];
         shift = wrap(P, d) - d;
     }
     for (int v = 0; v < nv; ++v)
         for (int d = 0; d < P->dim; ++d)
-            out[v * P->dim + d] = P->cv[((size_t)j * nv + v) * P->dim + d] + (d == 0 ? shift : 0.0);
+            out[v * P->dim + d] = (real)P->cv[((size_t)j * nv + v) * P->dim + d] + (d == 0 ? shift : 0.0);
 }
 
 /* A (n x m): averages over each stencil cell of the Taylor monomials about x_i. */
-void or_cell_matrix(const or_problem *P, int i, double *A)
+static void cell_matrix(const or_problem *P, int i, real *A)
 {
     int n = stencil_size(P, i), m = P->m;
     const int *rows = P->col + P->row_ptr[i];
-    double verts[(OR_MAXDIM + 1) * OR_MAXDIM];
-    const double *ci = P->cent + (size_t)i * P->dim;
+    real verts[(OR_MAXDIM + 1) * OR_MAXDIM], ci[OR_MAXDIM];
+    for (int d = 0; d < P->dim; ++d) ci[d] = P->cent[(size_t)i * P->dim + d];
     for (int r = 0; r < n; ++r) {
         image_vertices(P, i, rows[r], verts);
-        for (int k = 0; k < m; ++k)
-            A[r * m + k] = or_simplex_avg_monomial(P->dim, verts, ci, P->exps + 3 * k);
+        for (int k = 0; k < m; ++k) A[r * m + k] = simplex_avg(P->dim, verts, ci, P->exps + 3 * k);
     }
 }
 
+void or_cell_matrix(const or_problem *P, int i, double *A)
+{
+    real Ar[OR_MAXN * OR_MAXM];
+    cell_matrix(P, i, Ar);
+    for (int t = 0; t < stencil_size(P, i) * P->m; ++t) A[t] = (double)Ar[t];
+}
+
 /* Row weights omega for cell i from one scalar field u (length nc). */
-void or_cell_weights(const or_problem *P, int i, const double *u, double *w)
+static void cell_weights(const or_problem *P, int i, const real *u, real *w)
 {
     int n = stencil_size(P, i);
     const int *rows = P->col + P->row_ptr[i];
@@ -186,85 +223,107 @@ void or_cell_weights(const or_problem *P, int i, const double *u, double *w)
         for (int r = 0; r < n; ++r) w[r] = 1.0;
         return;
     }
-    double eh2 = P->eps * P->h * P->h;
-    double ui = u[i];
+    real h = P->h;
+    real eh2 = (real)P->eps * h * h;
+    real ui = u[i];
     /* beta of the centre: the smallest indicator among its facet neighbours */
-    double beta_i = -1.0;
+    real beta_i = -1.0;
     for (int lf = 0; lf <= P->dim; ++lf) {
         int j = P->nbr[(size_t)i * (P->dim + 1) + lf];
         if (j < 0) continue;
-        double b = (u[j] - ui) * (u[j] - ui) + eh2;
+        real b = (u[j] - ui) * (u[j] - ui) + eh2;
         if (beta_i < 0.0 || b < beta_i) beta_i = b;
     }
     if (beta_i < 0.0) beta_i = eh2;
     for (int r = 0; r < n; ++r) {
         int j = rows[r];
         if (j == i) {
-            w[r] = P->alpha_w / beta_i;
+            w[r] = (real)P->alpha_w / beta_i;
         } else {
-            double b = (u[j] - ui) * (u[j] - ui) + eh2;
+            real b = (u[j] - ui) * (u[j] - ui) + eh2;
             w[r] = 1.0 / b;
         }
     }
+}
+
+void or_cell_weights(const or_problem *P, int i, const double *u, double *w)
+{
+    /* only the stencil's and the facet neighbours' entries of u are read */
+    real *ur = (real *)calloc((size_t)P->nc, sizeof(real));
+    real wr[OR_MAXN];
+    const int *rows = P->col + P->row_ptr[i];
+    for (int r = 0; r < stencil_size(P, i); ++r) ur[rows[r]] = u[rows[r]];
+    for (int lf = 0; lf <= P->dim; ++lf) {
+        int j = P->nbr[(size_t)i * (P->dim + 1) + lf];
+        if (j >= 0) ur[j] = u[j];
+    }
+    cell_weights(P, i, ur, wr);
+    for (int r = 0; r < stencil_size(P, i); ++r) w[r] = (double)wr[r];
+    free(ur);
 }
 
 /* Solve min || W A S d - W b ||_2 with Householder QR and column pivoting,
  * truncating to the numerical rank r = #{k : |R_kk| > tol |R_11|}; returns r
  * and v = S E [R_{1:r,1:r}^{-1} (Q^T W b)_{1:r}; 0]. rdiag (length min(n,m))
  * receives the diagonal of R, perm the column order E. */
-int or_wls_qrcp_solve(int n, int m, const double *A, const double *w, const double *b,
-                      double tol, double *v, double *rdiag, int *perm_out)
+static int qrcp_solve(int n, int m, const real *A, const real *w, const real *b, real tol, real *v,
+                      real *rdiag, int *perm_out)
 {
-    double M[OR_MAXN][OR_MAXM], rhs[OR_MAXN], s[OR_MAXM], y[OR_MAXM];
+    real M[OR_MAXN][OR_MAXM], rhs[OR_MAXN], s[OR_MAXM], y[OR_MAXM];
     int perm[OR_MAXM];
     for (int r = 0; r < n; ++r) {
         for (int k = 0; k < m; ++k) M[r][k] = w[r] * A[r * m + k];
         rhs[r] = w[r] * b[r];
     }
     for (int k = 0; k < m; ++k) {
-        double ss = 0.0;
+        real ss = 0.0;
         for (int r = 0; r < n; ++r) ss += M[r][k] * M[r][k];
-        double nrm = sqrt(ss);
+        real nrm = sqrt(ss);
         s[k] = nrm > 0.0 ? 1.0 / nrm : 0.0;
         for (int r = 0; r < n; ++r) M[r][k] *= s[k];
         perm[k] = k;
     }
     int kmax = n < m ? n : m;
     for (int k = 0; k < kmax; ++k) {
-        /* pivot: largest exactly recomputed partial column norm, first on ties */
-        int best = k;
-        double bn = -1.0;
+        /* pivot: the largest exactly recomputed partial column norm; columns
+         * within a relative OR_PIVOT_TIE of the largest count as tied and the
+         * lowest index wins (after column scaling every norm is 1 at the first
+         * step, and rounding must not decide the order) */
+        real eta[OR_MAXM], bn = 0.0;
         for (int c = k; c < m; ++c) {
-            double eta = 0.0;
-            for (int r = k; r < n; ++r) eta += M[r][c] * M[r][c];
-            if (eta > bn) { bn = eta; best = c; }
+            eta[c] = 0.0;
+            for (int r = k; r < n; ++r) eta[c] += M[r][c] * M[r][c];
+            if (eta[c] > bn) bn = eta[c];
         }
+        int best = k;
+        for (int c = m - 1; c >= k; --c)
+            if (eta[c] >= bn * (1.0 - OR_PIVOT_TIE)) best = c;
         if (best != k) {
-            for (int r = 0; r < n; ++r) { double t = M[r][k]; M[r][k] = M[r][best]; M[r][best] = t; }
+            for (int r = 0; r < n; ++r) { real t = M[r][k]; M[r][k] = M[r][best]; M[r][best] = t; }
             int t = perm[k]; perm[k] = perm[best]; perm[best] = t;
         }
         /* Householder reflector H = I - tau v v^T with v_k = 1 (LAPACK convention) */
-        double alpha = M[k][k], xn2 = 0.0;
+        real alpha = M[k][k], xn2 = 0.0;
         for (int r = k + 1; r < n; ++r) xn2 += M[r][k] * M[r][k];
-        double tau, beta;
+        real tau, beta;
         if (xn2 == 0.0) {
             tau = 0.0;
             beta = alpha;
         } else {
             beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
             tau = (beta - alpha) / beta;
-            double scal = 1.0 / (alpha - beta);
+            real scal = 1.0 / (alpha - beta);
             for (int r = k + 1; r < n; ++r) M[r][k] *= scal;
         }
         M[k][k] = beta;
         if (tau != 0.0) {
             for (int c = k + 1; c < m; ++c) {
-                double ws = M[k][c];
+                real ws = M[k][c];
                 for (int r = k + 1; r < n; ++r) ws += M[r][k] * M[r][c];
                 M[k][c] -= tau * ws;
                 for (int r = k + 1; r < n; ++r) M[r][c] -= tau * M[r][k] * ws;
             }
-            double ws = rhs[k];
+            real ws = rhs[k];
             for (int r = k + 1; r < n; ++r) ws += M[r][k] * rhs[r];
             rhs[k] -= tau * ws;
             for (int r = k + 1; r < n; ++r) rhs[r] -= tau * M[r][k] * ws;
@@ -274,10 +333,10 @@ int or_wls_qrcp_solve(int n, int m, const double *A, const double *w, const doub
         if (rdiag) rdiag[k] = M[k][k];
     }
     int rank = 0;
-    double r11 = kmax > 0 ? fabs(M[0][0]) : 0.0;
+    real r11 = kmax > 0 ? fabs(M[0][0]) : 0.0;
     while (rank < kmax && fabs(M[rank][rank]) > tol * r11) ++rank;
     for (int k = rank - 1; k >= 0; --k) {
-        double acc = rhs[k];
+        real acc = rhs[k];
         for (int c = k + 1; c < rank; ++c) acc -= M[k][c] * y[c];
         y[k] = acc / M[k][k];
     }
@@ -288,45 +347,66 @@ int or_wls_qrcp_solve(int n, int m, const double *A, const double *w, const doub
     return rank;
 }
 
-/* sum_k v_k prod_d dx_d^{a_kd} / a_kd! */
-double or_eval_taylor(int dim, int m, const int *exps, const double *v, const double *dx)
+int or_wls_qrcp_solve(int n, int m, const double *A, const double *w, const double *b, double tol,
+                      double *v, double *rdiag, int *perm_out)
 {
-    double acc = 0.0;
+    real Ar[OR_MAXN * OR_MAXM], wr[OR_MAXN], br[OR_MAXN], vr[OR_MAXM], rd[OR_MAXM];
+    for (int t = 0; t < n * m; ++t) Ar[t] = A[t];
+    for (int r = 0; r < n; ++r) { wr[r] = w[r]; br[r] = b[r]; }
+    int rank = qrcp_solve(n, m, Ar, wr, br, tol, vr, rd, perm_out);
+    for (int k = 0; k < m; ++k) v[k] = (double)vr[k];
+    if (rdiag)
+        for (int k = 0; k < (n < m ? n : m); ++k) rdiag[k] = (double)rd[k];
+    return rank;
+}
+
+/* sum_k v_k prod_d dx_d^{a_kd} / a_kd! */
+static real eval_taylor(int dim, int m, const int *exps, const real *v, const real *dx)
+{
+    real acc = 0.0;
     for (int k = 0; k < m; ++k) {
-        double term = v[k];
+        real term = v[k];
         for (int d = 0; d < dim; ++d) {
             int a = exps[3 * k + d];
-            term *= pow(dx[d], (double)a) / factorial(a);
+            term *= pow(dx[d], (real)a) / factorial(a);
         }
         acc += term;
     }
     return acc;
 }
 
+double or_eval_taylor(int dim, int m, const int *exps, const double *v, const double *dx)
+{
+    real vr[OR_MAXM], xr[OR_MAXDIM];
+    for (int k = 0; k < m; ++k) vr[k] = v[k];
+    for (int d = 0; d < dim; ++d) xr[d] = dx[d];
+    return (double)eval_taylor(dim, m, exps, vr, xr);
+}
+
 /* ------------------------------------------------------------- physics */
 
-static double euler_pressure(const or_problem *P, const double *U)
+static real euler_pressure(const or_problem *P, const real *U)
 {
-    double rho = U[0], ke = 0.0;
+    real rho = U[0], ke = 0.0;
     for (int d = 0; d < P->dim; ++d) ke += U[1 + d] * U[1 + d];
     ke = 0.5 * ke / rho;
-    return (P->gamma - 1.0) * (U[P->dim + 1] - ke);
+    return ((real)P->gamma - 1.0) * (U[P->dim + 1] - ke);
 }
 
 /* physical normal flux F(U).n for every component */
-static void normal_flux(const or_problem *P, const double *U, const double *n, double *F)
+static void normal_flux(const or_problem *P, const real *U, const real *n, real *F)
 {
     if (P->flux == OR_ADVECTION) {
-        double an = 0.0;
-        for (int d = 0; d < P->dim; ++d) an += P->adv[d] * n[d];
+        real an = 0.0;
+        for (int d = 0; d < P->dim; ++d) an += (real)P->adv[d] * n[d];
         F[0] = an * U[0];
     } else if (P->flux == OR_BURGERS) {
-        double sn = 0.0;
+        real sn = 0.0;
         for (int d = 0; d < P->dim; ++d) sn += n[d];
         F[0] = 0.5 * U[0] * U[0] * sn;
     } else {
         int D = P->dim;
-        double rho = U[0], pr = euler_pressure(P, U), vn = 0.0;
+        real rho = U[0], pr = euler_pressure(P, U), vn = 0.0;
         for (int d = 0; d < D; ++d) vn += U[1 + d] / rho * n[d];
         F[0] = rho * vn;
         for (int d = 0; d < D; ++d) F[1 + d] = U[1 + d] * vn + pr * n[d];
@@ -335,20 +415,20 @@ static void normal_flux(const or_problem *P, const double *U, const double *n, d
 }
 
 /* normal spectral radius at a state (used for the Lax-Friedrichs alpha) */
-static double spectral_radius(const or_problem *P, const double *U, const double *n)
+static real spectral_radius(const or_problem *P, const real *U, const real *n)
 {
     if (P->flux == OR_ADVECTION) {
-        double an = 0.0;
-        for (int d = 0; d < P->dim; ++d) an += P->adv[d] * n[d];
+        real an = 0.0;
+        for (int d = 0; d < P->dim; ++d) an += (real)P->adv[d] * n[d];
         return fabs(an);
     } else if (P->flux == OR_BURGERS) {
-        double sn = 0.0;
+        real sn = 0.0;
         for (int d = 0; d < P->dim; ++d) sn += n[d];
         return fabs(U[0] * sn);
     } else {
-        double rho = U[0], pr = euler_pressure(P, U), vn = 0.0;
+        real rho = U[0], pr = euler_pressure(P, U), vn = 0.0;
         for (int d = 0; d < P->dim; ++d) vn += U[1 + d] / rho * n[d];
-        return fabs(vn) + sqrt(P->gamma * pr / rho);
+        return fabs(vn) + sqrt((real)P->gamma * pr / rho);
     }
 }
 
@@ -362,44 +442,48 @@ static size_t fval_index(const or_problem *P, int var, int i, int lf, int q)
     return (((size_t)var * P->nc + i) * F + lf) * P->nq + q;
 }
 
+static void load_normal(const or_problem *P, int i, int lf, real *n)
+{
+    for (int d = 0; d < P->dim; ++d) n[d] = P->normal[((size_t)i * faces_per_cell(P) + lf) * P->dim + d];
+}
+
 /* Reconstruct one cell for every variable: coefficients, own facet values. */
-static void reconstruct_cell(const or_problem *P, int i, const double *u, double *coef,
-                             double *fval, int *rank, unsigned char *fallback)
+static void reconstruct_cell(const or_problem *P, int i, const real *u, real *coef, real *fval,
+                             int *rank, unsigned char *fallback)
 {
     int n = stencil_size(P, i), m = P->m, V = P->nvars, F = faces_per_cell(P), D = P->dim;
     const int *rows = P->col + P->row_ptr[i];
-    double A[OR_MAXN * OR_MAXM], w[OR_MAXN], b[OR_MAXN];
-    double v[OR_MAXV][OR_MAXM];
-    or_cell_matrix(P, i, A);
+    real A[OR_MAXN * OR_MAXM], w[OR_MAXN], b[OR_MAXN];
+    real v[OR_MAXV][OR_MAXM];
+    cell_matrix(P, i, A);
     for (int var = 0; var < V; ++var) {
-        const double *uv = u + (size_t)var * P->nc;
-        or_cell_weights(P, i, uv, w);
+        const real *uv = u + (size_t)var * P->nc;
+        cell_weights(P, i, uv, w);
         for (int r = 0; r < n; ++r) b[r] = uv[rows[r]];
-        int rk = or_wls_qrcp_solve(n, m, A, w, b, P->rank_tol, v[var], NULL, NULL);
+        int rk = qrcp_solve(n, m, A, w, b, P->rank_tol, v[var], NULL, NULL);
         if (rank) rank[(size_t)var * P->nc + i] = rk;
     }
     /* facet values of the reconstruction */
-    double vals[OR_MAXV][OR_MAXF][OR_MAXQ];
+    real vals[OR_MAXV][OR_MAXF][OR_MAXQ];
     for (int lf = 0; lf < F; ++lf)
         for (int q = 0; q < P->nq; ++q) {
             const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
-            double dx[OR_MAXDIM];
-            for (int d = 0; d < D; ++d) dx[d] = x[d] - P->cent[(size_t)i * D + d];
-            for (int var = 0; var < V; ++var)
-                vals[var][lf][q] = or_eval_taylor(D, m, P->exps, v[var], dx);
+            real dx[OR_MAXDIM];
+            for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)i * D + d];
+            for (int var = 0; var < V; ++var) vals[var][lf][q] = eval_taylor(D, m, P->exps, v[var], dx);
         }
     /* Euler: keep the cell averages if any facet state is not physical */
     int fb = 0;
     if (P->flux == OR_EULER) {
         for (int lf = 0; lf < F && !fb; ++lf)
             for (int q = 0; q < P->nq && !fb; ++q) {
-                double U[OR_MAXV];
+                real U[OR_MAXV];
                 for (int var = 0; var < V; ++var) U[var] = vals[var][lf][q];
                 if (!(U[0] > 0.0) || !(euler_pressure(P, U) > 0.0)) fb = 1;
             }
         if (fb) {
             for (int var = 0; var < V; ++var) {
-                double ub = u[(size_t)var * P->nc + i];
+                real ub = u[(size_t)var * P->nc + i];
                 for (int k = 0; k < m; ++k) v[var][k] = 0.0;
                 v[var][0] = ub;
                 for (int lf = 0; lf < F; ++lf)
@@ -417,29 +501,56 @@ static void reconstruct_cell(const or_problem *P, int i, const double *u, double
     }
 }
 
-/* u: nvars x nc.  coef: nvars x nc x m.  fval: nvars x nc x (dim+1) x nq. */
+static real *to_real(const double *x, size_t n)
+{
+    real *r = (real *)malloc((n ? n : 1) * sizeof(real));
+    if (r)
+        for (size_t t = 0; t < n; ++t) r[t] = x[t];
+    return r;
+}
+
+static void to_double(const real *x, double *out, size_t n)
+{
+    for (size_t t = 0; t < n; ++t) out[t] = (double)x[t];
+}
+
+/* Reconstruct the listed cells (all cells when cells == NULL); outputs are
+ * indexed by cell id.  u: nvars x nc.  coef: nvars x nc x m.  fval: nvars x nc
+ * x (dim+1) x nq. */
+static int reconstruct_api(const or_problem *P, const double *u, int ncells, const int *cells, double *coef,
+                           double *fval, int *rank, unsigned char *fallback)
+{
+    size_t nu = (size_t)P->nvars * P->nc;
+    size_t ncoef = nu * P->m, nfv = nu * faces_per_cell(P) * P->nq;
+    real *ur = to_real(u, nu);
+    real *cr = (real *)calloc(ncoef ? ncoef : 1, sizeof(real));
+    real *fr = (real *)calloc(nfv ? nfv : 1, sizeof(real));
+    if (!ur || !cr || !fr) { free(ur); free(cr); free(fr); return -1; }
+    int count = cells ? ncells : P->nc;
+#pragma omp parallel for schedule(static)
+    for (int t = 0; t < count; ++t) reconstruct_cell(P, cells ? cells[t] : t, ur, cr, fr, rank, fallback);
+    if (coef) to_double(cr, coef, ncoef);
+    if (fval) to_double(fr, fval, nfv);
+    free(ur); free(cr); free(fr);
+    return 0;
+}
+
 int or_reconstruct(const or_problem *P, const double *u, double *coef, double *fval, int *rank,
                    unsigned char *fallback)
 {
-#pragma omp parallel for schedule(static)
-    for (int i = 0; i < P->nc; ++i) reconstruct_cell(P, i, u, coef, fval, rank, fallback);
-    return 0;
+    return reconstruct_api(P, u, 0, NULL, coef, fval, rank, fallback);
 }
 
-/* Reconstruct only the listed cells (outputs are indexed by cell id as above). */
 int or_reconstruct_cells(const or_problem *P, const double *u, int ncells, const int *cells,
                          double *coef, double *fval, int *rank, unsigned char *fallback)
 {
-#pragma omp parallel for schedule(static)
-    for (int t = 0; t < ncells; ++t) reconstruct_cell(P, cells[t], u, coef, fval, rank, fallback);
-    return 0;
+    return reconstruct_api(P, u, ncells, cells, coef, fval, rank, fallback);
 }
 
 /* Lax-Friedrichs numerical flux for all components. */
-static void lf_flux(const or_problem *P, const double *um, const double *up, const double *n,
-                    double alpha, double *out)
+static void lf_flux(const or_problem *P, const real *um, const real *up, const real *n, real alpha, real *out)
 {
-    double Fm[OR_MAXV], Fp[OR_MAXV];
+    real Fm[OR_MAXV], Fp[OR_MAXV];
     normal_flux(P, um, n, Fm);
     normal_flux(P, up, n, Fp);
     for (int var = 0; var < P->nvars; ++var)
@@ -448,74 +559,75 @@ static void lf_flux(const or_problem *P, const double *um, const double *up, con
 
 /* Global Lax-Friedrichs alpha: the largest normal spectral radius over every
  * cell's own facet-point states (the outside states are other cells' own). */
-static double global_alpha(const or_problem *P, const double *fval)
+static real global_alpha(const or_problem *P, const real *fval)
 {
-    int F = faces_per_cell(P), V = P->nvars, D = P->dim;
-    double amax = 0.0;
+    int F = faces_per_cell(P), V = P->nvars;
+    real amax = 0.0;
     for (int i = 0; i < P->nc; ++i)
         for (int lf = 0; lf < F; ++lf)
             for (int q = 0; q < P->nq; ++q) {
-                double U[OR_MAXV];
+                real U[OR_MAXV], n[OR_MAXDIM];
                 for (int var = 0; var < V; ++var) U[var] = fval[fval_index(P, var, i, lf, q)];
-                double a = spectral_radius(P, U, P->normal + ((size_t)i * F + lf) * D);
+                load_normal(P, i, lf, n);
+                real a = spectral_radius(P, U, n);
                 if (a > amax) amax = a;
             }
     return amax;
 }
 
-/* dudt_i = -(1/|tau_i|) sum_facets |f| sum_q w_q Fhat(u-, u+, n) for the listed
- * cells, given every cell's coefficients and own facet values. */
-static void divergence_cell(const or_problem *P, int i, const double *u, const double *coef,
-                            const double *fval, const unsigned char *fallback, double alpha,
-                            double *dudt)
+/* dudt_i = -(1/|tau_i|) sum_facets |f| sum_q w_q Fhat(u-, u+, n), given every
+ * cell's coefficients and own facet values. */
+static void divergence_cell(const or_problem *P, int i, const real *u, const real *coef, const real *fval,
+                            const unsigned char *fallback, real alpha, real *dudt)
 {
     int F = faces_per_cell(P), V = P->nvars, D = P->dim, m = P->m;
-    double tot[OR_MAXV];
+    real tot[OR_MAXV];
     for (int var = 0; var < V; ++var) tot[var] = 0.0;
     for (int lf = 0; lf < F; ++lf) {
         int j = P->nbr[(size_t)i * F + lf];
-        const double *n = P->normal + ((size_t)i * F + lf) * D;
-        double facc[OR_MAXV];
+        real n[OR_MAXDIM];
+        load_normal(P, i, lf, n);
+        real facc[OR_MAXV];
         for (int var = 0; var < V; ++var) facc[var] = 0.0;
         for (int q = 0; q < P->nq; ++q) {
-            double um[OR_MAXV], up[OR_MAXV], fh[OR_MAXV];
+            real um[OR_MAXV], up[OR_MAXV], fh[OR_MAXV];
             for (int var = 0; var < V; ++var) um[var] = fval[fval_index(P, var, i, lf, q)];
             if (j < 0) {
                 for (int var = 0; var < V; ++var) up[var] = um[var];   /* transmissive */
             } else {
                 const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
-                double dx[OR_MAXDIM];
-                for (int d = 0; d < D; ++d) dx[d] = x[d] - P->cent[(size_t)j * D + d];
+                real dx[OR_MAXDIM];
+                for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)j * D + d];
                 dx[0] = wrap(P, dx[0]);
                 for (int var = 0; var < V; ++var) {
                     if (fallback && fallback[j])
                         up[var] = u[(size_t)var * P->nc + j];
                     else
-                        up[var] = or_eval_taylor(D, m, P->exps, coef + ((size_t)var * P->nc + j) * m, dx);
+                        up[var] = eval_taylor(D, m, P->exps, coef + ((size_t)var * P->nc + j) * m, dx);
                 }
             }
-            double a = alpha;
+            real a = alpha;
             if (P->flux == OR_ADVECTION) a = spectral_radius(P, um, n);
             lf_flux(P, um, up, n, a, fh);
-            for (int var = 0; var < V; ++var) facc[var] += P->qw[q] * fh[var];
+            for (int var = 0; var < V; ++var) facc[var] += (real)P->qw[q] * fh[var];
         }
-        for (int var = 0; var < V; ++var) tot[var] += P->area[(size_t)i * F + lf] * facc[var];
+        for (int var = 0; var < V; ++var) tot[var] += (real)P->area[(size_t)i * F + lf] * facc[var];
     }
-    for (int var = 0; var < V; ++var) dudt[(size_t)var * P->nc + i] = -tot[var] / P->vol[i];
+    for (int var = 0; var < V; ++var) dudt[(size_t)var * P->nc + i] = -tot[var] / (real)P->vol[i];
 }
 
-/* Full right-hand side L(u).  alpha_out (nullable) receives the LF alpha used
- * (0 for linear advection, where alpha is per facet). */
-int or_rhs(const or_problem *P, const double *u, double *dudt, double *alpha_out)
+/* Full right-hand side L(u) in working precision. */
+static int rhs_real(const or_problem *P, const real *u, real *dudt, real *alpha_out)
 {
     size_t ncoef = (size_t)P->nvars * P->nc * P->m;
     size_t nfv = (size_t)P->nvars * P->nc * faces_per_cell(P) * P->nq;
-    double *coef = (double *)malloc(ncoef * sizeof(double));
-    double *fval = (double *)malloc(nfv * sizeof(double));
+    real *coef = (real *)malloc(ncoef * sizeof(real));
+    real *fval = (real *)malloc(nfv * sizeof(real));
     unsigned char *fb = (unsigned char *)calloc((size_t)P->nc, 1);
     if (!coef || !fval || !fb) { free(coef); free(fval); free(fb); return -1; }
-    or_reconstruct(P, u, coef, fval, NULL, fb);
-    double alpha = 0.0;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < P->nc; ++i) reconstruct_cell(P, i, u, coef, fval, NULL, fb);
+    real alpha = 0.0;
     if (P->flux != OR_ADVECTION) alpha = global_alpha(P, fval);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < P->nc; ++i) divergence_cell(P, i, u, coef, fval, fb, alpha, dudt);
@@ -524,26 +636,44 @@ int or_rhs(const or_problem *P, const double *u, double *dudt, double *alpha_out
     return 0;
 }
 
-/* n steps of the third-order TVD Runge-Kutta scheme, in place on u. */
-int or_rk3(const or_problem *P, double *u, double dt, int nsteps)
+/* L(u); alpha_out (nullable) receives the LF alpha used (0 for linear
+ * advection, where alpha is per facet). */
+int or_rhs(const or_problem *P, const double *u, double *dudt, double *alpha_out)
 {
     size_t N = (size_t)P->nvars * P->nc;
-    double *L = (double *)malloc(N * sizeof(double));
-    double *k1 = (double *)malloc(N * sizeof(double));
-    double *k2 = (double *)malloc(N * sizeof(double));
-    if (!L || !k1 || !k2) { free(L); free(k1); free(k2); return -1; }
+    real *ur = to_real(u, N), *Lr = (real *)malloc(N * sizeof(real)), a = 0.0;
+    if (!ur || !Lr) { free(ur); free(Lr); return -1; }
+    int st = rhs_real(P, ur, Lr, &a);
+    if (!st) to_double(Lr, dudt, N);
+    if (alpha_out) *alpha_out = (double)a;
+    free(ur); free(Lr);
+    return st;
+}
+
+/* n steps of the third-order TVD Runge-Kutta scheme, in place on u (the
+ * state is carried in working precision between stages and steps). */
+int or_rk3(const or_problem *P, double *u, double dt_in, int nsteps)
+{
+    size_t N = (size_t)P->nvars * P->nc;
+    real dt = dt_in;
+    real *U = to_real(u, N);
+    real *L = (real *)malloc(N * sizeof(real));
+    real *k1 = (real *)malloc(N * sizeof(real));
+    real *k2 = (real *)malloc(N * sizeof(real));
+    if (!U || !L || !k1 || !k2) goto fail;
     for (int s = 0; s < nsteps; ++s) {
-        if (or_rhs(P, u, L, NULL)) goto fail;
-        for (size_t t = 0; t < N; ++t) k1[t] = u[t] + dt * L[t];
-        if (or_rhs(P, k1, L, NULL)) goto fail;
-        for (size_t t = 0; t < N; ++t) k2[t] = 0.75 * u[t] + 0.25 * k1[t] + 0.25 * dt * L[t];
-        if (or_rhs(P, k2, L, NULL)) goto fail;
+        if (rhs_real(P, U, L, NULL)) goto fail;
+        for (size_t t = 0; t < N; ++t) k1[t] = U[t] + dt * L[t];
+        if (rhs_real(P, k1, L, NULL)) goto fail;
+        for (size_t t = 0; t < N; ++t) k2[t] = 0.75 * U[t] + 0.25 * k1[t] + 0.25 * dt * L[t];
+        if (rhs_real(P, k2, L, NULL)) goto fail;
         for (size_t t = 0; t < N; ++t)
-            u[t] = (1.0 / 3.0) * u[t] + (2.0 / 3.0) * k2[t] + (2.0 / 3.0) * dt * L[t];
+            U[t] = ((real)1.0 / 3.0) * U[t] + ((real)2.0 / 3.0) * k2[t] + ((real)2.0 / 3.0) * dt * L[t];
     }
-    free(L); free(k1); free(k2);
+    to_double(U, u, N);
+    free(U); free(L); free(k1); free(k2);
     return 0;
 fail:
-    free(L); free(k1); free(k2);
+    free(U); free(L); free(k1); free(k2);
     return -1;
 }

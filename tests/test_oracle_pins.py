@@ -258,7 +258,7 @@ def test_qrcp_solve_matches_lapack():
         assert np.max(np.abs((v - v_ref) / s)) <= tol
         assert np.max(np.abs((v - v_ls) / s)) <= tol
         # diag(R) magnitudes are non-increasing (pivoting), and match LAPACK's
-        assert np.all(np.abs(rd[1:]) <= np.abs(rd[:-1]) * (1 + 1e-12))
+        assert np.all(np.abs(rd[1:]) <= np.abs(rd[:-1]) * (1 + 1e-9))   # ties within 1e-10 allowed
 
 
 def test_rank_truncation_drops_dependent_column():
