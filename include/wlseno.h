@@ -1,0 +1,192 @@
+/*
+ * wlseno.h -- C-ABI of the MI355X WLS-ENO finite-volume library.
+ *
+ * The library implements, on one AMD Instinct MI355X (gfx950), the per-cell
+ * weighted-least-squares essentially non-oscillatory (WLS-ENO) reconstruction
+ * of Liu & Jiao (arXiv:1602.02694) and the finite-volume update built on it:
+ *
+ *   given cell averages u_i on a simplex mesh, for every cell
+ *     - gather the stencil's cell averages                    (Sec. 3.1.1, 3.2)
+ *     - form the non-smoothness indicators and weights        (Sec. 3.1.2, eqs.
+ *       smoothness indicator and weight)
+ *     - solve the column-scaled weighted least-squares system for the Taylor
+ *       coefficients with Householder QR and column pivoting  (Sec. 3.3.2, eq.
+ *       scaled_WLS and the rank-truncated pseudo-inverse)
+ *     - evaluate the degree p-1 polynomial at the facet quadrature points
+ *                                                             (end of Sec. 3.2)
+ *   then apply the Lax-Friedrichs flux (Sec. 1, eq. flux) to form
+ *   du_i/dt = -(1/|tau_i|) sum_facets flux (Sec. 1, eq. fvm) and advance with
+ *   the third-order TVD Runge-Kutta scheme (Sec. 4.2.1, eq. 3rd-order-RK).
+ *
+ * Conventions (shared with every caller):
+ *   - All floating point is IEEE binary64.  Indices are int32.
+ *   - Cell arrays are in the caller's ("user") cell order.  Internally the
+ *     library renumbers cells (reverse Cuthill-McKee); that is invisible here.
+ *   - Field arrays are structure-of-arrays: u[var * n_cell + cell].
+ *   - Local facet lf of a cell is the facet opposite its vertex lf.  Facet
+ *     points: 1-D the facet node; 2-D ceil(p/2) Gauss-Legendre points along the
+ *     edge from vertex (lf+1)%3 to vertex (lf+2)%3, in increasing parameter;
+ *     3-D the 3-point degree-2 rule with weight 2/3 on the facet vertices
+ *     (lf+1)%4, (lf+2)%4, (lf+3)%4 in that order.
+ *   - Taylor coefficients are in graded order: total degree ascending, then
+ *     exponent tuples in descending lexicographic order (x first); entry k
+ *     multiplies prod_d (x_d - c_d)^{a_kd} / a_kd! about the cell centroid c.
+ *   - Device pointers ("_dev") are caller-owned HIP device memory, borrowed for
+ *     the duration of the call.  Host pointers are read (or written) before the
+ *     call returns.  Device work is enqueued on the context's stream and the
+ *     call returns without waiting; the caller synchronises the stream.
+ *   - Every function returns a status and never throws; on failure
+ *     wlseno_last_error() describes the cause.  A context must be used from one
+ *     host thread at a time.
+ */
+#ifndef WLSENO_H
+#define WLSENO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WLSENO_OK = 0,
+    WLSENO_EINVAL = 1,       /* bad argument, bad mesh, stencil too small */
+    WLSENO_ENOMEM = 2,       /* host or device allocation failed */
+    WLSENO_EDEVICE = 3,      /* a HIP runtime call failed */
+    WLSENO_ESTATE = 4,       /* call out of order (e.g. rhs before stencil_build),
+                                or a device call on a host-only context */
+    WLSENO_EUNSUPPORTED = 5  /* valid request outside the compiled variants */
+} wlseno_status;
+
+/* flux functions */
+enum {
+    WLSENO_FLUX_ADVECTION = 0, /* F(u) = a u; Lax-Friedrichs alpha = |a.n| per facet */
+    WLSENO_FLUX_BURGERS = 1,   /* F(u) = (u^2/2)(1,..,1); alpha = global max |u sum_d n_d| */
+    WLSENO_FLUX_EULER = 2      /* reserved: conserved-variable Euler system */
+};
+
+/* mesh flags */
+#define WLSENO_MESH_PERIODIC_1D 1u /* 1-D only: first and last node are one point;
+                                       period = x_last - x_first */
+
+/* Method parameters.  wlseno_params_default() fills the readings used
+ * throughout: eps = 1e-2 and alpha_w = 1.5 (the example values of Sec. 3.1.2),
+ * rank_tol = 1e-12 relative to |R_11| (Sec. 3.3.2 leaves it open), unit
+ * weights off. */
+typedef struct {
+    int32_t p;           /* order: reconstruct polynomials of degree p-1 (1-D: 2..5, 2-D: 2..4, 3-D: 2..3) */
+    int32_t n_lo, n_hi;  /* stencil size rule: grow rings until >= n_lo cells, keep the n_hi nearest */
+    int32_t flux;        /* WLSENO_FLUX_* */
+    int32_t weight_mode; /* 0: WLS-ENO weights (eq. weight); 1: unit weights (plain least squares) */
+    int32_t reserved;
+    double eps;          /* epsilon in beta_j = (u_j - u_i)^2 + eps h^2 */
+    double alpha_w;      /* centre weight factor alpha > 1 in eq. (weight) */
+    double rank_tol;     /* numerical rank: |R_kk| > rank_tol |R_11| */
+    double velocity[3];  /* advection velocity a */
+    double gamma;        /* ratio of specific heats (Euler) */
+} wlseno_params;
+
+typedef struct {
+    int32_t dim;             /* 1, 2 or 3 */
+    int32_t m;               /* Taylor coefficients per cell = C(p-1+dim, dim) */
+    int32_t n_vars;          /* field components */
+    int32_t faces_per_cell;  /* dim + 1 */
+    int32_t points_per_face; /* facet quadrature points */
+    int32_t min_stencil, max_stencil;
+    int32_t reserved;
+    int64_t n_cell;
+    int64_t nnz;             /* total stencil entries */
+    double h;                /* mean edge length used in eps h^2 (1-D: mean width) */
+    double min_insphere;     /* min over cells of 2 dim |tau| / |d tau| (CFL length) */
+} wlseno_info;
+
+typedef struct wlseno_ctx *wlseno_t;
+
+/* Fill *out with the defaults described above (p=3, n_lo=12, n_hi=20,
+ * advection with a = (1,0,0), gamma = 1.4). */
+void wlseno_params_default(wlseno_params *out);
+
+/* Create a context on HIP device `device` (its default stream is used until
+ * wlseno_set_stream).  device = -1 creates a host-only context: mesh upload,
+ * stencil build and the query functions work, device calls return ESTATE. */
+wlseno_status wlseno_create(int device, wlseno_t *out);
+
+/* Free everything the context owns (host and device).  NULL is accepted. */
+wlseno_status wlseno_destroy(wlseno_t ctx);
+
+/* Text of the last error on this context ("" if none); valid until the next
+ * call on the context.  ctx = NULL gives the last create() failure. */
+const char *wlseno_last_error(wlseno_t ctx);
+
+/* Enqueue all later device work on `hip_stream` (a hipStream_t; NULL = the
+ * device's null stream). */
+wlseno_status wlseno_set_stream(wlseno_t ctx, void *hip_stream);
+
+/* Upload a simplex mesh (host arrays, copied).
+ *   xyz   : double[n_vert * dim] vertex coordinates
+ *   cells : int32[n_cell * (dim+1)] vertex ids; every cell must have positive
+ *           measure (2-D counter-clockwise, 3-D positively oriented), else EINVAL
+ *           naming the cell.
+ *   flags : WLSENO_MESH_PERIODIC_1D or 0.
+ * Facets shared by more than two cells give EINVAL.  Invalidates any previous
+ * stencil build.  (Sec. 3.3.1: cells, sibling half-facets, vertex-to-cell map.) */
+wlseno_status wlseno_mesh_upload(wlseno_t ctx, int dim, int64_t n_vert, const double *xyz,
+                                 int64_t n_cell, const int32_t *cells, uint32_t flags);
+
+/* Build the per-cell stencils and all per-cell geometry for `params`, and
+ * copy them to the device (device contexts).  Stencils follow the k-ring
+ * neighbourhoods of Sec. 3.2 (1/2-ring increments in 2-D, 1/3-ring in 3-D):
+ * levels grow until a stencil holds >= n_lo cells; stencils with more than
+ * n_hi cells keep the centre and the n_hi-1 cells with the smallest squared
+ * centroid distance (ties: lower user id).  Rows are ordered centre first,
+ * then by (squared distance, user id).  The squared distance is
+ * sum_d (c_jd - c_id)^2 accumulated in coordinate order with centroids
+ * (sum_v x_v)/(dim+1) accumulated in vertex order, no fused multiply-add
+ * (1-D periodic: nearest image).  A stencil with fewer than m cells gives
+ * EINVAL naming the cell. */
+wlseno_status wlseno_stencil_build(wlseno_t ctx, const wlseno_params *params);
+
+/* Sizes of the current build (after stencil_build). */
+wlseno_status wlseno_get_info(wlseno_t ctx, wlseno_info *out);
+
+/* Copy the stencils to host arrays in user order and user ids:
+ * row_ptr int32[n_cell+1], col int32[nnz]; rows as described above. */
+wlseno_status wlseno_get_stencil(wlseno_t ctx, int32_t *row_ptr, int32_t *col);
+
+/* Reconstruct every cell from u_dev (double[n_vars * n_cell]).
+ *   coef_dev     : nullable, double[n_vars * n_cell * m] Taylor coefficients
+ *   facevals_dev : nullable, double[n_vars * n_cell * (dim+1) * Q] values of the
+ *                  reconstruction at each cell's own facet points
+ *   rank_dev     : nullable, int32[n_vars * n_cell] numerical ranks */
+wlseno_status wlseno_reconstruct(wlseno_t ctx, const double *u_dev, double *coef_dev,
+                                 double *facevals_dev, int32_t *rank_dev);
+
+/* dudt_dev = L(u_dev): the semi-discrete right-hand side
+ * -(1/|tau_i|) sum_f |f| sum_q w_q Fhat(u-, u+, n).  Boundary facets use the
+ * transmissive ghost u+ = u-.  dudt_dev must not alias u_dev. */
+wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev);
+
+/* Advance u_dev in place by n_steps steps of size dt of third-order TVD
+ * Runge-Kutta (three right-hand sides per step). */
+wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps);
+
+/* The Lax-Friedrichs alpha used by the last rhs stage (Burgers/Euler; 0 for
+ * advection), read back from the device (synchronises the stream). */
+wlseno_status wlseno_last_alpha(wlseno_t ctx, double *alpha);
+
+/* Kernel timing for measurement.  on = 1 clears the accumulators and from
+ * then on brackets every reconstruction and flux/update launch with HIP
+ * events on the context's stream; on = 0 stops recording.  The events add a
+ * small gap between kernels, so time throughput with profiling off. */
+wlseno_status wlseno_profile(wlseno_t ctx, int on);
+
+/* Synchronise the stream and return the summed event time (milliseconds) and
+ * the number of launches recorded for `kernel`: 0 = reconstruction
+ * (k_reconstruct), 1 = flux, divergence and Runge-Kutta update (k_update). */
+wlseno_status wlseno_profile_read(wlseno_t ctx, int kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WLSENO_H */

@@ -1,0 +1,65 @@
+"""Build the WLS-ENO shared library in-tree for gfx950.
+
+    python -m paper_1602_02694_amd.build
+
+Produces ``paper_1602_02694_amd/libwlseno.so`` from ``csrc/``:
+``kernels.hip`` through hipcc (device code for gfx950), the host sources
+through g++ (``setup.cpp`` with -ffp-contract=off, since centroid and distance
+arithmetic fix the stencil order).
+"""
+
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libwlseno.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+ARCH = "gfx950"
+
+HIPCC_FLAGS = [
+    "--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
+    # no packed FP32 instructions anywhere in device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    hipcc = os.path.join(ROCM, "bin", "hipcc")
+    cxx = shutil.which("g++") or "g++"
+    inc = ["-I" + os.path.join(ROCM, "include"), "-I" + CSRC]
+    objs = []
+    o = os.path.join(BUILD, "kernels.o")
+    _run([hipcc] + HIPCC_FLAGS + inc + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", o], verbose)
+    objs.append(o)
+    o = os.path.join(BUILD, "setup.o")
+    _run([cxx] + CXX_FLAGS + ["-ffp-contract=off", "-fopenmp"] + inc +
+         ["-c", os.path.join(CSRC, "setup.cpp"), "-o", o], verbose)
+    objs.append(o)
+    o = os.path.join(BUILD, "api.o")
+    _run([cxx] + CXX_FLAGS + ["-D__HIP_PLATFORM_AMD__"] + inc +
+         ["-c", os.path.join(CSRC, "api.cpp"), "-o", o], verbose)
+    objs.append(o)
+    tmp = LIB + ".tmp"
+    _run([cxx, "-shared", "-fopenmp", "-o", tmp] + objs +
+         ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib")], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-q" not in sys.argv)
+    print(LIB)

@@ -1,0 +1,92 @@
+// Internal declarations of the WLS-ENO library (host setup, device data,
+// kernel launchers).  Not part of the C-ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/wlseno.h"
+
+namespace wlseno {
+
+struct Error {
+    wlseno_status status;
+    std::string msg;
+};
+
+// Number of Taylor coefficients C(p-1+dim, dim).
+int num_coeffs(int dim, int p);
+// Facet quadrature points per facet (1-D: 1; 2-D: ceil(p/2); 3-D: 3).
+int points_per_face(int dim, int p);
+
+// Mesh as uploaded (user order), with topology.
+struct HostMesh {
+    int dim = 0;
+    int64_t nv = 0, nc = 0;
+    bool periodic = false;
+    double period = 0.0;
+    std::vector<double> xyz;         // nv*dim
+    std::vector<int32_t> cells;      // nc*(dim+1), user vertex ids
+    std::vector<int32_t> vid;        // nc*(dim+1), periodic end node identified with node 0
+    std::vector<double> vol;         // nc
+    std::vector<double> cent;        // nc*dim
+    std::vector<int32_t> sib;        // nc*(dim+1): (cell << 2 | lf) of the sibling half-facet, or -1
+    std::vector<int32_t> v2c_ptr, v2c;   // vertex -> incident cells (CSR, ascending)
+    std::vector<int32_t> e2c_ptr, e2c;   // 3-D: edge -> incident cells
+    std::vector<int32_t> cell_edges;     // 3-D: nc*6 edge ids
+    double h = 0.0;                  // mean edge length (1-D: mean width)
+};
+
+// Everything derived for one parameter set, in device cell order.
+struct Build {
+    wlseno_params prm{};
+    int m = 0, nq = 0, nf = 0, nvars = 1, gs = 0;   // gs: geometry record stride (doubles)
+    int min_stencil = 0, max_stencil = 0;
+    double min_insphere = 0.0;
+    // user order / user ids
+    std::vector<int32_t> row_ptr, col;
+    // perm[d] = user id of device cell d; iperm[u] = device id of user cell u
+    std::vector<int32_t> perm, iperm;
+    // device order records
+    std::vector<double> geo;        // nc*gs: centroid, then moments nu(alpha)=mu(alpha)/alpha! for 2 <= |alpha| <= p-1
+    std::vector<double> vrel;       // nc*(dim+1)*dim vertex offsets from the centroid
+    std::vector<int32_t> sptr, scol;    // device-order CSR, device ids, centre first
+    std::vector<int32_t> dsib;      // nc*F: (device cell << 2 | lf) or -1
+    std::vector<int32_t> qperm;     // nc*F: 2 bits per point q: sibling's point index of own point q
+    std::vector<double> normal;     // nc*F*dim unit outward normals; sibling = exact negation
+    std::vector<double> area;       // nc*F facet measures (identical on both sides)
+    std::vector<double> rvol;       // nc: 1/|tau|
+};
+
+void mesh_setup(HostMesh &mesh, int dim, int64_t nv, const double *xyz, int64_t nc,
+                const int32_t *cells, uint32_t flags);
+void build_setup(const HostMesh &mesh, const wlseno_params &prm, Build &b);
+
+// ---------------------------------------------------------------- device
+struct DevMesh {
+    int dim = 0, p = 0, m = 0, nq = 0, nf = 0, nvars = 1, gs = 0;
+    int flux = 0, weight_mode = 0, max_stencil = 0;
+    int64_t nc = 0;
+    double eh2 = 0.0, alpha_w = 1.5, rank_tol = 1e-12, period = 0.0, gamma = 1.4;
+    double vel[3] = {0, 0, 0};
+    const double *geo = nullptr, *vrel = nullptr, *normal = nullptr, *area = nullptr, *rvol = nullptr;
+    const int32_t *sptr = nullptr, *scol = nullptr, *sib = nullptr, *qperm = nullptr, *perm = nullptr;
+    double *fv = nullptr;                  // nvars*nc*F*Q, device order, cell-major
+    unsigned long long *alpha = nullptr;   // 2 parities x 64 slots of max bits
+};
+
+constexpr int kAlphaSlots = 64;
+
+// Returns hipSuccess (0) or an error code; `supported` tells whether the
+// (dim, p, stencil size) combination has a compiled variant.
+bool reconstruct_supported(const DevMesh &dm);
+int launch_permute(const DevMesh &dm, const double *in, double *out, bool to_device_order, void *stream);
+int launch_clear_alpha(const DevMesh &dm, void *stream);
+int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *coef_user,
+                       double *fv_user, int32_t *rank_user, void *stream);
+// out = L (mode 0) or A*u0 + B*prev + Cdt*L (mode 1).
+int launch_update(const DevMesh &dm, const double *u0, const double *prev, double *out, double A,
+                  double B, double Cdt, int mode, int parity, void *stream);
+
+}  // namespace wlseno

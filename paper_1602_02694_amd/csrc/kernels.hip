@@ -1,0 +1,699 @@
+// WLS-ENO device kernels for gfx950 (MI355X).
+//
+//  k_reconstruct : one cell per group of 4 lanes (a DPP quad).  Each lane holds
+//                  RPL rows of the cell's weighted, column-scaled Taylor system
+//                  in registers; column norms and Householder dot products are
+//                  reduced across the quad with DPP quad_perm butterflies, so
+//                  every lane of a cell sees bitwise-identical sums and takes
+//                  the same pivot decisions.  Output: the degree p-1
+//                  polynomial evaluated at the cell's own facet points
+//                  (Sec. 3.1-3.3 of the paper).
+//  k_update      : one thread per cell.  Lax-Friedrichs flux at every facet
+//                  point (Sec. 1, eq. flux), computed by both cells of a facet
+//                  from identical operands in the orientation of the facet's
+//                  lower-numbered cell, so the two contributions are exact
+//                  negatives (conservative, deterministic, no atomics); then
+//                  L_i = -(1/|tau_i|) sum_f |f| sum_q w_q Fhat and the TVD RK3
+//                  stage combination (Sec. 4.2.1).
+//  k_permute     : user order <-> device (reverse Cuthill-McKee) order.
+//
+// All arithmetic is FP64 on the vector ALUs: these are tiny independent
+// least-squares solves, not a dense contraction, so MFMA does not apply.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace wlseno {
+namespace {
+
+constexpr int kFluxAdv = WLSENO_FLUX_ADVECTION;
+constexpr double kPivotTie = 1e-10;
+constexpr int kFluxBurgers = WLSENO_FLUX_BURGERS;
+
+constexpr int binom(int n, int k)
+{
+    int r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+template <int DIM, int P>
+struct Basis {
+    static constexpr int M = binom(P - 1 + DIM, DIM);
+    int e[M][3];
+    constexpr Basis() : e{}
+    {
+        int k = 0;
+        for (int q = 0; q <= P - 1; ++q) {
+            if (DIM == 1) {
+                e[k][0] = q; e[k][1] = 0; e[k][2] = 0; ++k;
+            } else if (DIM == 2) {
+                for (int a = q; a >= 0; --a) { e[k][0] = a; e[k][1] = q - a; e[k][2] = 0; ++k; }
+            } else {
+                for (int a = q; a >= 0; --a)
+                    for (int b = q - a; b >= 0; --b) { e[k][0] = a; e[k][1] = b; e[k][2] = q - a - b; ++k; }
+            }
+        }
+    }
+    constexpr int deg(int k) const { return e[k][0] + e[k][1] + e[k][2]; }
+    // beta_t <= alpha_k componentwise
+    constexpr bool le(int t, int k) const
+    {
+        return e[t][0] <= e[k][0] && e[t][1] <= e[k][1] && e[t][2] <= e[k][2];
+    }
+};
+
+template <int DIM, int P>
+constexpr int num_q() { return DIM == 1 ? 1 : (DIM == 2 ? ((P + 1) / 2 > 1 ? (P + 1) / 2 : 1) : 3); }
+
+// Geometry record stride: centroid + moments of degree 2..P-1, padded to even.
+template <int DIM, int P>
+constexpr int geo_stride()
+{
+    int s = DIM + (Basis<DIM, P>::M - 1 - DIM);
+    return (s & 1) ? s + 1 : s;
+}
+
+// ------------------------------------------------------------ lane exchange
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x)
+{
+    int lo = __double2loint(x);
+    int hi = __double2hiint(x);
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 4 lanes of a quad; identical bits in all four lanes.
+__device__ __forceinline__ double quad_sum(double x)
+{
+    x = x + dpp_d<0xB1>(x);   // quad_perm [1,0,3,2]
+    x = x + dpp_d<0x4E>(x);   // quad_perm [2,3,0,1]
+    return x;
+}
+
+// Value of lane l of the quad (l is a constant after unrolling).
+__device__ __forceinline__ double quad_bcast(double x, int l)
+{
+    switch (l & 3) {
+    case 0: return dpp_d<0x00>(x);
+    case 1: return dpp_d<0x55>(x);
+    case 2: return dpp_d<0xAA>(x);
+    default: return dpp_d<0xFF>(x);
+    }
+}
+
+// pw[d][a] = x_d^a / a!
+template <int DIM, int P>
+__device__ __forceinline__ void scaled_powers(const double (&x)[DIM], double (&pw)[DIM][P])
+{
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        pw[d][0] = 1.0;
+#pragma unroll
+        for (int a = 1; a < P; ++a) pw[d][a] = pw[d][a - 1] * x[d] * (1.0 / a);
+    }
+}
+
+// Facet point q of facet lf, relative to the centroid.
+template <int DIM, int Q>
+__device__ __forceinline__ void facet_point(const double *vr, int lf, int q, double (&x)[DIM])
+{
+    if constexpr (DIM == 1) {
+        x[0] = vr[lf == 0 ? 1 : 0];
+    } else if constexpr (DIM == 2) {
+        const double *a = vr + ((lf + 1) % 3) * 2;
+        const double *b = vr + ((lf + 2) % 3) * 2;
+        double t;
+        if constexpr (Q == 1) {
+            t = 0.5;
+        } else {
+            // Gauss-Legendre nodes on [0,1], ascending
+            const double h = 0.5 / 1.7320508075688772;   // 1/(2 sqrt 3)
+            t = q == 0 ? 0.5 - h : 0.5 + h;
+        }
+#pragma unroll
+        for (int d = 0; d < 2; ++d) x[d] = a[d] + t * (b[d] - a[d]);
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const double w = (t == q) ? (2.0 / 3.0) : (1.0 / 6.0);
+                s += w * vr[((lf + 1 + t) % 4) * 3 + d];
+            }
+            x[d] = s;
+        }
+    }
+}
+
+template <int DIM, int Q>
+__device__ __forceinline__ double quad_weight(int q)
+{
+    if constexpr (DIM == 1) return 1.0;
+    else if constexpr (DIM == 2) return Q == 1 ? 1.0 : 0.5;
+    else return 1.0 / 3.0;
+}
+
+struct RArgs {
+    int64_t nc;
+    const double *u, *geo, *vrel, *normal;
+    const int32_t *sptr, *scol, *sib, *perm;
+    double *fv;
+    double *coef_user, *fv_user;
+    int32_t *rank_user;
+    unsigned long long *alpha_acc;   // 64 slots (stride 16) of this stage's parity
+    double eh2, alpha_w, rank_tol, period;
+    int weight_mode;
+};
+
+// --------------------------------------------------------------- K1
+template <int DIM, int P, int RPL, int FLUX>
+__global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
+{
+    constexpr Basis<DIM, P> B{};
+    constexpr int M = Basis<DIM, P>::M;
+    constexpr int F = DIM + 1;
+    constexpr int Q = num_q<DIM, P>();
+    constexpr int NMOM = M - 1 - DIM;
+    constexpr int GS = geo_stride<DIM, P>();
+    constexpr int G = 4;
+    constexpr int RS = (M + G - 1) / G;
+
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cell = gid >> 2;
+    const int g = (int)(threadIdx.x & 3);
+    const bool live = cell < a.nc;
+    const int64_t c = live ? cell : a.nc - 1;
+
+    const double *gc = a.geo + c * GS;
+    double xc[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xc[d] = gc[d];
+    const double uc = a.u[c];
+    const int32_t base = a.sptr[c];
+    const int n = a.sptr[c + 1] - base;
+
+    // indicator of the centre: smallest over its facet neighbours
+    double bmin = -1.0;
+#pragma unroll
+    for (int lf = 0; lf < F; ++lf) {
+        const int32_t s = a.sib[c * F + lf];
+        if (s >= 0) {
+            const double du = a.u[s >> 2] - uc;
+            const double bt = du * du + a.eh2;
+            bmin = (bmin < 0.0 || bt < bmin) ? bt : bmin;
+        }
+    }
+    bmin = bmin < 0.0 ? a.eh2 : bmin;
+
+    // weighted rows  W A  and  W u
+    double A[RPL][M], bv[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * G + g;
+        const bool valid = live && r < n;
+        const int32_t j = valid ? a.scol[base + r] : (int32_t)c;
+        const double *gj = a.geo + (int64_t)j * GS;
+        double dl[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) dl[d] = gj[d] - xc[d];
+        if constexpr (DIM == 1) {
+            const double L = a.period;
+            if (L > 0.0) dl[0] = dl[0] > 0.5 * L ? dl[0] - L : (dl[0] < -0.5 * L ? dl[0] + L : dl[0]);
+        }
+        double nu[NMOM > 0 ? NMOM : 1];
+#pragma unroll
+        for (int t = 0; t < NMOM; ++t) nu[t] = gj[DIM + t];
+        const double uj = a.u[j];
+        double pw[DIM][P];
+        scaled_powers<DIM, P>(dl, pw);
+        // average over cell j of the Taylor monomial k about x_c:
+        //   sum_{t <= k} (delta^{a_k - a_t} / (a_k - a_t)!) nu_j(a_t), nu(0) = 1, nu(|a|=1) = 0
+        double row[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            double acc = 1.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) acc *= pw[d][B.e[k][d]];
+#pragma unroll
+            for (int t = 1 + DIM; t < M; ++t) {
+                if (B.le(t, k)) {
+                    double ph = nu[t - 1 - DIM];
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d) ph *= pw[d][B.e[k][d] - B.e[t][d]];
+                    acc += ph;
+                }
+            }
+            row[k] = acc;
+        }
+        double w = 1.0;
+        if (a.weight_mode == 0) {
+            const double du = uj - uc;
+            const double num = (r == 0) ? a.alpha_w : 1.0;
+            const double den = (r == 0) ? bmin : du * du + a.eh2;
+            w = num / den;
+        }
+        w = valid ? w : 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) A[s][k] = w * row[k];
+        bv[s] = w * uj;
+    }
+
+    // column scaling S = diag(1 / ||(W A)_k||)
+    double sc[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) t = fma(A[s][k], A[s][k], t);
+        t = quad_sum(t);
+        const double nr = sqrt(t);
+        sc[k] = nr > 0.0 ? 1.0 / nr : 0.0;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) A[s][k] *= sc[k];
+    }
+
+    // Householder QR with column pivoting.  Rows < k are retired into the
+    // owner lane's R store (Rs, cs) and zeroed in A, so every reduction runs
+    // over all slots without row predicates.
+    int pm[M];
+    double rd[M];
+    double Rs[RS][M], cs[RS];
+#pragma unroll
+    for (int k = 0; k < M; ++k) pm[k] = k;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+        cs[s] = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) Rs[s][k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        double eta[M];
+#pragma unroll
+        for (int cc = k; cc < M; ++cc) {
+            double t = 0.0;
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) t = fma(A[s][cc], A[s][cc], t);
+            eta[cc] = quad_sum(t);
+        }
+        // pivot: lowest column index among those within a relative kPivotTie
+        // of the largest partial norm (rounding must not order unit-norm ties)
+        double best = eta[k];
+#pragma unroll
+        for (int cc = k + 1; cc < M; ++cc) best = fmax(best, eta[cc]);
+        const double tie = best * (1.0 - kPivotTie);
+        int piv = M - 1;
+#pragma unroll
+        for (int cc = M - 1; cc >= k; --cc) piv = eta[cc] >= tie ? cc : piv;
+#pragma unroll
+        for (int cc = k + 1; cc < M; ++cc) {
+            const bool sw = piv == cc;
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) {
+                const double t0 = A[s][k], t1 = A[s][cc];
+                A[s][k] = sw ? t1 : t0;
+                A[s][cc] = sw ? t0 : t1;
+            }
+            // a pivot exchanges whole columns: the R entries of retired rows too
+#pragma unroll
+            for (int s = 0; s < RS; ++s) {
+                if (s * G < k) {
+                    const double t0 = Rs[s][k], t1 = Rs[s][cc];
+                    Rs[s][k] = sw ? t1 : t0;
+                    Rs[s][cc] = sw ? t0 : t1;
+                }
+            }
+            const double s0 = sc[k], s1 = sc[cc];
+            sc[k] = sw ? s1 : s0;
+            sc[cc] = sw ? s0 : s1;
+            const int p0 = pm[k], p1 = pm[cc];
+            pm[k] = sw ? p1 : p0;
+            pm[cc] = sw ? p0 : p1;
+        }
+        const double alpha = quad_bcast(A[k / G][k], k % G);
+        const bool nz = best > 0.0;
+        const double beta = nz ? -copysign(sqrt(best), alpha) : 0.0;
+        const double tau = nz ? (beta - alpha) / beta : 0.0;
+        const double scal = nz ? 1.0 / (alpha - beta) : 0.0;
+        const bool own = g == (k % G);
+        double v[RPL];
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) v[s] = A[s][k] * scal;
+        v[k / G] = own ? 1.0 : v[k / G];
+#pragma unroll
+        for (int cc = k + 1; cc < M; ++cc) {
+            double t = 0.0;
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) t = fma(v[s], A[s][cc], t);
+            const double tw = tau * quad_sum(t);
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) A[s][cc] = fma(-tw, v[s], A[s][cc]);
+        }
+        {
+            double t = 0.0;
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) t = fma(v[s], bv[s], t);
+            const double tw = tau * quad_sum(t);
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) bv[s] = fma(-tw, v[s], bv[s]);
+        }
+        rd[k] = beta;
+#pragma unroll
+        for (int cc = k + 1; cc < M; ++cc) {
+            Rs[k / G][cc] = own ? A[k / G][cc] : Rs[k / G][cc];
+            A[k / G][cc] = own ? 0.0 : A[k / G][cc];
+        }
+        Rs[k / G][k] = own ? beta : Rs[k / G][k];
+        cs[k / G] = own ? bv[k / G] : cs[k / G];
+        bv[k / G] = own ? 0.0 : bv[k / G];
+    }
+
+    // numerical rank and back substitution on the leading r x r block
+    const double thr = a.rank_tol * fabs(rd[0]);
+    int rank = 0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        ok = ok && (fabs(rd[k]) > thr);
+        rank += ok ? 1 : 0;
+    }
+    double y[M];
+#pragma unroll
+    for (int k = M - 1; k >= 0; --k) {
+        double acc = cs[k / G];
+#pragma unroll
+        for (int j = k + 1; j < M; ++j) acc = fma(-Rs[k / G][j], y[j], acc);
+        const double yk = quad_bcast(acc / Rs[k / G][k], k % G);
+        y[k] = (k < rank) ? yk : 0.0;
+    }
+    // coefficients in the original basis order: v = S E y
+    double coef[M];
+#pragma unroll
+    for (int o = 0; o < M; ++o) coef[o] = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const double val = sc[k] * y[k];
+#pragma unroll
+        for (int o = 0; o < M; ++o) coef[o] = (pm[k] == o) ? val : coef[o];
+    }
+
+    // evaluate at the facet points: lane g handles facet g
+    const int lf = g < F ? g : 0;
+    const double *vr = a.vrel + c * F * DIM;
+    double fq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        double x[DIM];
+        facet_point<DIM, Q>(vr, lf, q, x);
+        double pw[DIM][P];
+        scaled_powers<DIM, P>(x, pw);
+        double val = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            double ph = coef[k];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) ph *= pw[d][B.e[k][d]];
+            val += ph;
+        }
+        fq[q] = val;
+    }
+    const bool writer = live && g < F;
+    if (writer) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) a.fv[(c * F + lf) * Q + q] = fq[q];
+    }
+    if (live && (a.coef_user || a.fv_user || a.rank_user)) {
+        const int64_t uid = a.perm[c];
+        if (a.coef_user) {
+#pragma unroll
+            for (int o = 0; o < M; ++o)
+                if ((o & 3) == g) a.coef_user[uid * M + o] = coef[o];
+        }
+        if (a.fv_user && g < F) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) a.fv_user[(uid * F + lf) * Q + q] = fq[q];
+        }
+        if (a.rank_user && g == 0) a.rank_user[uid] = rank;
+    }
+
+    if constexpr (FLUX == kFluxBurgers) {
+        // global Lax-Friedrichs alpha: max |u sum_d n_d| over all facet points
+        double am = 0.0;
+        if (writer) {
+            double sn = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) sn += a.normal[(c * F + lf) * DIM + d];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) am = fmax(am, fabs(fq[q] * sn));
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) am = fmax(am, __shfl_xor(am, o));
+        if ((threadIdx.x & 63) == 0) {
+            const int slot = (int)((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % kAlphaSlots);
+            atomicMax(a.alpha_acc + slot * 16, (unsigned long long)__double_as_longlong(am));
+        }
+    }
+}
+
+// --------------------------------------------------------------- K2/K3
+struct UArgs {
+    int64_t nc;
+    const double *fv, *normal, *area, *rvol;
+    const int32_t *sib, *qperm;
+    const double *u0, *prev;
+    double *out;
+    const unsigned long long *alpha_rd;   // this stage's parity (64 slots, stride 16)
+    unsigned long long *alpha_clr;        // next stage's parity, cleared by block 0
+    double A, B, Cdt;
+    double vel[3];
+    int mode;
+};
+
+template <int DIM, int FLUX>
+__device__ __forceinline__ double lf_flux(double ua, double ub, const double (&n)[DIM], double alpha,
+                                          const double (&vel)[3])
+{
+    if constexpr (FLUX == kFluxAdv) {
+        double an = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) an += vel[d] * n[d];
+        return 0.5 * ((an * ua + an * ub) - fabs(an) * (ub - ua));
+    } else {
+        double sn = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) sn += n[d];
+        return 0.5 * ((0.5 * ua * ua * sn + 0.5 * ub * ub * sn) - alpha * (ub - ua));
+    }
+}
+
+template <int DIM, int Q, int FLUX>
+__global__ void __launch_bounds__(256) k_update(UArgs a)
+{
+    constexpr int F = DIM + 1;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double alpha = 0.0;
+    if constexpr (FLUX == kFluxBurgers) {
+        const int lane = (int)(threadIdx.x & 63);
+        double v = __longlong_as_double((long long)a.alpha_rd[lane * 16]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+        alpha = v;
+        if (blockIdx.x == 0 && threadIdx.x < kAlphaSlots) a.alpha_clr[threadIdx.x * 16] = 0ull;
+    }
+    if (c >= a.nc) return;
+    double vel[3] = {a.vel[0], a.vel[1], a.vel[2]};
+    double tot = 0.0;
+#pragma unroll
+    for (int lf = 0; lf < F; ++lf) {
+        const int32_t s = a.sib[c * F + lf];
+        double n[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) n[d] = a.normal[(c * F + lf) * DIM + d];
+        const double *own = a.fv + (c * F + lf) * Q;
+        double facc = 0.0;
+        if (s < 0) {
+            // transmissive boundary: outside state equals inside state
+#pragma unroll
+            for (int q = 0; q < Q; ++q) facc += quad_weight<DIM, Q>(q) * lf_flux<DIM, FLUX>(own[q], own[q], n, alpha, vel);
+        } else {
+            const int64_t j = s >> 2;
+            const int l2 = s & 3;
+            const double *oth = a.fv + (j * F + l2) * Q;
+            const bool owner = c < j;
+            const int32_t qp = owner ? a.qperm[c * F + lf] : a.qperm[j * F + l2];
+            double nn[DIM];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) nn[d] = owner ? n[d] : -n[d];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int qo = (qp >> (2 * q)) & 3;
+                const double ua = owner ? own[q] : oth[q];
+                const double ub = owner ? oth[qo] : own[qo];
+                facc += quad_weight<DIM, Q>(q) * lf_flux<DIM, FLUX>(ua, ub, nn, alpha, vel);
+            }
+            facc = owner ? facc : -facc;
+        }
+        tot += a.area[c * F + lf] * facc;
+    }
+    const double L = -tot * a.rvol[c];
+    double o;
+    if (a.mode == 0)
+        o = L;
+    else
+        o = a.A * a.u0[c] + a.B * a.prev[c] + a.Cdt * L;
+    a.out[c] = o;
+}
+
+// ------------------------------------------------------------- helpers
+__global__ void k_permute(int64_t nc, int nvars, const int32_t *perm, const double *in, double *out,
+                          int to_device)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc * nvars) return;
+    const int64_t v = t / nc, d = t - v * nc;
+    const int64_t u = perm[d];
+    if (to_device)
+        out[v * nc + d] = in[v * nc + u];
+    else
+        out[v * nc + u] = in[v * nc + d];
+}
+
+__global__ void k_clear_alpha(unsigned long long *alpha)
+{
+    const int t = threadIdx.x;
+    if (t < 2 * kAlphaSlots) alpha[t * 16] = 0ull;
+}
+
+// ------------------------------------------------------------ dispatch
+inline int blocks_for(int64_t work, int per_block) { return (int)((work + per_block - 1) / per_block); }
+
+template <int DIM, int P, int RPL>
+int launch_k1(const DevMesh &dm, const RArgs &args, hipStream_t st)
+{
+    const int nb = blocks_for(dm.nc * 4, 256);
+    if (dm.flux == kFluxBurgers)
+        hipLaunchKernelGGL((k_reconstruct<DIM, P, RPL, kFluxBurgers>), dim3(nb), dim3(256), 0, st, args);
+    else
+        hipLaunchKernelGGL((k_reconstruct<DIM, P, RPL, kFluxAdv>), dim3(nb), dim3(256), 0, st, args);
+    return (int)hipGetLastError();
+}
+
+template <int DIM, int Q>
+int launch_k23(const DevMesh &dm, const UArgs &args, hipStream_t st)
+{
+    const int nb = blocks_for(dm.nc, 256);
+    if (dm.flux == kFluxBurgers)
+        hipLaunchKernelGGL((k_update<DIM, Q, kFluxBurgers>), dim3(nb), dim3(256), 0, st, args);
+    else
+        hipLaunchKernelGGL((k_update<DIM, Q, kFluxAdv>), dim3(nb), dim3(256), 0, st, args);
+    return (int)hipGetLastError();
+}
+
+// rows per lane needed for the largest stencil
+inline int rpl_needed(const DevMesh &dm) { return (dm.max_stencil + 3) / 4; }
+
+}  // namespace
+
+bool reconstruct_supported(const DevMesh &dm)
+{
+    const int r = rpl_needed(dm);
+    if (dm.dim == 1) return dm.p >= 2 && dm.p <= 5 && r <= 2;
+    if (dm.dim == 2) return (dm.p == 2 && r <= 2) || (dm.p == 3 && r <= 5) || (dm.p == 4 && r <= 9);
+    return false;
+}
+
+int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *coef_user, double *fv_user,
+                       int32_t *rank_user, void *stream)
+{
+    RArgs a;
+    a.nc = dm.nc;
+    a.u = u;
+    a.geo = dm.geo;
+    a.vrel = dm.vrel;
+    a.normal = dm.normal;
+    a.sptr = dm.sptr;
+    a.scol = dm.scol;
+    a.sib = dm.sib;
+    a.perm = dm.perm;
+    a.fv = dm.fv;
+    a.coef_user = coef_user;
+    a.fv_user = fv_user;
+    a.rank_user = rank_user;
+    a.alpha_acc = dm.alpha + (size_t)parity * kAlphaSlots * 16;
+    a.eh2 = dm.eh2;
+    a.alpha_w = dm.alpha_w;
+    a.rank_tol = dm.rank_tol;
+    a.period = dm.period;
+    a.weight_mode = dm.weight_mode;
+    hipStream_t st = (hipStream_t)stream;
+    const int r = rpl_needed(dm);
+    if (dm.dim == 1) {
+        switch (dm.p) {
+        case 2: return launch_k1<1, 2, 2>(dm, a, st);
+        case 3: return launch_k1<1, 3, 2>(dm, a, st);
+        case 4: return launch_k1<1, 4, 2>(dm, a, st);
+        case 5: return launch_k1<1, 5, 2>(dm, a, st);
+        }
+    } else if (dm.dim == 2) {
+        if (dm.p == 2 && r <= 2) return launch_k1<2, 2, 2>(dm, a, st);
+        if (dm.p == 3 && r <= 5) return launch_k1<2, 3, 5>(dm, a, st);
+        if (dm.p == 4 && r <= 9) return launch_k1<2, 4, 9>(dm, a, st);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_update(const DevMesh &dm, const double *u0, const double *prev, double *out, double A, double B,
+                  double Cdt, int mode, int parity, void *stream)
+{
+    UArgs a;
+    a.nc = dm.nc;
+    a.fv = dm.fv;
+    a.normal = dm.normal;
+    a.area = dm.area;
+    a.rvol = dm.rvol;
+    a.sib = dm.sib;
+    a.qperm = dm.qperm;
+    a.u0 = u0;
+    a.prev = prev;
+    a.out = out;
+    a.alpha_rd = dm.alpha + (size_t)parity * kAlphaSlots * 16;
+    a.alpha_clr = dm.alpha + (size_t)(parity ^ 1) * kAlphaSlots * 16;
+    a.A = A;
+    a.B = B;
+    a.Cdt = Cdt;
+    a.vel[0] = dm.vel[0];
+    a.vel[1] = dm.vel[1];
+    a.vel[2] = dm.vel[2];
+    a.mode = mode;
+    hipStream_t st = (hipStream_t)stream;
+    if (dm.dim == 1) return launch_k23<1, 1>(dm, a, st);
+    if (dm.dim == 2) {
+        if (dm.nq == 1) return launch_k23<2, 1>(dm, a, st);
+        if (dm.nq == 2) return launch_k23<2, 2>(dm, a, st);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_permute(const DevMesh &dm, const double *in, double *out, bool to_device_order, void *stream)
+{
+    const int64_t work = dm.nc * dm.nvars;
+    hipLaunchKernelGGL(k_permute, dim3(blocks_for(work, 256)), dim3(256), 0, (hipStream_t)stream, dm.nc,
+                       dm.nvars, dm.perm, in, out, to_device_order ? 1 : 0);
+    return (int)hipGetLastError();
+}
+
+int launch_clear_alpha(const DevMesh &dm, void *stream)
+{
+    hipLaunchKernelGGL(k_clear_alpha, dim3(1), dim3(2 * kAlphaSlots), 0, (hipStream_t)stream, dm.alpha);
+    return (int)hipGetLastError();
+}
+
+}  // namespace wlseno

@@ -1,0 +1,161 @@
+"""Python binding of the WLS-ENO C-ABI (marshalling only).
+
+Every numerical step runs in the HIP kernels of ``libwlseno.so``; this module
+passes pointers, sizes and torch's current HIP stream, and turns status codes
+into exceptions.  Device arrays are ``torch.float64`` tensors on the GPU.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _native as N
+
+
+class WLSENOError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{N.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+class WLSENO:
+    """One context: a mesh, its stencils and the device data of one parameter set."""
+
+    def __init__(self, device: int = 0):
+        self._lib = N.load()
+        h = C.c_void_p()
+        st = self._lib.wlseno_create(int(device), C.byref(h))
+        if st != N.WLSENO_OK:
+            raise WLSENOError(st, self._lib.wlseno_last_error(None).decode())
+        self._h = h
+        self.device = int(device)
+        self.dim = None
+        self.n_cell = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.wlseno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != N.WLSENO_OK:
+            raise WLSENOError(st, self._lib.wlseno_last_error(self._h).decode())
+
+    def _sync_stream(self):
+        if self.device >= 0:
+            import torch
+
+            s = torch.cuda.current_stream(self.device).cuda_stream
+            self._check(self._lib.wlseno_set_stream(self._h, C.c_void_p(s)))
+
+    # ------------------------------------------------------------ setup
+    def mesh_upload(self, dim, verts, cells, periodic=False):
+        v = np.ascontiguousarray(np.asarray(verts, dtype=np.float64).reshape(-1, dim))
+        c = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, dim + 1))
+        self._check(self._lib.wlseno_mesh_upload(
+            self._h, int(dim), v.shape[0], v.ctypes.data_as(C.POINTER(C.c_double)), c.shape[0],
+            c.ctypes.data_as(C.POINTER(C.c_int32)), N.MESH_PERIODIC_1D if periodic else 0))
+        self.dim = int(dim)
+        self.n_cell = int(c.shape[0])
+
+    def stencil_build(self, p=3, n_lo=12, n_hi=20, flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2,
+                      alpha_w=1.5, rank_tol=1e-12, weight_mode=0, gamma=1.4):
+        prm = N.Params()
+        self._lib.wlseno_params_default(C.byref(prm))
+        prm.p, prm.n_lo, prm.n_hi = int(p), int(n_lo), int(n_hi)
+        prm.flux = N.FLUX[flux] if isinstance(flux, str) else int(flux)
+        prm.weight_mode = int(weight_mode)
+        prm.eps, prm.alpha_w, prm.rank_tol, prm.gamma = float(eps), float(alpha_w), float(rank_tol), float(gamma)
+        for d in range(3):
+            prm.velocity[d] = float(velocity[d]) if d < len(velocity) else 0.0
+        self._check(self._lib.wlseno_stencil_build(self._h, C.byref(prm)))
+        self.flux = flux
+
+    def info(self) -> dict:
+        inf = N.Info()
+        self._check(self._lib.wlseno_get_info(self._h, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in N.Info._fields_ if k != "reserved"}
+
+    def stencil(self):
+        inf = self.info()
+        rp = np.zeros(inf["n_cell"] + 1, dtype=np.int32)
+        col = np.zeros(inf["nnz"], dtype=np.int32)
+        self._check(self._lib.wlseno_get_stencil(self._h, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                 col.ctypes.data_as(C.POINTER(C.c_int32))))
+        return rp, col
+
+    # ------------------------------------------------------------ device
+    def _field(self, u):
+        import torch
+
+        if not (isinstance(u, torch.Tensor) and u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()):
+            raise TypeError("expected a contiguous float64 CUDA tensor")
+        if u.numel() != self.info()["n_vars"] * self.n_cell:
+            raise ValueError("field has the wrong number of entries")
+        return u
+
+    def reconstruct(self, u, coef=True, facevals=True, rank=True):
+        import torch
+
+        u = self._field(u)
+        inf = self.info()
+        V, nc = inf["n_vars"], inf["n_cell"]
+        out = {}
+        if coef:
+            out["coef"] = torch.empty((V, nc, inf["m"]), dtype=torch.float64, device=u.device)
+        if facevals:
+            out["fval"] = torch.empty((V, nc, inf["faces_per_cell"], inf["points_per_face"]),
+                                      dtype=torch.float64, device=u.device)
+        if rank:
+            out["rank"] = torch.empty((V, nc), dtype=torch.int32, device=u.device)
+        self._sync_stream()
+        self._check(self._lib.wlseno_reconstruct(self._h, _ptr(u), _ptr(out.get("coef")), _ptr(out.get("fval")),
+                                                 _ptr(out.get("rank"))))
+        return out
+
+    def rhs(self, u, out=None):
+        import torch
+
+        u = self._field(u)
+        if out is None:
+            out = torch.empty_like(u)
+        self._sync_stream()
+        self._check(self._lib.wlseno_rhs(self._h, _ptr(u), _ptr(out)))
+        return out
+
+    def step(self, u, dt, n_steps):
+        """Advance u in place by n_steps TVD RK3 steps of size dt."""
+        u = self._field(u)
+        self._sync_stream()
+        self._check(self._lib.wlseno_step(self._h, _ptr(u), float(dt), int(n_steps)))
+        return u
+
+    def last_alpha(self) -> float:
+        a = C.c_double(0.0)
+        self._sync_stream()
+        self._check(self._lib.wlseno_last_alpha(self._h, C.byref(a)))
+        return a.value
+
+    # ---------------------------------------------------------- profiling
+    def profile(self, on: bool):
+        self._sync_stream()
+        self._check(self._lib.wlseno_profile(self._h, 1 if on else 0))
+
+    def profile_read(self, kernel: int):
+        """(total ms, launches) of kernel 0 (reconstruction) or 1 (flux/update)."""
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        self._check(self._lib.wlseno_profile_read(self._h, int(kernel), C.byref(ms), C.byref(n)))
+        return ms.value, n.value

@@ -1,0 +1,210 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Every comparison is element by element on the same seeded inputs, with the
+tolerance rule of tests/parity.py (1e-12 relative, floored at 1e-2 of the
+field's magnitude).  Stencils are integers and must be identical.
+"""
+
+import numpy as np
+import pytest
+
+from parity import (assert_parity, assert_poly_parity, cell_conditions, cell_noise, flux_scale, floor_tol,
+                    neighbourhood_max)
+from workloads import configs, periodic_line, uniform_periodic_line, jittered_square, fields
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _gpu(mesh, **kw):
+    from paper_1602_02694_amd import WLSENO
+
+    w = WLSENO(device=0)
+    w.mesh_upload(mesh.dim, mesh.verts, mesh.cells, mesh.periodic)
+    w.stencil_build(**kw)
+    return w
+
+
+def _oracle(mesh, **kw):
+    import oracle
+
+    kw = dict(kw)
+    kw.pop("rank_tol", None)
+    return oracle.Oracle(mesh.dim, mesh.verts, mesh.cells, mesh.periodic, **kw)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _compare_all(mesh, u0, steps, dt, name, **kw):
+    torch = _torch()
+    _say(f"[case] {name}: n_cell={mesh.n_cell} kw={kw}")
+    w = _gpu(mesh, **kw)
+    o = _oracle(mesh, **kw)
+    ox = _oracle(mesh, extended=True, stencil=(o.row_ptr, o.col), **kw)
+    rp, col = w.stencil()
+    assert np.array_equal(rp, o.row_ptr) and np.array_equal(col, o.col), "stencils differ"
+    kappa = cell_conditions(o, u0)                       # (V, nc)
+    kappa_nb = neighbourhood_max(o, kappa)
+    u = torch.tensor(np.asarray(u0, dtype=np.float64).reshape(-1), device="cuda")
+    rec = w.reconstruct(u)
+    torch.cuda.synchronize()
+    ref = o.reconstruct(u0)
+    refx = ox.reconstruct(u0)
+    assert np.array_equal(rec["rank"].cpu().numpy(), ref["rank"]), "numerical ranks differ"
+    fv_floor = floor_tol(kappa[:, :, None, None], cell_noise(ref["fval"], refx["fval"], cell_axes=2))
+    assert_parity(rec["fval"].cpu().numpy(), ref["fval"], f"{name} facet values", tol_floor=fv_floor)
+    # Taylor coefficients, compared through the polynomials they define on each cell
+    assert_poly_parity(rec["coef"].cpu().numpy(), ref["coef"], o, u0, f"{name} polynomials",
+                       xcoef=refx["coef"], tol_floor=floor_tol(kappa))
+    L = w.rhs(u)
+    torch.cuda.synchronize()
+    Lo, alpha_o = o.rhs(u0)
+    Lx, _ = ox.rhs(u0)
+    S = flux_scale(o, ref["fval"])
+    assert_parity(L.cpu().numpy(), Lo.reshape(-1), f"{name} rhs", scale=S,
+                  tol_floor=floor_tol(kappa_nb.reshape(-1), cell_noise(Lo.reshape(-1), Lx.reshape(-1), scale=S)))
+    if kw.get("flux") == "burgers":
+        assert w.last_alpha() == pytest.approx(alpha_o, rel=1e-13)
+    if steps:
+        w.step(u, dt, steps)
+        torch.cuda.synchronize()
+        uo = o.step(u0, dt, steps).reshape(-1)
+        ux = ox.step(u0, dt, steps).reshape(-1)
+        assert_parity(u.cpu().numpy(), uo, f"{name} {steps} steps",
+                      tol_floor=floor_tol(kappa_nb.reshape(-1), cell_noise(uo, ux)))
+    return w, o
+
+
+def test_line_advection_200():
+    """1-D periodic, jittered widths, p=3, 5-cell stencils, sine + square wave (full size)."""
+    wl = configs.line_advection()
+    s = wl.settings
+    dt = 0.5 * np.min(np.diff(wl.mesh.verts[:, 0]))
+    _compare_all(wl.mesh, wl.u0, s["steps"], dt, "line200", p=3, n_lo=5, n_hi=5, flux="advection",
+                 velocity=(1.0, 0, 0))
+
+
+def test_line_p5_seven_cells_and_burgers():
+    mesh = periodic_line(97, 0.1, 77)
+    u0 = fields.line_cell_averages(mesh, lambda x: 0.3 * x - 0.7 * np.cos(2 * np.pi * x) / (2 * np.pi))
+    dt = 0.3 * np.min(np.diff(mesh.verts[:, 0]))
+    _compare_all(mesh, u0, 20, dt, "line97-p5-burgers", p=5, n_lo=7, n_hi=7, flux="burgers")
+
+
+def test_square_small_advection_ragged():
+    """2-D p=3 on a small mesh whose cell count is not a multiple of the block size."""
+    mesh = jittered_square(13, 0.3, 91)
+    u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+    assert mesh.n_cell % 64 != 0
+    _compare_all(mesh, u0, 10, 0.002, "square13-adv", p=3, n_lo=12, n_hi=20, flux="advection",
+                 velocity=(1.0, 0.5, 0))
+
+
+def test_square_unit_weights():
+    mesh = jittered_square(11, 0.3, 92)
+    u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+    _compare_all(mesh, u0, 5, 0.002, "square11-ls", p=3, n_lo=12, n_hi=20, flux="burgers", weight_mode=1)
+
+
+def test_square_p4():
+    mesh = jittered_square(14, 0.3, 93)
+    u0 = fields.cell_averages(mesh, lambda x: np.sin(3 * x[:, 0]) * np.cos(2 * x[:, 1]) + (x[:, 0] > 0.5))
+    _compare_all(mesh, u0, 5, 0.002, "square14-p4", p=4, n_lo=20, n_hi=36, flux="burgers")
+
+
+def test_square_p2():
+    mesh = jittered_square(12, 0.3, 94)
+    u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+    _compare_all(mesh, u0, 5, 0.002, "square12-p2", p=2, n_lo=3, n_hi=6, flux="advection",
+                 velocity=(0.3, -1.0, 0))
+
+
+def test_tiny_mesh_whole_domain_stencils():
+    """Edge case: 8 triangles; every stencil is the whole mesh."""
+    mesh = jittered_square(3, 0.0, 1)
+    u0 = np.arange(mesh.n_cell, dtype=np.float64) * 0.1
+    _compare_all(mesh, u0, 3, 0.01, "square3", p=3, n_lo=12, n_hi=20, flux="burgers")
+
+
+def test_polynomial_reproduction_gpu():
+    """Degree-2 data are reconstructed exactly by the GPU path too."""
+    torch = _torch()
+    mesh = jittered_square(17, 0.3, 95)
+    fn = fields.polynomial_field(5, 2, 2)
+    w = _gpu(mesh, p=3, n_lo=12, n_hi=20)
+    o = _oracle(mesh, p=3, n_lo=12, n_hi=20)
+    u = torch.tensor(fields.cell_averages(mesh, fn), device="cuda")
+    fv = w.reconstruct(u)["fval"][0].cpu().numpy()
+    exact = fn(o.mesh.qx.reshape(-1, 2)).reshape(fv.shape)
+    assert np.max(np.abs(fv - exact)) < 1e-10 * np.max(np.abs(exact))
+
+
+def test_conservation_and_determinism_gpu():
+    torch = _torch()
+    wl = configs.square_burgers(40, 2001)
+    w = _gpu(wl.mesh, p=3, n_lo=12, n_hi=20, flux="burgers")
+    o = _oracle(wl.mesh, p=3, n_lo=12, n_hi=20, flux="burgers")
+    u = torch.tensor(wl.u0, device="cuda")
+    L1 = w.rhs(u).cpu().numpy()
+    L2 = w.rhs(u).cpu().numpy()
+    assert np.array_equal(L1, L2), "rhs not bitwise reproducible"
+    fv = w.reconstruct(u)["fval"][0].cpu().numpy()
+    bnd = 0.0
+    for i in range(o.nc):
+        for lf in range(3):
+            if o.mesh.nbr[i, lf] < 0:
+                sn = o.mesh.normal[i, lf].sum()
+                bnd += o.mesh.area[i, lf] * np.dot(o.mesh.qw, 0.5 * fv[i, lf] ** 2 * sn)
+    total = np.dot(o.mesh.vol, L1)
+    assert abs(total + bnd) < 1e-12 * np.sum(np.abs(o.mesh.vol * L1))
+    # stepping twice from the same state gives identical bits
+    a = u.clone()
+    b = u.clone()
+    w.step(a, 1e-3, 3)
+    w.step(b, 1e-3, 3)
+    assert torch.equal(a, b)
+
+
+def test_square_burgers_full_size():
+    """The benchmark workload: ~19.6k triangles, p=3, Burgers, 12-20 cell stencils.
+    One rhs, the reconstruction, and 10 RK3 steps against the oracle."""
+    wl = configs.square_burgers()
+    s = wl.settings
+    u0 = wl.u0
+    from paper_1602_02694_amd import WLSENO
+
+    w = WLSENO(device=-1)
+    w.mesh_upload(2, wl.mesh.verts, wl.mesh.cells)
+    w.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers")
+    dt = 0.5 * w.info()["min_insphere"] / (np.sqrt(2.0) * np.max(np.abs(u0)))
+    _compare_all(wl.mesh, u0, 10, dt, "square100-burgers", p=3, n_lo=12, n_hi=20, flux="burgers")
+
+
+def test_errors_on_device_context():
+    torch = _torch()
+    from paper_1602_02694_amd import WLSENO, WLSENOError
+
+    w = WLSENO(device=0)
+    u = torch.zeros(10, dtype=torch.float64, device="cuda")
+    with pytest.raises(WLSENOError) as e:
+        w._check(w._lib.wlseno_rhs(w._h, u.data_ptr(), u.data_ptr() + 40))
+    assert e.value.status == 4           # before stencil_build
+    mesh = jittered_square(6, 0.3, 3)
+    w.mesh_upload(2, mesh.verts, mesh.cells)
+    w.stencil_build(p=3, n_lo=12, n_hi=20)
+    v = torch.zeros(mesh.n_cell, dtype=torch.float64, device="cuda")
+    with pytest.raises(WLSENOError) as e:
+        w._check(w._lib.wlseno_rhs(w._h, v.data_ptr(), v.data_ptr()))
+    assert e.value.status == 1           # aliasing
+    with pytest.raises(WLSENOError) as e:
+        w._check(w._lib.wlseno_step(w._h, v.data_ptr(), float("nan"), 1))
+    assert e.value.status == 1

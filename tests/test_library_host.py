@@ -1,0 +1,139 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* the shared library loads and exports every function include/wlseno.h declares;
+* a host-only context (device -1) builds stencils that equal the oracle's
+  independent builder exactly (sets and row order; integer results);
+* error paths return the documented status codes.
+"""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from workloads import periodic_line, jittered_square, jittered_cube, configs
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1602_02694_amd as P
+
+    if not os.path.exists(P.LIB_PATH):
+        from paper_1602_02694_amd import build
+
+        build.build()
+    from paper_1602_02694_amd import _native
+
+    return _native.load()
+
+
+def test_exports_match_header(lib):
+    hdr = open(os.path.join(ROOT, "include", "wlseno.h")).read()
+    declared = set(re.findall(r"\b(wlseno_[a-z_]+)\s*\(", hdr))
+    from paper_1602_02694_amd import _native
+
+    assert declared == set(_native.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _host_ctx(mesh, **kw):
+    from paper_1602_02694_amd import WLSENO
+
+    w = WLSENO(device=-1)
+    w.mesh_upload(mesh.dim, mesh.verts, mesh.cells, mesh.periodic)
+    w.stencil_build(**kw)
+    return w
+
+
+@pytest.mark.parametrize("case", ["line", "square", "square_p4", "cube"])
+def test_stencils_equal_oracle(lib, case):
+    from oracle.mesh import OracleMesh
+
+    if case == "line":
+        mesh, kw = periodic_line(60, 0.1, 1001), dict(p=3, n_lo=5, n_hi=5)
+    elif case == "square":
+        mesh, kw = jittered_square(24, 0.3, 2001), dict(p=3, n_lo=12, n_hi=20)
+    elif case == "square_p4":
+        mesh, kw = jittered_square(16, 0.3, 3001), dict(p=4, n_lo=20, n_hi=36)
+    else:
+        mesh, kw = jittered_cube(6, 0.15, 4001), dict(p=3, n_lo=30, n_hi=50)
+    w = _host_ctx(mesh, **kw)
+    rp, col = w.stencil()
+    om = OracleMesh(mesh.dim, mesh.verts, mesh.cells, mesh.periodic, p=kw["p"])
+    orp, ocol = om.stencils(kw["n_lo"], kw["n_hi"])
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(col, ocol)
+    inf = w.info()
+    assert inf["h"] == pytest.approx(om.h, rel=1e-13)
+    assert inf["min_stencil"] >= min(kw["n_lo"], inf["m"])
+    assert inf["max_stencil"] <= kw["n_hi"]
+
+
+def test_info_sizes(lib):
+    w = _host_ctx(jittered_square(10, 0.3, 5), p=3, n_lo=12, n_hi=20)
+    inf = w.info()
+    assert (inf["dim"], inf["m"], inf["faces_per_cell"], inf["points_per_face"], inf["n_vars"]) == (2, 6, 3, 2, 1)
+    w = _host_ctx(periodic_line(30, 0.1, 5), p=5, n_lo=7, n_hi=7)
+    inf = w.info()
+    assert (inf["dim"], inf["m"], inf["faces_per_cell"], inf["points_per_face"]) == (1, 5, 2, 1)
+    assert inf["min_insphere"] == pytest.approx(np.min(np.diff(periodic_line(30, 0.1, 5).verts[:, 0])))
+
+
+def test_error_paths(lib):
+    from paper_1602_02694_amd import WLSENO, WLSENOError
+
+    mesh = jittered_square(6, 0.3, 9)
+    # inverted cell
+    bad = mesh.cells.copy()
+    bad[3, [0, 1]] = bad[3, [1, 0]]
+    w = WLSENO(device=-1)
+    with pytest.raises(WLSENOError) as e:
+        w.mesh_upload(2, mesh.verts, bad)
+    assert e.value.status == 1 and "cell 3" in str(e.value)
+    # vertex id out of range
+    bad = mesh.cells.copy()
+    bad[0, 0] = 10 ** 6
+    with pytest.raises(WLSENOError) as e:
+        w.mesh_upload(2, mesh.verts, bad)
+    assert e.value.status == 1
+    # periodic flag outside 1-D
+    with pytest.raises(WLSENOError):
+        w.mesh_upload(2, mesh.verts, mesh.cells, periodic=True)
+    # stencil before mesh / reversed size rule / too few coefficients
+    w2 = WLSENO(device=-1)
+    with pytest.raises(WLSENOError) as e:
+        w2.stencil_build()
+    assert e.value.status == 4
+    w.mesh_upload(2, mesh.verts, mesh.cells)
+    with pytest.raises(WLSENOError):
+        w.stencil_build(p=3, n_lo=20, n_hi=12)
+    with pytest.raises(WLSENOError):
+        w.stencil_build(p=3, n_lo=4, n_hi=5)        # n_hi < m = 6
+    # a 2-cell mesh cannot hold a 6-coefficient stencil
+    w3 = WLSENO(device=-1)
+    w3.mesh_upload(2, np.array([[0, 0], [1, 0], [0, 1], [1, 1.0]]), np.array([[0, 1, 2], [1, 3, 2]]))
+    with pytest.raises(WLSENOError) as e:
+        w3.stencil_build(p=3, n_lo=6, n_hi=10)
+    assert e.value.status == 1 and "fewer than" in str(e.value)
+    # device call on a host-only context
+    w.stencil_build(p=3, n_lo=12, n_hi=20)
+    rc = lib.wlseno_rhs(w._h, C.c_void_p(16), C.c_void_p(32))
+    assert rc == 4
+    # facet shared by three triangles
+    v = np.array([[0, 0], [1, 0], [0.5, 1], [0.5, -1], [0.6, 0.9]], dtype=float)
+    cells = np.array([[0, 1, 2], [1, 0, 3], [0, 1, 4]])
+    with pytest.raises(WLSENOError) as e:
+        w.mesh_upload(2, v, cells)
+    assert "more than two" in str(e.value)
+
+
+def test_null_context_and_create_errors(lib):
+    assert lib.wlseno_rhs(None, None, None) == 1
+    h = C.c_void_p()
+    assert lib.wlseno_create(-5, C.byref(h)) == 1
+    assert b"device" in lib.wlseno_last_error(None)
+    assert lib.wlseno_destroy(None) == 0
