@@ -72,13 +72,15 @@ enum {
 /* Method parameters.  wlseno_params_default() fills the readings used
  * throughout: eps = 1e-2 and alpha_w = 1.5 (the example values of Sec. 3.1.2),
  * rank_tol = 1e-12 relative to |R_11| (Sec. 3.3.2 leaves it open), unit
- * weights off. */
+ * weights off, automatic lane count. */
 typedef struct {
     int32_t p;           /* order: reconstruct polynomials of degree p-1 (1-D: 2..5, 2-D: 2..4, 3-D: 2..3) */
     int32_t n_lo, n_hi;  /* stencil size rule: grow rings until >= n_lo cells, keep the n_hi nearest */
     int32_t flux;        /* WLSENO_FLUX_* */
     int32_t weight_mode; /* 0: WLS-ENO weights (eq. weight); 1: unit weights (plain least squares) */
-    int32_t reserved;
+    int32_t lanes;       /* lanes per cell in the reconstruction kernel: 0 = automatic (4), 4 or 8
+                            (8 is compiled for 2-D p = 3 only; other variants use 4).  Results
+                            agree to rounding either way. */
     double eps;          /* epsilon in beta_j = (u_j - u_i)^2 + eps h^2 */
     double alpha_w;      /* centre weight factor alpha > 1 in eq. (weight) */
     double rank_tol;     /* numerical rank: |R_kk| > rank_tol |R_11| */

@@ -121,8 +121,12 @@ void upload_build(wlseno_ctx *c)
     dm.gs = b.gs;
     dm.flux = b.prm.flux;
     dm.weight_mode = b.prm.weight_mode;
+    dm.lanes = b.prm.lanes;
     dm.max_stencil = b.max_stencil;
     dm.nc = m.nc;
+    dm.nbuckets = b.nbuckets;
+    for (int t = 0; t < kMaxBuckets; ++t) dm.bucket_rpl[t] = b.bucket_rpl[t];
+    for (int t = 0; t <= kMaxBuckets; ++t) dm.bucket_cell0[t] = b.bucket_cell0[t];
     dm.eh2 = b.prm.eps * m.h * m.h;
     dm.alpha_w = b.prm.alpha_w;
     dm.rank_tol = b.prm.rank_tol;
@@ -136,6 +140,8 @@ void upload_build(wlseno_ctx *c)
     dm.rvol = upload(c, b.rvol);
     dm.sptr = upload(c, b.sptr);
     dm.scol = upload(c, b.scol);
+    dm.spad = upload(c, b.spad);
+    for (int t = 0; t <= kMaxBuckets; ++t) dm.spad_off[t] = b.spad_off[t];
     dm.sib = upload(c, b.dsib);
     dm.qperm = upload(c, b.qperm);
     dm.perm = upload(c, b.perm);

@@ -17,6 +17,12 @@ struct Error {
 
 // Number of Taylor coefficients C(p-1+dim, dim).
 int num_coeffs(int dim, int p);
+
+// Stencil-size buckets of the reconstruction kernel: each bucket runs a
+// variant holding `rpl` stencil rows per lane (4 lanes per cell).
+constexpr int kMaxBuckets = 3;
+// Ascending rows-per-lane variants compiled for (dim, p); empty if none.
+std::vector<int> rpl_variants(int dim, int p);
 // Facet quadrature points per facet (1-D: 1; 2-D: ceil(p/2); 3-D: 3).
 int points_per_face(int dim, int p);
 
@@ -48,14 +54,25 @@ struct Build {
     std::vector<int32_t> row_ptr, col;
     // perm[d] = user id of device cell d; iperm[u] = device id of user cell u
     std::vector<int32_t> perm, iperm;
+    // stencil-size buckets: device cells [bucket_cell0[b], bucket_cell0[b+1])
+    // use bucket_rpl[b] rows per lane (nbuckets <= kMaxBuckets; 0 = unsupported)
+    int nbuckets = 0;
+    int bucket_rpl[kMaxBuckets] = {0, 0, 0};
+    int64_t bucket_cell0[kMaxBuckets + 1] = {0, 0, 0, 0};
     // device order records
     std::vector<double> geo;        // nc*gs: centroid, then moments nu(alpha)=mu(alpha)/alpha! for 2 <= |alpha| <= p-1
     std::vector<double> vrel;       // nc*(dim+1)*dim vertex offsets from the centroid
     std::vector<int32_t> sptr, scol;    // device-order CSR, device ids, centre first
-    std::vector<int32_t> dsib;      // nc*F: (device cell << 2 | lf) or -1
-    std::vector<int32_t> qperm;     // nc*F: 2 bits per point q: sibling's point index of own point q
-    std::vector<double> normal;     // nc*F*dim unit outward normals; sibling = exact negation
-    std::vector<double> area;       // nc*F facet measures (identical on both sides)
+    // padded stencil table for the reconstruction kernel: cells of bucket b
+    // hold 4*bucket_rpl[b] entries each (device ids, centre first, -1 padding)
+    // starting at spad_off[b]
+    std::vector<int32_t> spad;
+    int64_t spad_off[kMaxBuckets + 1] = {0, 0, 0, 0};
+    // facet arrays are facet-major: [F][nc] (normals [F][nc][dim])
+    std::vector<int32_t> dsib;      // [F][nc]: (device cell << 2 | lf) or -1
+    std::vector<int32_t> qperm;     // [F][nc]: 2 bits per point q: sibling's point index of own point q
+    std::vector<double> normal;     // [F][nc][dim] unit outward normals; sibling = exact negation
+    std::vector<double> area;       // [F][nc] facet measures (identical on both sides)
     std::vector<double> rvol;       // nc: 1/|tau|
 };
 
@@ -67,12 +84,18 @@ void build_setup(const HostMesh &mesh, const wlseno_params &prm, Build &b);
 struct DevMesh {
     int dim = 0, p = 0, m = 0, nq = 0, nf = 0, nvars = 1, gs = 0;
     int flux = 0, weight_mode = 0, max_stencil = 0;
+    int lanes = 0;   // lanes per cell in the reconstruction: 0 = automatic, 4 or 8
     int64_t nc = 0;
+    int nbuckets = 0;
+    int bucket_rpl[kMaxBuckets] = {0, 0, 0};
+    int64_t bucket_cell0[kMaxBuckets + 1] = {0, 0, 0, 0};
     double eh2 = 0.0, alpha_w = 1.5, rank_tol = 1e-12, period = 0.0, gamma = 1.4;
     double vel[3] = {0, 0, 0};
     const double *geo = nullptr, *vrel = nullptr, *normal = nullptr, *area = nullptr, *rvol = nullptr;
     const int32_t *sptr = nullptr, *scol = nullptr, *sib = nullptr, *qperm = nullptr, *perm = nullptr;
-    double *fv = nullptr;                  // nvars*nc*F*Q, device order, cell-major
+    const int32_t *spad = nullptr;
+    int64_t spad_off[kMaxBuckets + 1] = {0, 0, 0, 0};
+    double *fv = nullptr;                  // [nvars][F][nc][Q], device order
     unsigned long long *alpha = nullptr;   // 2 parities x 64 slots of max bits
 };
 

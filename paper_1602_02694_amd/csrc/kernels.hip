@@ -23,6 +23,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -108,6 +109,30 @@ __device__ __forceinline__ double quad_bcast(double x, int l)
     }
 }
 
+// Sum over a group of G = 4 or 8 lanes.  For G = 8 the two quad totals are
+// exchanged with row_half_mirror (lane i <-> 7-i), so every lane adds the
+// same two operands and all eight hold identical bits.
+template <int G>
+__device__ __forceinline__ double group_sum(double x)
+{
+    x = quad_sum(x);
+    if constexpr (G == 8) x = x + dpp_d<0x141>(x);
+    return x;
+}
+
+// Value of lane l (constant after unrolling) of the group, for lane g.
+template <int G>
+__device__ __forceinline__ double group_bcast(double x, int l, int g)
+{
+    const double t = quad_bcast(x, l & 3);
+    if constexpr (G == 4) {
+        return t;
+    } else {
+        const double o = dpp_d<0x141>(t);
+        return ((g >> 2) == (l >> 2)) ? t : o;
+    }
+}
+
 // pw[d][a] = x_d^a / a!
 template <int DIM, int P>
 __device__ __forceinline__ void scaled_powers(const double (&x)[DIM], double (&pw)[DIM][P])
@@ -164,18 +189,56 @@ __device__ __forceinline__ double quad_weight(int q)
 struct RArgs {
     int64_t nc;
     const double *u, *geo, *vrel, *normal;
-    const int32_t *sptr, *scol, *sib, *perm;
+    const int32_t *spad, *sib, *perm;
     double *fv;
     double *coef_user, *fv_user;
     int32_t *rank_user;
     unsigned long long *alpha_acc;   // 64 slots (stride 16) of this stage's parity
     double eh2, alpha_w, rank_tol, period;
     int weight_mode;
+    // stencil-size buckets: cells [cell0[b], cell0[b+1]) run with rpl[b] rows
+    // per lane, in workgroups [blk0[b], blk0[b+1])
+    int64_t cell0[kMaxBuckets + 1];
+    int blk0[kMaxBuckets + 1];
+    int64_t spad_off[kMaxBuckets + 1];   // padded stencil table of bucket b
+    int stride[kMaxBuckets];             // its entries per cell
 };
 
+// 1/x to ~1 ulp: hardware estimate and two Newton steps (x finite, nonzero).
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// 1/sqrt(x) to ~1 ulp (x > 0): hardware estimate and two Newton steps.
+__device__ __forceinline__ double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    return fma(y, e, y);
+}
+
+// Workgroups are handed to the 8 XCDs round robin; renumber them so that each
+// XCD works on one contiguous range of cells and stencil neighbours share its L2.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int xcd = b & 7, idx = b >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
 // --------------------------------------------------------------- K1
-template <int DIM, int P, int RPL, int FLUX>
-__global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
+// Reconstruction of one cell by the 4 lanes of a quad (g = lane in the quad).
+template <int DIM, int P, int G, int RPL, int FLUX>
+__device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, int64_t cell_begin, int64_t cell_end,
+                                                 const int32_t *spad, int stride, int g, double *lds, int slot)
 {
     constexpr Basis<DIM, P> B{};
     constexpr int M = Basis<DIM, P>::M;
@@ -183,28 +246,22 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
     constexpr int Q = num_q<DIM, P>();
     constexpr int NMOM = M - 1 - DIM;
     constexpr int GS = geo_stride<DIM, P>();
-    constexpr int G = 4;
     constexpr int RS = (M + G - 1) / G;
 
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t cell = gid >> 2;
-    const int g = (int)(threadIdx.x & 3);
-    const bool live = cell < a.nc;
-    const int64_t c = live ? cell : a.nc - 1;
+    const bool live = cell < cell_end;
+    const int64_t c = live ? cell : cell_end - 1;
+    const int32_t *srow = spad + (c - cell_begin) * stride;
 
     const double *gc = a.geo + c * GS;
     double xc[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) xc[d] = gc[d];
     const double uc = a.u[c];
-    const int32_t base = a.sptr[c];
-    const int n = a.sptr[c + 1] - base;
-
     // indicator of the centre: smallest over its facet neighbours
     double bmin = -1.0;
 #pragma unroll
     for (int lf = 0; lf < F; ++lf) {
-        const int32_t s = a.sib[c * F + lf];
+        const int32_t s = a.sib[lf * a.nc + c];
         if (s >= 0) {
             const double du = a.u[s >> 2] - uc;
             const double bt = du * du + a.eh2;
@@ -218,8 +275,9 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         const int r = s * G + g;
-        const bool valid = live && r < n;
-        const int32_t j = valid ? a.scol[base + r] : (int32_t)c;
+        const int32_t jj = (live && r < stride) ? srow[r] : -1;
+        const bool valid = jj >= 0;
+        const int32_t j = valid ? jj : (int32_t)c;
         const double *gj = a.geo + (int64_t)j * GS;
         double dl[DIM];
 #pragma unroll
@@ -258,7 +316,7 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
             const double du = uj - uc;
             const double num = (r == 0) ? a.alpha_w : 1.0;
             const double den = (r == 0) ? bmin : du * du + a.eh2;
-            w = num / den;
+            w = num * rcp_nr(den);
         }
         w = valid ? w : 0.0;
 #pragma unroll
@@ -273,9 +331,8 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
         double t = 0.0;
 #pragma unroll
         for (int s = 0; s < RPL; ++s) t = fma(A[s][k], A[s][k], t);
-        t = quad_sum(t);
-        const double nr = sqrt(t);
-        sc[k] = nr > 0.0 ? 1.0 / nr : 0.0;
+        t = group_sum<G>(t);
+        sc[k] = t > 0.0 ? rsq_nr(t) : 0.0;
 #pragma unroll
         for (int s = 0; s < RPL; ++s) A[s][k] *= sc[k];
     }
@@ -296,53 +353,68 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
     }
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        double eta[M];
-#pragma unroll
-        for (int cc = k; cc < M; ++cc) {
+        double best;
+        if (k == 0) {
+            // After the scaling every nonzero column has unit norm and column 0
+            // (the weights themselves) is never zero, so under the tie rule the
+            // first pivot is always column 0: no search, no exchange.
             double t = 0.0;
 #pragma unroll
-            for (int s = 0; s < RPL; ++s) t = fma(A[s][cc], A[s][cc], t);
-            eta[cc] = quad_sum(t);
-        }
-        // pivot: lowest column index among those within a relative kPivotTie
-        // of the largest partial norm (rounding must not order unit-norm ties)
-        double best = eta[k];
+            for (int s = 0; s < RPL; ++s) t = fma(A[s][0], A[s][0], t);
+            best = group_sum<G>(t);
+        } else {
+            double eta[M];
 #pragma unroll
-        for (int cc = k + 1; cc < M; ++cc) best = fmax(best, eta[cc]);
-        const double tie = best * (1.0 - kPivotTie);
-        int piv = M - 1;
+            for (int cc = k; cc < M; ++cc) {
+                double t = 0.0;
 #pragma unroll
-        for (int cc = M - 1; cc >= k; --cc) piv = eta[cc] >= tie ? cc : piv;
-#pragma unroll
-        for (int cc = k + 1; cc < M; ++cc) {
-            const bool sw = piv == cc;
-#pragma unroll
-            for (int s = 0; s < RPL; ++s) {
-                const double t0 = A[s][k], t1 = A[s][cc];
-                A[s][k] = sw ? t1 : t0;
-                A[s][cc] = sw ? t0 : t1;
+                for (int s = 0; s < RPL; ++s) t = fma(A[s][cc], A[s][cc], t);
+                eta[cc] = group_sum<G>(t);
             }
-            // a pivot exchanges whole columns: the R entries of retired rows too
+            // pivot: lowest column index among those within a relative kPivotTie
+            // of the largest partial norm (rounding must not order ties)
+            best = eta[k];
 #pragma unroll
-            for (int s = 0; s < RS; ++s) {
-                if (s * G < k) {
-                    const double t0 = Rs[s][k], t1 = Rs[s][cc];
-                    Rs[s][k] = sw ? t1 : t0;
-                    Rs[s][cc] = sw ? t0 : t1;
+            for (int cc = k + 1; cc < M; ++cc) best = fmax(best, eta[cc]);
+            const double tie = best * (1.0 - kPivotTie);
+            int piv = M - 1;
+#pragma unroll
+            for (int cc = M - 1; cc >= k; --cc) piv = eta[cc] >= tie ? cc : piv;
+            best = eta[k];
+#pragma unroll
+            for (int cc = k + 1; cc < M; ++cc) best = piv == cc ? eta[cc] : best;
+#pragma unroll
+            for (int cc = k + 1; cc < M; ++cc) {
+                const bool sw = piv == cc;
+#pragma unroll
+                for (int s = 0; s < RPL; ++s) {
+                    const double t0 = A[s][k], t1 = A[s][cc];
+                    A[s][k] = sw ? t1 : t0;
+                    A[s][cc] = sw ? t0 : t1;
                 }
+                // a pivot exchanges whole columns: the R entries of retired rows too
+#pragma unroll
+                for (int s = 0; s < RS; ++s) {
+                    if (s * G < k) {
+                        const double t0 = Rs[s][k], t1 = Rs[s][cc];
+                        Rs[s][k] = sw ? t1 : t0;
+                        Rs[s][cc] = sw ? t0 : t1;
+                    }
+                }
+                const double s0 = sc[k], s1 = sc[cc];
+                sc[k] = sw ? s1 : s0;
+                sc[cc] = sw ? s0 : s1;
+                const int p0 = pm[k], p1 = pm[cc];
+                pm[k] = sw ? p1 : p0;
+                pm[cc] = sw ? p0 : p1;
             }
-            const double s0 = sc[k], s1 = sc[cc];
-            sc[k] = sw ? s1 : s0;
-            sc[cc] = sw ? s0 : s1;
-            const int p0 = pm[k], p1 = pm[cc];
-            pm[k] = sw ? p1 : p0;
-            pm[cc] = sw ? p0 : p1;
         }
-        const double alpha = quad_bcast(A[k / G][k], k % G);
+        const double alpha = group_bcast<G>(A[k / G][k], k % G, g);
         const bool nz = best > 0.0;
         const double beta = nz ? -copysign(sqrt(best), alpha) : 0.0;
-        const double tau = nz ? (beta - alpha) / beta : 0.0;
-        const double scal = nz ? 1.0 / (alpha - beta) : 0.0;
+        const double rb = nz ? rcp_nr(beta) : 0.0;
+        const double tau = (beta - alpha) * rb;
+        const double scal = nz ? rcp_nr(alpha - beta) : 0.0;
         const bool own = g == (k % G);
         double v[RPL];
 #pragma unroll
@@ -353,7 +425,7 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
             double t = 0.0;
 #pragma unroll
             for (int s = 0; s < RPL; ++s) t = fma(v[s], A[s][cc], t);
-            const double tw = tau * quad_sum(t);
+            const double tw = tau * group_sum<G>(t);
 #pragma unroll
             for (int s = 0; s < RPL; ++s) A[s][cc] = fma(-tw, v[s], A[s][cc]);
         }
@@ -361,7 +433,7 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
             double t = 0.0;
 #pragma unroll
             for (int s = 0; s < RPL; ++s) t = fma(v[s], bv[s], t);
-            const double tw = tau * quad_sum(t);
+            const double tw = tau * group_sum<G>(t);
 #pragma unroll
             for (int s = 0; s < RPL; ++s) bv[s] = fma(-tw, v[s], bv[s]);
         }
@@ -391,19 +463,19 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
         double acc = cs[k / G];
 #pragma unroll
         for (int j = k + 1; j < M; ++j) acc = fma(-Rs[k / G][j], y[j], acc);
-        const double yk = quad_bcast(acc / Rs[k / G][k], k % G);
+        const double yk = group_bcast<G>(acc * rcp_nr(Rs[k / G][k]), k % G, g);
         y[k] = (k < rank) ? yk : 0.0;
     }
-    // coefficients in the original basis order: v = S E y
+    // coefficients in the original basis order, v = S E y, through LDS: lane g
+    // stores the entries k = g, g+G, ... at their original positions
+    double *lc = lds + slot * M;
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+        if ((k % G) == g) lc[pm[k]] = sc[k] * y[k];
+    __syncthreads();
     double coef[M];
 #pragma unroll
-    for (int o = 0; o < M; ++o) coef[o] = 0.0;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        const double val = sc[k] * y[k];
-#pragma unroll
-        for (int o = 0; o < M; ++o) coef[o] = (pm[k] == o) ? val : coef[o];
-    }
+    for (int o = 0; o < M; ++o) coef[o] = lc[o];
 
     // evaluate at the facet points: lane g handles facet g
     const int lf = g < F ? g : 0;
@@ -428,14 +500,14 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
     const bool writer = live && g < F;
     if (writer) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) a.fv[(c * F + lf) * Q + q] = fq[q];
+        for (int q = 0; q < Q; ++q) a.fv[(lf * a.nc + c) * Q + q] = fq[q];
     }
     if (live && (a.coef_user || a.fv_user || a.rank_user)) {
         const int64_t uid = a.perm[c];
         if (a.coef_user) {
 #pragma unroll
             for (int o = 0; o < M; ++o)
-                if ((o & 3) == g) a.coef_user[uid * M + o] = coef[o];
+                if ((o % G) == g) a.coef_user[uid * M + o] = coef[o];
         }
         if (a.fv_user && g < F) {
 #pragma unroll
@@ -450,16 +522,40 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
         if (writer) {
             double sn = 0.0;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) sn += a.normal[(c * F + lf) * DIM + d];
+            for (int d = 0; d < DIM; ++d) sn += a.normal[(lf * a.nc + c) * DIM + d];
 #pragma unroll
             for (int q = 0; q < Q; ++q) am = fmax(am, fabs(fq[q] * sn));
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) am = fmax(am, __shfl_xor(am, o));
         if ((threadIdx.x & 63) == 0) {
-            const int slot = (int)((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % kAlphaSlots);
-            atomicMax(a.alpha_acc + slot * 16, (unsigned long long)__double_as_longlong(am));
+            const int sl = (int)((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % kAlphaSlots);
+            atomicMax(a.alpha_acc + sl * 16, (unsigned long long)__double_as_longlong(am));
         }
+    }
+}
+
+// One workgroup = 256/G cells of one stencil-size bucket, G lanes per cell.
+template <int DIM, int P, int FLUX, int G, int R0, int R1, int R2>
+__global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
+{
+    constexpr int CPB = 256 / G;   // cells per workgroup
+    __shared__ double lds[CPB * Basis<DIM, P>::M];
+    const int L = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int g = (int)(threadIdx.x % G);
+    const int slot = (int)(threadIdx.x / G);
+    if (L < a.blk0[1]) {
+        const int64_t cell = a.cell0[0] + (int64_t)(L - a.blk0[0]) * CPB + slot;
+        reconstruct_cell<DIM, P, G, R0, FLUX>(a, cell, a.cell0[0], a.cell0[1], a.spad + a.spad_off[0], a.stride[0], g,
+                                              lds, slot);
+    } else if (L < a.blk0[2]) {
+        const int64_t cell = a.cell0[1] + (int64_t)(L - a.blk0[1]) * CPB + slot;
+        reconstruct_cell<DIM, P, G, R1, FLUX>(a, cell, a.cell0[1], a.cell0[2], a.spad + a.spad_off[1], a.stride[1], g,
+                                              lds, slot);
+    } else {
+        const int64_t cell = a.cell0[2] + (int64_t)(L - a.blk0[2]) * CPB + slot;
+        reconstruct_cell<DIM, P, G, R2, FLUX>(a, cell, a.cell0[2], a.cell0[3], a.spad + a.spad_off[2], a.stride[2], g,
+                                              lds, slot);
     }
 }
 
@@ -513,11 +609,12 @@ __global__ void __launch_bounds__(256) k_update(UArgs a)
     double tot = 0.0;
 #pragma unroll
     for (int lf = 0; lf < F; ++lf) {
-        const int32_t s = a.sib[c * F + lf];
+        const int64_t N = a.nc;
+        const int32_t s = a.sib[lf * N + c];
         double n[DIM];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) n[d] = a.normal[(c * F + lf) * DIM + d];
-        const double *own = a.fv + (c * F + lf) * Q;
+        for (int d = 0; d < DIM; ++d) n[d] = a.normal[(lf * N + c) * DIM + d];
+        const double *own = a.fv + (lf * N + c) * Q;
         double facc = 0.0;
         if (s < 0) {
             // transmissive boundary: outside state equals inside state
@@ -526,9 +623,9 @@ __global__ void __launch_bounds__(256) k_update(UArgs a)
         } else {
             const int64_t j = s >> 2;
             const int l2 = s & 3;
-            const double *oth = a.fv + (j * F + l2) * Q;
+            const double *oth = a.fv + (l2 * N + j) * Q;
             const bool owner = c < j;
-            const int32_t qp = owner ? a.qperm[c * F + lf] : a.qperm[j * F + l2];
+            const int32_t qp = owner ? a.qperm[lf * N + c] : a.qperm[l2 * N + j];
             double nn[DIM];
 #pragma unroll
             for (int d = 0; d < DIM; ++d) nn[d] = owner ? n[d] : -n[d];
@@ -541,7 +638,7 @@ __global__ void __launch_bounds__(256) k_update(UArgs a)
             }
             facc = owner ? facc : -facc;
         }
-        tot += a.area[c * F + lf] * facc;
+        tot += a.area[lf * N + c] * facc;
     }
     const double L = -tot * a.rvol[c];
     double o;
@@ -575,14 +672,21 @@ __global__ void k_clear_alpha(unsigned long long *alpha)
 // ------------------------------------------------------------ dispatch
 inline int blocks_for(int64_t work, int per_block) { return (int)((work + per_block - 1) / per_block); }
 
-template <int DIM, int P, int RPL>
-int launch_k1(const DevMesh &dm, const RArgs &args, hipStream_t st)
+template <int DIM, int P, int G, int R0, int R1, int R2>
+int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
 {
-    const int nb = blocks_for(dm.nc * 4, 256);
+    // workgroup ranges of the buckets for 256/G cells per workgroup
+    int nb = 0;
+    for (int b = 0; b < kMaxBuckets; ++b) {
+        args.blk0[b] = nb;
+        nb += blocks_for(args.cell0[b + 1] - args.cell0[b], 256 / G);
+    }
+    args.blk0[kMaxBuckets] = nb;
+    if (nb == 0) return 0;
     if (dm.flux == kFluxBurgers)
-        hipLaunchKernelGGL((k_reconstruct<DIM, P, RPL, kFluxBurgers>), dim3(nb), dim3(256), 0, st, args);
+        hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
     else
-        hipLaunchKernelGGL((k_reconstruct<DIM, P, RPL, kFluxAdv>), dim3(nb), dim3(256), 0, st, args);
+        hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxAdv, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
     return (int)hipGetLastError();
 }
 
@@ -597,17 +701,24 @@ int launch_k23(const DevMesh &dm, const UArgs &args, hipStream_t st)
     return (int)hipGetLastError();
 }
 
-// rows per lane needed for the largest stencil
-inline int rpl_needed(const DevMesh &dm) { return (dm.max_stencil + 3) / 4; }
-
 }  // namespace
+
+std::vector<int> rpl_variants(int dim, int p)
+{
+    if (dim == 1 && p >= 2 && p <= 5) return {2};
+    if (dim == 2 && p == 2) return {2};
+    if (dim == 2 && p == 3) return {3, 4, 5};
+    if (dim == 2 && p == 4) return {5, 7, 9};
+    return {};
+}
 
 bool reconstruct_supported(const DevMesh &dm)
 {
-    const int r = rpl_needed(dm);
-    if (dm.dim == 1) return dm.p >= 2 && dm.p <= 5 && r <= 2;
-    if (dm.dim == 2) return (dm.p == 2 && r <= 2) || (dm.p == 3 && r <= 5) || (dm.p == 4 && r <= 9);
-    return false;
+    const std::vector<int> v = rpl_variants(dm.dim, dm.p);
+    if (v.empty() || dm.nbuckets != (int)v.size()) return false;
+    for (int b = 0; b < dm.nbuckets; ++b)
+        if (dm.bucket_rpl[b] != v[b]) return false;
+    return dm.max_stencil <= 4 * v.back();
 }
 
 int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *coef_user, double *fv_user,
@@ -619,8 +730,7 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     a.geo = dm.geo;
     a.vrel = dm.vrel;
     a.normal = dm.normal;
-    a.sptr = dm.sptr;
-    a.scol = dm.scol;
+    a.spad = dm.spad;
     a.sib = dm.sib;
     a.perm = dm.perm;
     a.fv = dm.fv;
@@ -633,19 +743,29 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     a.rank_tol = dm.rank_tol;
     a.period = dm.period;
     a.weight_mode = dm.weight_mode;
+    // bucket b covers the variant's b-th rows-per-lane value; unused buckets are empty
+    for (int b = 0; b <= kMaxBuckets; ++b) {
+        a.cell0[b] = dm.bucket_cell0[b < dm.nbuckets ? b : dm.nbuckets];
+        a.spad_off[b] = dm.spad_off[b];
+        if (b < kMaxBuckets) a.stride[b] = b < dm.nbuckets ? 4 * dm.bucket_rpl[b] : 0;
+    }
     hipStream_t st = (hipStream_t)stream;
-    const int r = rpl_needed(dm);
+    // 4 lanes per cell unless 8 are asked for (measured faster at every size)
+    const bool wide = dm.lanes == 8;
     if (dm.dim == 1) {
         switch (dm.p) {
-        case 2: return launch_k1<1, 2, 2>(dm, a, st);
-        case 3: return launch_k1<1, 3, 2>(dm, a, st);
-        case 4: return launch_k1<1, 4, 2>(dm, a, st);
-        case 5: return launch_k1<1, 5, 2>(dm, a, st);
+        case 2: return launch_k1<1, 2, 4, 2, 2, 2>(dm, a, st);
+        case 3: return launch_k1<1, 3, 4, 2, 2, 2>(dm, a, st);
+        case 4: return launch_k1<1, 4, 4, 2, 2, 2>(dm, a, st);
+        case 5: return launch_k1<1, 5, 4, 2, 2, 2>(dm, a, st);
         }
     } else if (dm.dim == 2) {
-        if (dm.p == 2 && r <= 2) return launch_k1<2, 2, 2>(dm, a, st);
-        if (dm.p == 3 && r <= 5) return launch_k1<2, 3, 5>(dm, a, st);
-        if (dm.p == 4 && r <= 9) return launch_k1<2, 4, 9>(dm, a, st);
+        if (dm.p == 2) return launch_k1<2, 2, 4, 2, 2, 2>(dm, a, st);
+        if (dm.p == 3) {
+            if (wide) return launch_k1<2, 3, 8, 2, 2, 3>(dm, a, st);
+            return launch_k1<2, 3, 4, 3, 4, 5>(dm, a, st);
+        }
+        if (dm.p == 4) return launch_k1<2, 4, 4, 5, 7, 9>(dm, a, st);
     }
     return (int)hipErrorInvalidValue;
 }

@@ -438,6 +438,7 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     if (prm.flux != WLSENO_FLUX_ADVECTION && prm.flux != WLSENO_FLUX_BURGERS)
         throw Error{WLSENO_EUNSUPPORTED, "flux must be advection or Burgers"};
     if (prm.weight_mode != 0 && prm.weight_mode != 1) throw inval("weight_mode must be 0 or 1");
+    if (prm.lanes != 0 && prm.lanes != 4 && prm.lanes != 8) throw inval("lanes must be 0, 4 or 8");
     if (!(prm.eps >= 0.0) || !(prm.alpha_w > 0.0) || !(prm.rank_tol >= 0.0))
         throw inval("eps >= 0, alpha_w > 0 and rank_tol >= 0 required");
     Build b;
@@ -485,8 +486,33 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
         b.max_stencil = std::max(b.max_stencil, cnt[i]);
     }
 
-    // renumbering
-    b.perm = rcm_order(m);
+    // renumbering: reverse Cuthill-McKee, then a stable partition into the
+    // reconstruction kernel's stencil-size buckets (rows per lane >= n/4)
+    std::vector<int32_t> rcm = rcm_order(m);
+    const std::vector<int> variants = rpl_variants(dim, prm.p);
+    if (variants.empty() || (int)variants.size() > kMaxBuckets) {
+        b.perm = std::move(rcm);
+        b.nbuckets = 0;
+        b.bucket_cell0[0] = 0;
+        for (int t = 1; t <= kMaxBuckets; ++t) b.bucket_cell0[t] = nc;
+    } else {
+        const int nbk = (int)variants.size();
+        auto bucket_of = [&](int64_t u) {
+            for (int t = 0; t < nbk; ++t)
+                if (4 * variants[t] >= cnt[u]) return t;
+            return nbk - 1;   // too large: reported as unsupported by the device upload
+        };
+        b.perm.clear();
+        b.perm.reserve(nc);
+        b.nbuckets = nbk;
+        for (int t = 0; t < nbk; ++t) {
+            b.bucket_rpl[t] = variants[t];
+            b.bucket_cell0[t] = (int64_t)b.perm.size();
+            for (int32_t u : rcm)
+                if (bucket_of(u) == t) b.perm.push_back(u);
+        }
+        for (int t = nbk; t <= kMaxBuckets; ++t) b.bucket_cell0[t] = nc;
+    }
     b.iperm.assign(nc, 0);
     for (int64_t d = 0; d < nc; ++d) b.iperm[b.perm[d]] = (int32_t)d;
 
@@ -497,6 +523,24 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     for (int64_t d = 0; d < nc; ++d) {
         int32_t u = b.perm[d];
         for (int32_t t = 0; t < cnt[u]; ++t) b.scol[b.sptr[d] + t] = b.iperm[b.col[b.row_ptr[u] + t]];
+    }
+    // padded per-bucket stencil table (no row-pointer load in the kernel)
+    {
+        int64_t off = 0;
+        for (int t = 0; t < kMaxBuckets; ++t) {
+            b.spad_off[t] = off;
+            if (t < b.nbuckets) off += (b.bucket_cell0[t + 1] - b.bucket_cell0[t]) * 4 * b.bucket_rpl[t];
+        }
+        b.spad_off[kMaxBuckets] = off;
+        b.spad.assign(off, -1);
+        for (int t = 0; t < b.nbuckets; ++t) {
+            const int stride = 4 * b.bucket_rpl[t];
+            for (int64_t d = b.bucket_cell0[t]; d < b.bucket_cell0[t + 1]; ++d) {
+                const int64_t base = b.spad_off[t] + (d - b.bucket_cell0[t]) * stride;
+                const int32_t n = b.sptr[d + 1] - b.sptr[d];
+                for (int32_t r = 0; r < n && r < stride; ++r) b.spad[base + r] = b.scol[b.sptr[d] + r];
+            }
+        }
     }
 
     // geometry records: centroid + moments nu(alpha) = mu(alpha)/alpha!, 2 <= |alpha| <= p-1
@@ -605,8 +649,8 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
             double n[3] = {0, 0, 0}, ar = 0.0;
             if (s < 0) {
                 own_normal(u, lf, n, &ar);
-                for (int k = 0; k < dim; ++k) b.normal[(d * F + lf) * dim + k] = n[k];
-                b.area[d * F + lf] = ar;
+                for (int k = 0; k < dim; ++k) b.normal[(lf * nc + d) * dim + k] = n[k];
+                b.area[lf * nc + d] = ar;
             } else {
                 int64_t u2 = s >> 2;
                 int lf2 = s & 3;
@@ -619,9 +663,9 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
                     own_normal(u2, lf2, n, &ar);
                     for (int k = 0; k < dim; ++k) n[k] = -n[k];
                 }
-                for (int k = 0; k < dim; ++k) b.normal[(d * F + lf) * dim + k] = n[k];
-                b.area[d * F + lf] = ar;
-                b.dsib[d * F + lf] = (int32_t)((d2 << 2) | lf2);
+                for (int k = 0; k < dim; ++k) b.normal[(lf * nc + d) * dim + k] = n[k];
+                b.area[lf * nc + d] = ar;
+                b.dsib[lf * nc + d] = (int32_t)((d2 << 2) | lf2);
                 // sibling point index of each own point
                 int32_t code = 0;
                 for (int q = 0; q < Q; ++q) {
@@ -635,9 +679,9 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
                     }
                     code |= q2 << (2 * q);
                 }
-                b.qperm[d * F + lf] = code;
+                b.qperm[lf * nc + d] = code;
             }
-            perim += b.area[d * F + lf];
+            perim += b.area[lf * nc + d];
         }
         double ins = dim == 1 ? m.vol[u] : 2.0 * dim * m.vol[u] / perim;
         min_ins = std::min(min_ins, ins);

@@ -71,12 +71,13 @@ class WLSENO:
         self.n_cell = int(c.shape[0])
 
     def stencil_build(self, p=3, n_lo=12, n_hi=20, flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2,
-                      alpha_w=1.5, rank_tol=1e-12, weight_mode=0, gamma=1.4):
+                      alpha_w=1.5, rank_tol=1e-12, weight_mode=0, gamma=1.4, lanes=0):
         prm = N.Params()
         self._lib.wlseno_params_default(C.byref(prm))
         prm.p, prm.n_lo, prm.n_hi = int(p), int(n_lo), int(n_hi)
         prm.flux = N.FLUX[flux] if isinstance(flux, str) else int(flux)
         prm.weight_mode = int(weight_mode)
+        prm.lanes = int(lanes)
         prm.eps, prm.alpha_w, prm.rank_tol, prm.gamma = float(eps), float(alpha_w), float(rank_tol), float(gamma)
         for d in range(3):
             prm.velocity[d] = float(velocity[d]) if d < len(velocity) else 0.0

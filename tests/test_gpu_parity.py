@@ -37,6 +37,7 @@ def _oracle(mesh, **kw):
 
     kw = dict(kw)
     kw.pop("rank_tol", None)
+    kw.pop("lanes", None)
     return oracle.Oracle(mesh.dim, mesh.verts, mesh.cells, mesh.periodic, **kw)
 
 
@@ -100,13 +101,14 @@ def test_line_p5_seven_cells_and_burgers():
     _compare_all(mesh, u0, 20, dt, "line97-p5-burgers", p=5, n_lo=7, n_hi=7, flux="burgers")
 
 
-def test_square_small_advection_ragged():
+@pytest.mark.parametrize("lanes", [4, 8])
+def test_square_small_advection_ragged(lanes):
     """2-D p=3 on a small mesh whose cell count is not a multiple of the block size."""
     mesh = jittered_square(13, 0.3, 91)
     u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
     assert mesh.n_cell % 64 != 0
-    _compare_all(mesh, u0, 10, 0.002, "square13-adv", p=3, n_lo=12, n_hi=20, flux="advection",
-                 velocity=(1.0, 0.5, 0))
+    _compare_all(mesh, u0, 10, 0.002, f"square13-adv-lanes{lanes}", p=3, n_lo=12, n_hi=20, flux="advection",
+                 velocity=(1.0, 0.5, 0), lanes=lanes)
 
 
 def test_square_unit_weights():
@@ -174,9 +176,11 @@ def test_conservation_and_determinism_gpu():
     assert torch.equal(a, b)
 
 
-def test_square_burgers_full_size():
+@pytest.mark.parametrize("lanes", [0, 8])
+def test_square_burgers_full_size(lanes):
     """The benchmark workload: ~19.6k triangles, p=3, Burgers, 12-20 cell stencils.
-    One rhs, the reconstruction, and 10 RK3 steps against the oracle."""
+    One rhs, the reconstruction, and 10 RK3 steps against the oracle, with the
+    automatic lane count (4 lanes per cell) and with 8."""
     wl = configs.square_burgers()
     s = wl.settings
     u0 = wl.u0
@@ -186,7 +190,8 @@ def test_square_burgers_full_size():
     w.mesh_upload(2, wl.mesh.verts, wl.mesh.cells)
     w.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers")
     dt = 0.5 * w.info()["min_insphere"] / (np.sqrt(2.0) * np.max(np.abs(u0)))
-    _compare_all(wl.mesh, u0, 10, dt, "square100-burgers", p=3, n_lo=12, n_hi=20, flux="burgers")
+    _compare_all(wl.mesh, u0, 10, dt, f"square100-burgers-lanes{lanes}", p=3, n_lo=12, n_hi=20, flux="burgers",
+                 lanes=lanes)
 
 
 def test_errors_on_device_context():
