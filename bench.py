@@ -10,9 +10,14 @@ triangulation of a 100x100 jittered lattice (19,602 triangles, p = 3,
 timed region starts.
 
 Prints one JSON line: throughput in cell-updates/s (cells x steps / s), a
-roofline entry for the dominant kernel (event-timed in this run), and the
-FP64 CPU oracle timed on a bounded sample of the same workload on the host's
-cores, together with the GPU-vs-oracle parity of that sample.
+roofline entry for the dominant kernel (the reconstruction, FP64-ALU bound)
+and one for the flux/update kernel (HBM bound), both event-timed in this run,
+and the FP64 CPU oracle timed on a bounded sample of the same workload on the
+host's cores, together with the GPU-vs-oracle parity of that sample.
+`--workload square-large` runs the 1000x1000-point companion mesh (~2.0 M
+triangles) on which HBM traffic is measured (profiles/traffic.json holds the
+calibrated rocprofv3 FETCH_SIZE/WRITE_SIZE per launch, valid while the kernel
+source hash matches).
 """
 
 from __future__ import annotations
@@ -55,6 +60,15 @@ def recon_flops(n, m, dim, F, Q):
     back = m * m + m
     evalf = F * Q * 3 * m
     return build + weights + form + scale + qr + back + evalf
+
+
+def update_bytes(nc, dim, F, Q):
+    """Compulsory HBM bytes of one flux/update launch: sibling ids (4F),
+    area-scaled normals (8 F dim), the cell's own facet values (8 F Q; the
+    neighbour's copy of a facet value is counted once, as its own), 1/|tau|,
+    the state and stage inputs (one array in the first RK stage, two in the
+    others: 8 x 4/3 on average) and the output."""
+    return nc * (4 * F + 8 * F * dim + 8 * F * Q + 8 + 8 * 4.0 / 3.0 + 8)
 
 
 def traffic_record(kernel, workload):
@@ -135,6 +149,14 @@ def main():
     value = nc * args.steps / elapsed
     log(f"[bench] {args.steps} steps in {elapsed * 1e3:.2f} ms -> {value:.4g} cell-updates/s")
 
+    # a plain device copy of known size, so that hardware traffic counters of a
+    # profiled run can be calibrated (bytes read and written = 2 x 512 MiB)
+    cal_src = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
+    cal_dst = torch.empty_like(cal_src)
+    cal_dst.copy_(cal_src)
+    torch.cuda.synchronize()
+    del cal_src, cal_dst
+
     # kernel timing with HIP events on the library's stream, same K steps
     w.profile(True)
     u = u_init.clone()
@@ -160,7 +182,19 @@ def main():
         "traffic": traffic,
         "avg_launch_us": k1_avg * 1e3,
         "flops_per_launch": flops,
-        "update_kernel_avg_us": k2_avg * 1e3,
+    }
+    ub = update_bytes(nc, 2, F, Q)
+    ach_u = ub / (k2_avg * 1e-3) / 1e9
+    roofline_update = {
+        "bound": "hbm",
+        "kernel": "k_update",
+        "achieved": ach_u,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": ach_u / HBM_PEAK_GBS,
+        "traffic": traffic_record("k_update", args.workload),
+        "avg_launch_us": k2_avg * 1e3,
+        "bytes_per_launch": ub,
     }
 
     out = {
@@ -187,6 +221,7 @@ def main():
             "dt": dt,
         },
         "roofline": roofline,
+        "roofline_update": roofline_update,
     }
 
     if args.cpu_seconds > 0 and args.workload == "square":

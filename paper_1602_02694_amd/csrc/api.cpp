@@ -136,7 +136,6 @@ void upload_build(wlseno_ctx *c)
     dm.geo = upload(c, b.geo);
     dm.vrel = upload(c, b.vrel);
     dm.normal = upload(c, b.normal);
-    dm.area = upload(c, b.area);
     dm.rvol = upload(c, b.rvol);
     dm.sptr = upload(c, b.sptr);
     dm.scol = upload(c, b.scol);

@@ -71,8 +71,9 @@ struct Build {
     // facet arrays are facet-major: [F][nc] (normals [F][nc][dim])
     std::vector<int32_t> dsib;      // [F][nc]: (device cell << 2 | lf) or -1
     std::vector<int32_t> qperm;     // [F][nc]: 2 bits per point q: sibling's point index of own point q
-    std::vector<double> normal;     // [F][nc][dim] unit outward normals; sibling = exact negation
-    std::vector<double> area;       // [F][nc] facet measures (identical on both sides)
+    std::vector<double> normal;     // [F][nc][dim] outward normals scaled by the facet measure (|f| n);
+                                    // the sibling's is the exact negation
+    std::vector<double> area;       // [F][nc] facet measures (host only)
     std::vector<double> rvol;       // nc: 1/|tau|
 };
 
@@ -91,7 +92,7 @@ struct DevMesh {
     int64_t bucket_cell0[kMaxBuckets + 1] = {0, 0, 0, 0};
     double eh2 = 0.0, alpha_w = 1.5, rank_tol = 1e-12, period = 0.0, gamma = 1.4;
     double vel[3] = {0, 0, 0};
-    const double *geo = nullptr, *vrel = nullptr, *normal = nullptr, *area = nullptr, *rvol = nullptr;
+    const double *geo = nullptr, *vrel = nullptr, *normal = nullptr, *rvol = nullptr;   // normal = |f| n
     const int32_t *sptr = nullptr, *scol = nullptr, *sib = nullptr, *qperm = nullptr, *perm = nullptr;
     const int32_t *spad = nullptr;
     int64_t spad_off[kMaxBuckets + 1] = {0, 0, 0, 0};

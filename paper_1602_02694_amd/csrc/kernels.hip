@@ -520,9 +520,14 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
         // global Lax-Friedrichs alpha: max |u sum_d n_d| over all facet points
         double am = 0.0;
         if (writer) {
-            double sn = 0.0;
+            double sm = 0.0, mm = 0.0;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) sn += a.normal[(lf * a.nc + c) * DIM + d];
+            for (int d = 0; d < DIM; ++d) {
+                const double md = a.normal[(lf * a.nc + c) * DIM + d];   // |f| n
+                sm += md;
+                mm += md * md;
+            }
+            const double sn = sm / sqrt(mm);
 #pragma unroll
             for (int q = 0; q < Q; ++q) am = fmax(am, fabs(fq[q] * sn));
         }
@@ -561,8 +566,8 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
 
 // --------------------------------------------------------------- K2/K3
 struct UArgs {
-    int64_t nc;
-    const double *fv, *normal, *area, *rvol;
+    int nc;
+    const double *fv, *snormal, *rvol;    // snormal = |f| n, [F][N][DIM]
     const int32_t *sib, *qperm;
     const double *u0, *prev;
     double *out;
@@ -573,20 +578,26 @@ struct UArgs {
     int mode;
 };
 
+// |f| times the Lax-Friedrichs flux for the area-scaled normal m = |f| n.
 template <int DIM, int FLUX>
-__device__ __forceinline__ double lf_flux(double ua, double ub, const double (&n)[DIM], double alpha,
+__device__ __forceinline__ double lf_flux(double ua, double ub, const double (&m)[DIM], double alpha,
                                           const double (&vel)[3])
 {
     if constexpr (FLUX == kFluxAdv) {
-        double an = 0.0;
+        // alpha = |a.n| per facet, so |f| alpha = |a.m|
+        double am = 0.0;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) an += vel[d] * n[d];
-        return 0.5 * ((an * ua + an * ub) - fabs(an) * (ub - ua));
+        for (int d = 0; d < DIM; ++d) am += vel[d] * m[d];
+        return 0.5 * ((am * ua + am * ub) - fabs(am) * (ub - ua));
     } else {
-        double sn = 0.0;
+        double sm = 0.0, mm = 0.0;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) sn += n[d];
-        return 0.5 * ((0.5 * ua * ua * sn + 0.5 * ub * ub * sn) - alpha * (ub - ua));
+        for (int d = 0; d < DIM; ++d) {
+            sm += m[d];
+            mm += m[d] * m[d];
+        }
+        const double af = alpha * sqrt(mm);
+        return 0.5 * ((0.5 * ua * ua * sm + 0.5 * ub * ub * sm) - af * (ub - ua));
     }
 }
 
@@ -594,7 +605,8 @@ template <int DIM, int Q, int FLUX>
 __global__ void __launch_bounds__(256) k_update(UArgs a)
 {
     constexpr int F = DIM + 1;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned N = (unsigned)a.nc;
+    const unsigned c = (unsigned)xcd_block((int)blockIdx.x, (int)gridDim.x) * 256u + threadIdx.x;
     double alpha = 0.0;
     if constexpr (FLUX == kFluxBurgers) {
         const int lane = (int)(threadIdx.x & 63);
@@ -604,41 +616,46 @@ __global__ void __launch_bounds__(256) k_update(UArgs a)
         alpha = v;
         if (blockIdx.x == 0 && threadIdx.x < kAlphaSlots) a.alpha_clr[threadIdx.x * 16] = 0ull;
     }
-    if (c >= a.nc) return;
+    if (c >= N) return;
     double vel[3] = {a.vel[0], a.vel[1], a.vel[2]};
     double tot = 0.0;
 #pragma unroll
     for (int lf = 0; lf < F; ++lf) {
-        const int64_t N = a.nc;
-        const int32_t s = a.sib[lf * N + c];
-        double n[DIM];
+        const unsigned fc = lf * N + c;
+        const int32_t s = a.sib[fc];
+        double m[DIM];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) n[d] = a.normal[(lf * N + c) * DIM + d];
-        const double *own = a.fv + (lf * N + c) * Q;
+        for (int d = 0; d < DIM; ++d) m[d] = a.snormal[fc * DIM + d];
+        const double *own = a.fv + fc * Q;
         double facc = 0.0;
         if (s < 0) {
             // transmissive boundary: outside state equals inside state
 #pragma unroll
-            for (int q = 0; q < Q; ++q) facc += quad_weight<DIM, Q>(q) * lf_flux<DIM, FLUX>(own[q], own[q], n, alpha, vel);
+            for (int q = 0; q < Q; ++q)
+                facc += quad_weight<DIM, Q>(q) * lf_flux<DIM, FLUX>(own[q], own[q], m, alpha, vel);
         } else {
-            const int64_t j = s >> 2;
-            const int l2 = s & 3;
+            // both cells evaluate the facet from identical operands in the
+            // orientation of the lower-numbered cell; the other one negates
+            const unsigned j = (unsigned)s >> 2;
+            const unsigned l2 = (unsigned)s & 3u;
             const double *oth = a.fv + (l2 * N + j) * Q;
             const bool owner = c < j;
-            const int32_t qp = owner ? a.qperm[lf * N + c] : a.qperm[l2 * N + j];
-            double nn[DIM];
+            int32_t qp = 0;
+            if constexpr (DIM == 3) qp = owner ? a.qperm[fc] : a.qperm[l2 * N + j];
+            double mm[DIM];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) nn[d] = owner ? n[d] : -n[d];
+            for (int d = 0; d < DIM; ++d) mm[d] = owner ? m[d] : -m[d];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                const int qo = (qp >> (2 * q)) & 3;
+                // the sibling's point matching point q: reversed along an edge in 2-D
+                const int qo = DIM == 3 ? ((qp >> (2 * q)) & 3) : (Q - 1 - q);
                 const double ua = owner ? own[q] : oth[q];
                 const double ub = owner ? oth[qo] : own[qo];
-                facc += quad_weight<DIM, Q>(q) * lf_flux<DIM, FLUX>(ua, ub, nn, alpha, vel);
+                facc += quad_weight<DIM, Q>(q) * lf_flux<DIM, FLUX>(ua, ub, mm, alpha, vel);
             }
             facc = owner ? facc : -facc;
         }
-        tot += a.area[lf * N + c] * facc;
+        tot += facc;
     }
     const double L = -tot * a.rvol[c];
     double o;
@@ -774,10 +791,9 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
                   double Cdt, int mode, int parity, void *stream)
 {
     UArgs a;
-    a.nc = dm.nc;
+    a.nc = (int)dm.nc;
     a.fv = dm.fv;
-    a.normal = dm.normal;
-    a.area = dm.area;
+    a.snormal = dm.normal;
     a.rvol = dm.rvol;
     a.sib = dm.sib;
     a.qperm = dm.qperm;

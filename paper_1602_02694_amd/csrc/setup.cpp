@@ -649,7 +649,7 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
             double n[3] = {0, 0, 0}, ar = 0.0;
             if (s < 0) {
                 own_normal(u, lf, n, &ar);
-                for (int k = 0; k < dim; ++k) b.normal[(lf * nc + d) * dim + k] = n[k];
+                for (int k = 0; k < dim; ++k) b.normal[(lf * nc + d) * dim + k] = ar * n[k];
                 b.area[lf * nc + d] = ar;
             } else {
                 int64_t u2 = s >> 2;
@@ -663,7 +663,8 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
                     own_normal(u2, lf2, n, &ar);
                     for (int k = 0; k < dim; ++k) n[k] = -n[k];
                 }
-                for (int k = 0; k < dim; ++k) b.normal[(lf * nc + d) * dim + k] = n[k];
+                // scaled by the facet measure; the sibling's is the exact negation
+                for (int k = 0; k < dim; ++k) b.normal[(lf * nc + d) * dim + k] = ar * n[k];
                 b.area[lf * nc + d] = ar;
                 b.dsib[lf * nc + d] = (int32_t)((d2 << 2) | lf2);
                 // sibling point index of each own point
