@@ -89,14 +89,36 @@ def traffic_record(kernel, workload):
     return None
 
 
-def make_workload(name):
-    from workloads import configs
+# name -> (mesh builder, initial data, settings)
+WORKLOADS = {
+    "square": dict(dim=2, side=100, seed=2001, p=3, n_lo=12, n_hi=20, flux="burgers", velocity=(0, 0, 0),
+                   metric=METRIC),
+    "square-large": dict(dim=2, side=1000, seed=2002, p=3, n_lo=12, n_hi=20, flux="burgers",
+                         velocity=(0, 0, 0), metric=METRIC),
+    "cube": dict(dim=3, side=74, seed=4001, p=3, n_lo=30, n_hi=50, flux="advection",
+                 velocity=(1.0, 0.5, 0.25), metric="cell-updates/s (p=3, 3-D tet, FP64) at 1e-12 vs oracle"),
+}
 
-    if name == "square":
-        return configs.square_burgers(100, 2001)
-    if name == "square-large":
-        return configs.square_burgers(1000, 2002)
-    raise SystemExit(f"unknown workload {name}")
+
+def make_workload(name):
+    """Mesh and initial cell averages, built in two logged phases."""
+    from workloads import fields, jittered_cube, jittered_square
+    from workloads.configs import Workload
+
+    cfg = WORKLOADS[name]
+    t = time.time()
+    if cfg["dim"] == 2:
+        mesh = jittered_square(cfg["side"], 0.3, cfg["seed"])
+    else:
+        mesh = jittered_cube(cfg["side"], 0.15, cfg["seed"])
+    log(f"[bench] mesh: {mesh.n_cell} cells in {time.time() - t:.1f}s")
+    t = time.time()
+    fn = fields.gaussian_bump_with_step_2d if cfg["dim"] == 2 else fields.sine_with_sphere_3d
+    u0 = fields.cell_averages(mesh, fn)
+    kind = "burgers" if cfg["flux"] == "burgers" else "advection"
+    shape = "tri" if cfg["dim"] == 2 else "tet"
+    log(f"[bench] initial averages in {time.time() - t:.1f}s")
+    return Workload(f"{shape}{mesh.n_cell}-{kind}-p{cfg['p']}", mesh, u0, dict(cfg))
 
 
 def main():
@@ -104,7 +126,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="square", choices=["square", "square-large"])
+    ap.add_argument("--workload", default="square", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables the CPU leg)")
     args = ap.parse_args()
@@ -117,20 +139,25 @@ def main():
 
     from paper_1602_02694_amd import WLSENO
 
-    t0 = time.time()
     wl = make_workload(args.workload)
+    cfg = wl.settings
     mesh = wl.mesh
-    log(f"[bench] workload {wl.name}: {mesh.n_cell} cells, generated in {time.time() - t0:.1f}s")
+    dim = mesh.dim
+    log(f"[bench] workload {wl.name}")
     w = WLSENO(device=0)
-    w.mesh_upload(2, mesh.verts, mesh.cells)
     t1 = time.time()
-    w.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers")
+    w.mesh_upload(dim, mesh.verts, mesh.cells)
+    w.stencil_build(p=cfg["p"], n_lo=cfg["n_lo"], n_hi=cfg["n_hi"], flux=cfg["flux"], velocity=cfg["velocity"])
     info = w.info()
     rp, _ = w.stencil()
     nsz = np.diff(rp)
     log(f"[bench] setup {time.time() - t1:.2f}s, stencils {nsz.min()}-{nsz.max()} (mean {nsz.mean():.2f})")
     u0 = np.ascontiguousarray(wl.u0, dtype=np.float64)
-    dt = 0.5 * info["min_insphere"] / (np.sqrt(2.0) * np.max(np.abs(u0)))
+    if cfg["flux"] == "burgers":
+        speed = np.sqrt(float(dim)) * np.max(np.abs(u0))
+    else:
+        speed = float(np.linalg.norm(cfg["velocity"][:dim]))
+    dt = 0.5 * info["min_insphere"] / speed
     u_init = torch.tensor(u0, device="cuda")
 
     # warm-up
@@ -167,7 +194,7 @@ def main():
     k1_avg = k1_ms / max(k1_n, 1)
     k2_avg = k2_ms / max(k2_n, 1)
     F, Q, m = info["faces_per_cell"], info["points_per_face"], info["m"]
-    flops = float(np.sum(recon_flops(nsz, m, 2, F, Q)))
+    flops = float(np.sum(recon_flops(nsz, m, dim, F, Q)))
     achieved = flops / (k1_avg * 1e-3) / 1e12
     log(f"[bench] k_reconstruct avg {k1_avg * 1e3:.2f} us ({k1_n} launches), "
         f"k_update avg {k2_avg * 1e3:.2f} us; {flops / nc:.0f} flop/cell")
@@ -183,7 +210,7 @@ def main():
         "avg_launch_us": k1_avg * 1e3,
         "flops_per_launch": flops,
     }
-    ub = update_bytes(nc, 2, F, Q)
+    ub = update_bytes(nc, dim, F, Q)
     ach_u = ub / (k2_avg * 1e-3) / 1e9
     roofline_update = {
         "bound": "hbm",
@@ -198,7 +225,7 @@ def main():
     }
 
     out = {
-        "metric": METRIC,
+        "metric": cfg["metric"],
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -212,11 +239,13 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": wl.name,
-            "mesh": f"Delaunay triangulation of a jittered {int(round(np.sqrt(mesh.n_vert)))}^2 lattice on [0,1]^2",
+            "mesh": (f"Delaunay triangulation of a jittered {cfg['side']}^{dim} lattice on [0,1]^{dim}"
+                     f" (seed {cfg['seed']})"),
             "n_cell": nc,
-            "p": 3,
+            "p": cfg["p"],
             "stencil_cells": [int(nsz.min()), int(nsz.max())],
-            "flux": "burgers, global Lax-Friedrichs alpha",
+            "flux": ("burgers, global Lax-Friedrichs alpha" if cfg["flux"] == "burgers"
+                     else f"linear advection, a = {tuple(cfg['velocity'][:dim])}"),
             "time_integrator": "TVD RK3",
             "dt": dt,
         },

@@ -125,7 +125,7 @@ void upload_build(wlseno_ctx *c)
     dm.max_stencil = b.max_stencil;
     dm.nc = m.nc;
     dm.nbuckets = b.nbuckets;
-    for (int t = 0; t < kMaxBuckets; ++t) dm.bucket_rpl[t] = b.bucket_rpl[t];
+    for (int t = 0; t < kMaxBuckets; ++t) dm.bucket_cap[t] = b.bucket_cap[t];
     for (int t = 0; t <= kMaxBuckets; ++t) dm.bucket_cell0[t] = b.bucket_cell0[t];
     dm.eh2 = b.prm.eps * m.h * m.h;
     dm.alpha_w = b.prm.alpha_w;

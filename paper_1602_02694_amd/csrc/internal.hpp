@@ -18,11 +18,12 @@ struct Error {
 // Number of Taylor coefficients C(p-1+dim, dim).
 int num_coeffs(int dim, int p);
 
-// Stencil-size buckets of the reconstruction kernel: each bucket runs a
-// variant holding `rpl` stencil rows per lane (4 lanes per cell).
+// Stencil-size buckets of the reconstruction kernel: bucket b holds the cells
+// whose stencils have at most cap[b] rows; its variant keeps ceil(cap[b]/G)
+// rows per lane with G lanes per cell.
 constexpr int kMaxBuckets = 3;
-// Ascending rows-per-lane variants compiled for (dim, p); empty if none.
-std::vector<int> rpl_variants(int dim, int p);
+// Ascending bucket capacities compiled for (dim, p); empty if none.
+std::vector<int> stencil_capacities(int dim, int p);
 // Facet quadrature points per facet (1-D: 1; 2-D: ceil(p/2); 3-D: 3).
 int points_per_face(int dim, int p);
 
@@ -55,16 +56,16 @@ struct Build {
     // perm[d] = user id of device cell d; iperm[u] = device id of user cell u
     std::vector<int32_t> perm, iperm;
     // stencil-size buckets: device cells [bucket_cell0[b], bucket_cell0[b+1])
-    // use bucket_rpl[b] rows per lane (nbuckets <= kMaxBuckets; 0 = unsupported)
+    // have at most bucket_cap[b] stencil rows (nbuckets <= kMaxBuckets; 0 = unsupported)
     int nbuckets = 0;
-    int bucket_rpl[kMaxBuckets] = {0, 0, 0};
+    int bucket_cap[kMaxBuckets] = {0, 0, 0};
     int64_t bucket_cell0[kMaxBuckets + 1] = {0, 0, 0, 0};
     // device order records
     std::vector<double> geo;        // nc*gs: centroid, then moments nu(alpha)=mu(alpha)/alpha! for 2 <= |alpha| <= p-1
     std::vector<double> vrel;       // nc*(dim+1)*dim vertex offsets from the centroid
     std::vector<int32_t> sptr, scol;    // device-order CSR, device ids, centre first
     // padded stencil table for the reconstruction kernel: cells of bucket b
-    // hold 4*bucket_rpl[b] entries each (device ids, centre first, -1 padding)
+    // hold bucket_cap[b] entries each (device ids, centre first, -1 padding)
     // starting at spad_off[b]
     std::vector<int32_t> spad;
     int64_t spad_off[kMaxBuckets + 1] = {0, 0, 0, 0};
@@ -88,7 +89,7 @@ struct DevMesh {
     int lanes = 0;   // lanes per cell in the reconstruction: 0 = automatic, 4 or 8
     int64_t nc = 0;
     int nbuckets = 0;
-    int bucket_rpl[kMaxBuckets] = {0, 0, 0};
+    int bucket_cap[kMaxBuckets] = {0, 0, 0};
     int64_t bucket_cell0[kMaxBuckets + 1] = {0, 0, 0, 0};
     double eh2 = 0.0, alpha_w = 1.5, rank_tol = 1e-12, period = 0.0, gamma = 1.4;
     double vel[3] = {0, 0, 0};

@@ -109,14 +109,16 @@ __device__ __forceinline__ double quad_bcast(double x, int l)
     }
 }
 
-// Sum over a group of G = 4 or 8 lanes.  For G = 8 the two quad totals are
-// exchanged with row_half_mirror (lane i <-> 7-i), so every lane adds the
-// same two operands and all eight hold identical bits.
+// Sum over a group of G = 4, 8 or 16 lanes.  Beyond the quad, partial sums
+// are exchanged with row_half_mirror (lane i <-> 7-i) and row_mirror
+// (i <-> 15-i): every lane adds the same two operands, so all lanes of the
+// group hold identical bits.
 template <int G>
 __device__ __forceinline__ double group_sum(double x)
 {
     x = quad_sum(x);
-    if constexpr (G == 8) x = x + dpp_d<0x141>(x);
+    if constexpr (G >= 8) x = x + dpp_d<0x141>(x);
+    if constexpr (G >= 16) x = x + dpp_d<0x140>(x);
     return x;
 }
 
@@ -124,12 +126,19 @@ __device__ __forceinline__ double group_sum(double x)
 template <int G>
 __device__ __forceinline__ double group_bcast(double x, int l, int g)
 {
-    const double t = quad_bcast(x, l & 3);
+    const double t = quad_bcast(x, l & 3);          // lane l&3 of this lane's quad
     if constexpr (G == 4) {
         return t;
-    } else {
-        const double o = dpp_d<0x141>(t);
+    } else if constexpr (G == 8) {
+        const double o = dpp_d<0x141>(t);           // ... of the other quad of the 8
         return ((g >> 2) == (l >> 2)) ? t : o;
+    } else {
+        // quads reachable: own (q), half mirror (q^1), mirror (q^3), both (q^2)
+        const double t1 = dpp_d<0x141>(t);
+        const double t2 = dpp_d<0x140>(t);
+        const double t3 = dpp_d<0x140>(t1);
+        const int d = (g >> 2) ^ (l >> 2);
+        return d == 0 ? t : (d == 1 ? t1 : (d == 3 ? t2 : t3));
     }
 }
 
@@ -720,22 +729,24 @@ int launch_k23(const DevMesh &dm, const UArgs &args, hipStream_t st)
 
 }  // namespace
 
-std::vector<int> rpl_variants(int dim, int p)
+std::vector<int> stencil_capacities(int dim, int p)
 {
-    if (dim == 1 && p >= 2 && p <= 5) return {2};
-    if (dim == 2 && p == 2) return {2};
-    if (dim == 2 && p == 3) return {3, 4, 5};
-    if (dim == 2 && p == 4) return {5, 7, 9};
+    if (dim == 1 && p >= 2 && p <= 5) return {8};
+    if (dim == 2 && p == 2) return {8};
+    if (dim == 2 && p == 3) return {12, 16, 20};
+    if (dim == 2 && p == 4) return {20, 28, 36};
+    if (dim == 3 && p == 2) return {16};
+    if (dim == 3 && p == 3) return {32, 40, 56};
     return {};
 }
 
 bool reconstruct_supported(const DevMesh &dm)
 {
-    const std::vector<int> v = rpl_variants(dm.dim, dm.p);
+    const std::vector<int> v = stencil_capacities(dm.dim, dm.p);
     if (v.empty() || dm.nbuckets != (int)v.size()) return false;
     for (int b = 0; b < dm.nbuckets; ++b)
-        if (dm.bucket_rpl[b] != v[b]) return false;
-    return dm.max_stencil <= 4 * v.back();
+        if (dm.bucket_cap[b] != v[b]) return false;
+    return dm.max_stencil <= v.back();
 }
 
 int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *coef_user, double *fv_user,
@@ -764,11 +775,12 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     for (int b = 0; b <= kMaxBuckets; ++b) {
         a.cell0[b] = dm.bucket_cell0[b < dm.nbuckets ? b : dm.nbuckets];
         a.spad_off[b] = dm.spad_off[b];
-        if (b < kMaxBuckets) a.stride[b] = b < dm.nbuckets ? 4 * dm.bucket_rpl[b] : 0;
+        if (b < kMaxBuckets) a.stride[b] = b < dm.nbuckets ? dm.bucket_cap[b] : 0;
     }
     hipStream_t st = (hipStream_t)stream;
-    // 4 lanes per cell unless 8 are asked for (measured faster at every size)
-    const bool wide = dm.lanes == 8;
+    // rows per lane = ceil(capacity / lanes); 4 lanes per cell in 1-D and 2-D,
+    // 16 in 3-D (10 coefficients, stencils up to 56 rows)
+    const int lanes = dm.lanes ? dm.lanes : (dm.dim == 3 ? 16 : 4);
     if (dm.dim == 1) {
         switch (dm.p) {
         case 2: return launch_k1<1, 2, 4, 2, 2, 2>(dm, a, st);
@@ -779,10 +791,19 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     } else if (dm.dim == 2) {
         if (dm.p == 2) return launch_k1<2, 2, 4, 2, 2, 2>(dm, a, st);
         if (dm.p == 3) {
-            if (wide) return launch_k1<2, 3, 8, 2, 2, 3>(dm, a, st);
+            if (lanes == 8) return launch_k1<2, 3, 8, 2, 2, 3>(dm, a, st);
             return launch_k1<2, 3, 4, 3, 4, 5>(dm, a, st);
         }
-        if (dm.p == 4) return launch_k1<2, 4, 4, 5, 7, 9>(dm, a, st);
+        if (dm.p == 4) {
+            if (lanes == 8) return launch_k1<2, 4, 8, 3, 4, 5>(dm, a, st);
+            return launch_k1<2, 4, 4, 5, 7, 9>(dm, a, st);
+        }
+    } else if (dm.dim == 3) {
+        if (dm.p == 2) return launch_k1<3, 2, 4, 4, 4, 4>(dm, a, st);
+        if (dm.p == 3) {
+            if (lanes == 8) return launch_k1<3, 3, 8, 4, 5, 7>(dm, a, st);
+            return launch_k1<3, 3, 16, 2, 3, 4>(dm, a, st);
+        }
     }
     return (int)hipErrorInvalidValue;
 }
@@ -815,6 +836,7 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
         if (dm.nq == 1) return launch_k23<2, 1>(dm, a, st);
         if (dm.nq == 2) return launch_k23<2, 2>(dm, a, st);
     }
+    if (dm.dim == 3 && dm.nq == 3) return launch_k23<3, 3>(dm, a, st);
     return (int)hipErrorInvalidValue;
 }
 

@@ -438,7 +438,8 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     if (prm.flux != WLSENO_FLUX_ADVECTION && prm.flux != WLSENO_FLUX_BURGERS)
         throw Error{WLSENO_EUNSUPPORTED, "flux must be advection or Burgers"};
     if (prm.weight_mode != 0 && prm.weight_mode != 1) throw inval("weight_mode must be 0 or 1");
-    if (prm.lanes != 0 && prm.lanes != 4 && prm.lanes != 8) throw inval("lanes must be 0, 4 or 8");
+    if (prm.lanes != 0 && prm.lanes != 4 && prm.lanes != 8 && prm.lanes != 16)
+        throw inval("lanes must be 0, 4, 8 or 16");
     if (!(prm.eps >= 0.0) || !(prm.alpha_w > 0.0) || !(prm.rank_tol >= 0.0))
         throw inval("eps >= 0, alpha_w > 0 and rank_tol >= 0 required");
     Build b;
@@ -487,9 +488,9 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     }
 
     // renumbering: reverse Cuthill-McKee, then a stable partition into the
-    // reconstruction kernel's stencil-size buckets (rows per lane >= n/4)
+    // reconstruction kernel's stencil-size buckets
     std::vector<int32_t> rcm = rcm_order(m);
-    const std::vector<int> variants = rpl_variants(dim, prm.p);
+    const std::vector<int> variants = stencil_capacities(dim, prm.p);
     if (variants.empty() || (int)variants.size() > kMaxBuckets) {
         b.perm = std::move(rcm);
         b.nbuckets = 0;
@@ -499,14 +500,14 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
         const int nbk = (int)variants.size();
         auto bucket_of = [&](int64_t u) {
             for (int t = 0; t < nbk; ++t)
-                if (4 * variants[t] >= cnt[u]) return t;
+                if (variants[t] >= cnt[u]) return t;
             return nbk - 1;   // too large: reported as unsupported by the device upload
         };
         b.perm.clear();
         b.perm.reserve(nc);
         b.nbuckets = nbk;
         for (int t = 0; t < nbk; ++t) {
-            b.bucket_rpl[t] = variants[t];
+            b.bucket_cap[t] = variants[t];
             b.bucket_cell0[t] = (int64_t)b.perm.size();
             for (int32_t u : rcm)
                 if (bucket_of(u) == t) b.perm.push_back(u);
@@ -529,12 +530,12 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
         int64_t off = 0;
         for (int t = 0; t < kMaxBuckets; ++t) {
             b.spad_off[t] = off;
-            if (t < b.nbuckets) off += (b.bucket_cell0[t + 1] - b.bucket_cell0[t]) * 4 * b.bucket_rpl[t];
+            if (t < b.nbuckets) off += (b.bucket_cell0[t + 1] - b.bucket_cell0[t]) * b.bucket_cap[t];
         }
         b.spad_off[kMaxBuckets] = off;
         b.spad.assign(off, -1);
         for (int t = 0; t < b.nbuckets; ++t) {
-            const int stride = 4 * b.bucket_rpl[t];
+            const int stride = b.bucket_cap[t];
             for (int64_t d = b.bucket_cell0[t]; d < b.bucket_cell0[t + 1]; ++d) {
                 const int64_t base = b.spad_off[t] + (d - b.bucket_cell0[t]) * stride;
                 const int32_t n = b.sptr[d + 1] - b.sptr[d];

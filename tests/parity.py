@@ -99,21 +99,29 @@ def poly_dev(gcoef, ocoef, o, u, floor=FLOOR):
     """Taylor coefficient vectors compared through the polynomials they define:
     the bound sum_k |dv_k| rho_i^{|a_k|} / a_k! on their largest difference over
     the ball of radius rho_i (centroid to farthest vertex) that holds cell i,
-    relative to max(|u_i|, floor * max|u|)."""
+    relative to the same bound of the reference polynomial itself,
+    sum_k |v_k| rho_i^{|a_k|} / a_k! (at least max(|u_i|, floor * max|u|)).
+
+    A backward-stable least-squares solve bounds the error of the whole
+    coefficient vector relative to that vector's own size, so a polynomial that
+    varies far more across the ball than its mean value (a cell at a steep
+    front, u_i near zero) is measured against its own range, as facet values
+    are measured against their own magnitude."""
     from math import factorial
 
     m = o.mesh
     rho = np.sqrt(((m.cv - m.cent[:, None, :]) ** 2).sum(axis=2)).max(axis=1)      # (nc,)
     g = np.asarray(gcoef, dtype=np.float64)
     r = np.asarray(ocoef, dtype=np.float64)
-    assert g.shape == r.shape, (what, g.shape, r.shape)
-    assert np.all(np.isfinite(g)), f"{what}: non-finite GPU coefficients"
+    assert g.shape == r.shape, (g.shape, r.shape)
+    assert np.all(np.isfinite(g)), "non-finite GPU coefficients"
     deg = o.exps.sum(axis=1)
     fac = np.array([np.prod([factorial(int(a)) for a in e]) for e in o.exps], dtype=np.float64)
     w = rho[:, None] ** deg[None, :] / fac[None, :]                                # (nc, m)
     dev = (np.abs(g - r) * w[None]).sum(axis=2)                                     # (V, nc)
+    size = (np.abs(r) * w[None]).sum(axis=2)
     uu = np.asarray(u, dtype=np.float64).reshape(dev.shape)
-    sc = np.maximum(np.abs(uu), floor * np.max(np.abs(uu), axis=1, keepdims=True))
+    sc = np.maximum(np.maximum(np.abs(uu), size), floor * np.max(np.abs(uu), axis=1, keepdims=True))
     return dev / np.where(sc > 0, sc, 1.0)
 
 

@@ -49,6 +49,12 @@ def _compare_all(mesh, u0, steps, dt, name, **kw):
     torch = _torch()
     _say(f"[case] {name}: n_cell={mesh.n_cell} kw={kw}")
     w = _gpu(mesh, **kw)
+    if dt is None:
+        # half the CFL limit of the smallest cell: |a| dt <= r_min / 2
+        v = np.asarray(kw.get("velocity", (0.0, 0.0, 0.0)))[: mesh.dim]
+        speed = (np.sqrt(mesh.dim) * np.max(np.abs(u0)) if kw.get("flux") == "burgers"
+                 else float(np.linalg.norm(v)))
+        dt = 0.5 * w.info()["min_insphere"] / speed
     o = _oracle(mesh, **kw)
     ox = _oracle(mesh, extended=True, stencil=(o.row_ptr, o.col), **kw)
     rp, col = w.stencil()
@@ -213,3 +219,34 @@ def test_errors_on_device_context():
     with pytest.raises(WLSENOError) as e:
         w._check(w._lib.wlseno_step(w._h, v.data_ptr(), float("nan"), 1))
     assert e.value.status == 1
+
+
+# ------------------------------------------------------------------ 3-D
+
+@pytest.mark.parametrize("lanes", [0, 8])
+def test_cube_advection_p3(lanes):
+    """Tetrahedra of a jittered 8^3 lattice, p=3 (10 coefficients), 30-50 cell
+    stencils, a = (1, 0.5, 0.25), sine product plus a sphere step."""
+    from workloads import jittered_cube
+
+    mesh = jittered_cube(8, 0.15, 4101)
+    u0 = fields.cell_averages(mesh, fields.sine_with_sphere_3d)
+    _compare_all(mesh, u0, 5, None, f"cube8-adv-lanes{lanes}", p=3, n_lo=30, n_hi=50, flux="advection",
+                 velocity=(1.0, 0.5, 0.25), lanes=lanes)
+
+
+def test_cube_burgers_p3():
+    from workloads import jittered_cube
+
+    mesh = jittered_cube(7, 0.15, 4102)
+    u0 = fields.cell_averages(mesh, lambda x: 0.3 + 0.7 * np.sin(2 * np.pi * (x[:, 0] + x[:, 1] + x[:, 2]) / 3))
+    _compare_all(mesh, u0, 5, None, "cube7-burgers", p=3, n_lo=30, n_hi=50, flux="burgers")
+
+
+def test_cube_p2():
+    from workloads import jittered_cube
+
+    mesh = jittered_cube(7, 0.15, 4103)
+    u0 = fields.cell_averages(mesh, fields.sine_with_sphere_3d)
+    _compare_all(mesh, u0, 3, None, "cube7-p2", p=2, n_lo=8, n_hi=16, flux="advection",
+                 velocity=(0.3, -1.0, 0.5))
