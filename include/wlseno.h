@@ -79,9 +79,9 @@ typedef struct {
     int32_t flux;        /* WLSENO_FLUX_* */
     int32_t weight_mode; /* 0: WLS-ENO weights (eq. weight); 1: unit weights (plain least squares) */
     int32_t lanes;       /* lanes per cell in the reconstruction kernel: 0 = automatic (4 in 1-D and
-                            2-D, 16 in 3-D); 8 is also compiled for 2-D p = 3, 4 and 3-D p = 3.
-                            Other requests fall back to the automatic choice.  Results agree to
-                            rounding either way. */
+                            2-D, 8 in 3-D); 8 and 16 are also compiled for 2-D p = 3, 4 and
+                            3-D p = 3.  Other values are EINVAL; other (dim, p) pairs use the
+                            automatic choice.  Results agree to rounding either way. */
     double eps;          /* epsilon in beta_j = (u_j - u_i)^2 + eps h^2 */
     double alpha_w;      /* centre weight factor alpha > 1 in eq. (weight) */
     double rank_tol;     /* numerical rank: |R_kk| > rank_tol |R_11| */
@@ -177,16 +177,17 @@ wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps);
  * advection), read back from the device (synchronises the stream). */
 wlseno_status wlseno_last_alpha(wlseno_t ctx, double *alpha);
 
-/* Kernel timing for measurement.  on = 1 clears the accumulators and from
- * then on brackets every reconstruction and flux/update launch with HIP
- * events on the context's stream; on = 0 stops recording.  The events add a
- * small gap between kernels, so time throughput with profiling off. */
-wlseno_status wlseno_profile(wlseno_t ctx, int on);
-
-/* Synchronise the stream and return the summed event time (milliseconds) and
- * the number of launches recorded for `kernel`: 0 = reconstruction
- * (k_reconstruct), 1 = flux, divergence and Runge-Kutta update (k_update). */
-wlseno_status wlseno_profile_read(wlseno_t ctx, int kernel, double *total_ms, int64_t *launches);
+/* Kernel timing for measurement.  Reconstructs u_dev (user order, n_cell
+ * doubles on the device, not modified) once, then records a HIP event on the
+ * context's stream, launches one kernel of a right-hand-side stage `launches`
+ * times back to back, records a second event and synchronises; *avg_ms is the
+ * elapsed time divided by `launches`.  kernel 0 = reconstruction
+ * (k_reconstruct: stencil gather, weights, QRCP solve, facet evaluation),
+ * 1 = flux, divergence and update (k_update, writing L(u) to an internal
+ * buffer).  Both launches are idempotent, so back-to-back runs measure the
+ * kernel itself without event gaps between launches.  EINVAL for kernel not
+ * 0/1, launches < 1 or a null pointer; ESTATE without a device stencil build. */
+wlseno_status wlseno_time_kernel(wlseno_t ctx, int kernel, const double *u_dev, int launches, double *avg_ms);
 
 #ifdef __cplusplus
 }

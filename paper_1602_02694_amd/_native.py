@@ -16,8 +16,7 @@ MESH_PERIODIC_1D = 1
 EXPORTS = [
     "wlseno_params_default", "wlseno_create", "wlseno_destroy", "wlseno_last_error", "wlseno_set_stream",
     "wlseno_mesh_upload", "wlseno_stencil_build", "wlseno_get_info", "wlseno_get_stencil",
-    "wlseno_reconstruct", "wlseno_rhs", "wlseno_step", "wlseno_last_alpha", "wlseno_profile",
-    "wlseno_profile_read",
+    "wlseno_reconstruct", "wlseno_rhs", "wlseno_step", "wlseno_last_alpha", "wlseno_time_kernel",
 ]
 
 
@@ -74,8 +73,7 @@ def load():
     lib.wlseno_rhs.argtypes = [vp, vp, vp]
     lib.wlseno_step.argtypes = [vp, vp, C.c_double, C.c_int]
     lib.wlseno_last_alpha.argtypes = [vp, dp]
-    lib.wlseno_profile.argtypes = [vp, C.c_int]
-    lib.wlseno_profile_read.argtypes = [vp, C.c_int, dp, C.POINTER(C.c_int64)]
+    lib.wlseno_time_kernel.argtypes = [vp, C.c_int, vp, C.c_int, dp]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name not in ("wlseno_params_default", "wlseno_last_error"):

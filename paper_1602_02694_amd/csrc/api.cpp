@@ -26,11 +26,6 @@ struct wlseno_ctx {
     std::vector<void *> allocs;
     double *ubuf = nullptr, *kbuf = nullptr, *tbuf = nullptr;
     int last_parity = 0;
-    // kernel timing: event pairs per kernel kind, reused between runs
-    bool profiling = false;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    std::vector<std::pair<size_t, int>> ev_marks;   // (start event index, kernel kind)
 };
 
 namespace {
@@ -45,29 +40,6 @@ void check_hip(hipError_t e, const char *what)
 void check_launch(int e, const char *what)
 {
     if (e != 0) throw Error{WLSENO_EDEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)e)};
-}
-
-void free_events(wlseno_ctx *c)
-{
-    if (c->device >= 0) {
-        (void)hipSetDevice(c->device);
-        for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    }
-    c->ev_pool.clear();
-    c->ev_used = 0;
-    c->ev_marks.clear();
-}
-
-// Record an event on the stream (profiling only); returns its pool index.
-size_t mark(wlseno_ctx *c)
-{
-    if (c->ev_used == c->ev_pool.size()) {
-        hipEvent_t e;
-        check_hip(hipEventCreate(&e), "hipEventCreate");
-        c->ev_pool.push_back(e);
-    }
-    check_hip(hipEventRecord(c->ev_pool[c->ev_used], c->stream), "hipEventRecord");
-    return c->ev_used++;
 }
 
 void free_device(wlseno_ctx *c)
@@ -163,19 +135,8 @@ void upload_build(wlseno_ctx *c)
 void stage(wlseno_ctx *c, const double *in, const double *u0, const double *prev, double *out, double A,
            double B, double Cdt, int mode, int parity)
 {
-    if (c->profiling) {
-        size_t e0 = mark(c);
-        check_launch(launch_reconstruct(c->dm, in, parity, nullptr, nullptr, nullptr, c->stream), "reconstruct");
-        mark(c);
-        c->ev_marks.push_back({e0, 0});
-        size_t e1 = mark(c);
-        check_launch(launch_update(c->dm, u0, prev, out, A, B, Cdt, mode, parity, c->stream), "update");
-        mark(c);
-        c->ev_marks.push_back({e1, 1});
-    } else {
-        check_launch(launch_reconstruct(c->dm, in, parity, nullptr, nullptr, nullptr, c->stream), "reconstruct");
-        check_launch(launch_update(c->dm, u0, prev, out, A, B, Cdt, mode, parity, c->stream), "update");
-    }
+    check_launch(launch_reconstruct(c->dm, in, parity, nullptr, nullptr, nullptr, c->stream), "reconstruct");
+    check_launch(launch_update(c->dm, u0, prev, out, A, B, Cdt, mode, parity, c->stream), "update");
     c->last_parity = parity;
 }
 
@@ -250,7 +211,6 @@ wlseno_status wlseno_create(int device, wlseno_t *out)
 wlseno_status wlseno_destroy(wlseno_t ctx)
 {
     if (!ctx) return WLSENO_OK;
-    free_events(ctx);
     free_device(ctx);
     delete ctx;
     return WLSENO_OK;
@@ -400,40 +360,40 @@ wlseno_status wlseno_last_alpha(wlseno_t ctx, double *alpha)
     API_END(ctx)
 }
 
-wlseno_status wlseno_profile(wlseno_t ctx, int on)
+wlseno_status wlseno_time_kernel(wlseno_t ctx, int kernel, const double *u_dev, int launches, double *avg_ms)
 {
     API_BEGIN(ctx)
-    if (ctx->device < 0) throw Error{WLSENO_ESTATE, "host-only context has no device"};
-    check_hip(hipSetDevice(ctx->device), "hipSetDevice");
-    if (on) {
-        check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-        ctx->ev_used = 0;
-        ctx->ev_marks.clear();
-    }
-    ctx->profiling = on != 0;
-    API_END(ctx)
-}
-
-wlseno_status wlseno_profile_read(wlseno_t ctx, int kernel, double *total_ms, int64_t *launches)
-{
-    API_BEGIN(ctx)
-    if (!total_ms || !launches) throw Error{WLSENO_EINVAL, "null output"};
+    if (!u_dev || !avg_ms) throw Error{WLSENO_EINVAL, "null pointer"};
     if (kernel != 0 && kernel != 1) throw Error{WLSENO_EINVAL, "kernel must be 0 or 1"};
-    if (ctx->device < 0) throw Error{WLSENO_ESTATE, "host-only context has no device"};
-    check_hip(hipSetDevice(ctx->device), "hipSetDevice");
-    check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    double tot = 0.0;
-    int64_t cnt = 0;
-    for (const auto &mk : ctx->ev_marks) {
-        if (mk.second != kernel) continue;
-        float ms = 0.0f;
-        check_hip(hipEventElapsedTime(&ms, ctx->ev_pool[mk.first], ctx->ev_pool[mk.first + 1]),
-                  "hipEventElapsedTime");
-        tot += ms;
-        ++cnt;
+    if (launches < 1) throw Error{WLSENO_EINVAL, "launches must be >= 1"};
+    need_device(ctx);
+    // state in device order, facet values and alpha of one reconstruction
+    check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
+    check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
+    check_launch(launch_reconstruct(ctx->dm, ctx->ubuf, 0, nullptr, nullptr, nullptr, ctx->stream), "reconstruct");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    check_hip(hipEventCreate(&e0), "hipEventCreate");
+    hipError_t he = hipEventCreate(&e1);
+    float ms = 0.0f;
+    if (he == hipSuccess) he = hipEventRecord(e0, ctx->stream);
+    int le = 0;
+    for (int i = 0; he == hipSuccess && le == 0 && i < launches; ++i) {
+        // both are idempotent here: the reconstruction rewrites the same facet
+        // values and alpha maximum, the update writes L(u) to a buffer of its own
+        if (kernel == 0)
+            le = launch_reconstruct(ctx->dm, ctx->ubuf, 0, nullptr, nullptr, nullptr, ctx->stream);
+        else
+            le = launch_update(ctx->dm, nullptr, nullptr, ctx->tbuf, 0.0, 0.0, 1.0, 0, 0, ctx->stream);
     }
-    *total_ms = tot;
-    *launches = cnt;
+    if (he == hipSuccess && le == 0) he = hipEventRecord(e1, ctx->stream);
+    if (he == hipSuccess && le == 0) he = hipEventSynchronize(e1);
+    if (he == hipSuccess && le == 0) he = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    check_launch(le, kernel == 0 ? "reconstruct" : "update");
+    check_hip(he, "kernel timing events");
+    ctx->last_parity = 0;
+    *avg_ms = (double)ms / launches;
     API_END(ctx)
 }
 

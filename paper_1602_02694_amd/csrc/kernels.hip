@@ -348,9 +348,11 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
 
     // Householder QR with column pivoting.  Rows < k are retired into the
     // owner lane's R store (Rs, cs) and zeroed in A, so every reduction runs
-    // over all slots without row predicates.
+    // over all slots without row predicates.  Column exchanges and row
+    // retirement run under lane masks (cells of a wave pivot independently);
+    // an exchange no cell of the wave needs is skipped.
     int pm[M];
-    double rd[M];
+    double rd[M], rinv[M];
     double Rs[RS][M], cs[RS];
 #pragma unroll
     for (int k = 0; k < M; ++k) pm[k] = k;
@@ -382,46 +384,53 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
             }
             // pivot: lowest column index among those within a relative kPivotTie
             // of the largest partial norm (rounding must not order ties)
+            double mx[M];
+#pragma unroll
+            for (int cc = k; cc < M; ++cc) mx[cc] = eta[cc];
+#pragma unroll
+            for (int w = 1; w < M - k; w *= 2)
+#pragma unroll
+                for (int cc = k; cc + w < M; cc += 2 * w) mx[cc] = fmax(mx[cc], mx[cc + w]);
+            const double tie = mx[k] * (1.0 - kPivotTie);
+            unsigned msk = 0u;
+#pragma unroll
+            for (int cc = k; cc < M; ++cc) msk |= (eta[cc] >= tie) ? (1u << cc) : 0u;
+            const int piv = msk ? __builtin_ctz(msk) : k;
             best = eta[k];
-#pragma unroll
-            for (int cc = k + 1; cc < M; ++cc) best = fmax(best, eta[cc]);
-            const double tie = best * (1.0 - kPivotTie);
-            int piv = M - 1;
-#pragma unroll
-            for (int cc = M - 1; cc >= k; --cc) piv = eta[cc] >= tie ? cc : piv;
-            best = eta[k];
-#pragma unroll
-            for (int cc = k + 1; cc < M; ++cc) best = piv == cc ? eta[cc] : best;
 #pragma unroll
             for (int cc = k + 1; cc < M; ++cc) {
-                const bool sw = piv == cc;
+                if (piv == cc) {
+                    best = eta[cc];
 #pragma unroll
-                for (int s = 0; s < RPL; ++s) {
-                    const double t0 = A[s][k], t1 = A[s][cc];
-                    A[s][k] = sw ? t1 : t0;
-                    A[s][cc] = sw ? t0 : t1;
-                }
-                // a pivot exchanges whole columns: the R entries of retired rows too
-#pragma unroll
-                for (int s = 0; s < RS; ++s) {
-                    if (s * G < k) {
-                        const double t0 = Rs[s][k], t1 = Rs[s][cc];
-                        Rs[s][k] = sw ? t1 : t0;
-                        Rs[s][cc] = sw ? t0 : t1;
+                    for (int s = 0; s < RPL; ++s) {
+                        const double t0 = A[s][k];
+                        A[s][k] = A[s][cc];
+                        A[s][cc] = t0;
                     }
+                    // a pivot exchanges whole columns: the R entries of retired rows too
+#pragma unroll
+                    for (int s = 0; s < RS; ++s) {
+                        if (s * G < k) {
+                            const double t0 = Rs[s][k];
+                            Rs[s][k] = Rs[s][cc];
+                            Rs[s][cc] = t0;
+                        }
+                    }
+                    const double s0 = sc[k];
+                    sc[k] = sc[cc];
+                    sc[cc] = s0;
+                    const int p0 = pm[k];
+                    pm[k] = pm[cc];
+                    pm[cc] = p0;
                 }
-                const double s0 = sc[k], s1 = sc[cc];
-                sc[k] = sw ? s1 : s0;
-                sc[cc] = sw ? s0 : s1;
-                const int p0 = pm[k], p1 = pm[cc];
-                pm[k] = sw ? p1 : p0;
-                pm[cc] = sw ? p0 : p1;
             }
         }
         const double alpha = group_bcast<G>(A[k / G][k], k % G, g);
         const bool nz = best > 0.0;
-        const double beta = nz ? -copysign(sqrt(best), alpha) : 0.0;
-        const double rb = nz ? rcp_nr(beta) : 0.0;
+        // beta = -sign(alpha) ||x||, and 1/beta, from one reciprocal square root
+        const double rs = nz ? rsq_nr(best) : 0.0;
+        const double beta = nz ? -copysign(best * rs, alpha) : 0.0;
+        const double rb = -copysign(rs, alpha);
         const double tau = (beta - alpha) * rb;
         const double scal = nz ? rcp_nr(alpha - beta) : 0.0;
         const bool own = g == (k % G);
@@ -447,17 +456,20 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
             for (int s = 0; s < RPL; ++s) bv[s] = fma(-tw, v[s], bv[s]);
         }
         rd[k] = beta;
+        rinv[k] = rb;
+        if (own) {
 #pragma unroll
-        for (int cc = k + 1; cc < M; ++cc) {
-            Rs[k / G][cc] = own ? A[k / G][cc] : Rs[k / G][cc];
-            A[k / G][cc] = own ? 0.0 : A[k / G][cc];
+            for (int cc = k + 1; cc < M; ++cc) {
+                Rs[k / G][cc] = A[k / G][cc];
+                A[k / G][cc] = 0.0;
+            }
+            cs[k / G] = bv[k / G];
+            bv[k / G] = 0.0;
         }
-        Rs[k / G][k] = own ? beta : Rs[k / G][k];
-        cs[k / G] = own ? bv[k / G] : cs[k / G];
-        bv[k / G] = own ? 0.0 : bv[k / G];
     }
 
     // numerical rank and back substitution on the leading r x r block
+    // (R_kk = beta_k, whose reciprocal the factorisation kept)
     const double thr = a.rank_tol * fabs(rd[0]);
     int rank = 0;
     bool ok = true;
@@ -472,7 +484,7 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
         double acc = cs[k / G];
 #pragma unroll
         for (int j = k + 1; j < M; ++j) acc = fma(-Rs[k / G][j], y[j], acc);
-        const double yk = group_bcast<G>(acc * rcp_nr(Rs[k / G][k]), k % G, g);
+        const double yk = group_bcast<G>(acc, k % G, g) * rinv[k];
         y[k] = (k < rank) ? yk : 0.0;
     }
     // coefficients in the original basis order, v = S E y, through LDS: lane g
@@ -610,12 +622,12 @@ __device__ __forceinline__ double lf_flux(double ua, double ub, const double (&m
     }
 }
 
-template <int DIM, int Q, int FLUX>
-__global__ void __launch_bounds__(256) k_update(UArgs a)
+template <int DIM, int Q, int FLUX, int BS>
+__global__ void __launch_bounds__(BS) k_update(UArgs a)
 {
     constexpr int F = DIM + 1;
     const unsigned N = (unsigned)a.nc;
-    const unsigned c = (unsigned)xcd_block((int)blockIdx.x, (int)gridDim.x) * 256u + threadIdx.x;
+    const unsigned c = (unsigned)xcd_block((int)blockIdx.x, (int)gridDim.x) * (unsigned)BS + threadIdx.x;
     double alpha = 0.0;
     if constexpr (FLUX == kFluxBurgers) {
         const int lane = (int)(threadIdx.x & 63);
@@ -719,11 +731,12 @@ int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
 template <int DIM, int Q>
 int launch_k23(const DevMesh &dm, const UArgs &args, hipStream_t st)
 {
-    const int nb = blocks_for(dm.nc, 256);
+    constexpr int BS = 256;   // 64 and 128 measured no faster, also on small meshes
+    const int nb = blocks_for(dm.nc, BS);
     if (dm.flux == kFluxBurgers)
-        hipLaunchKernelGGL((k_update<DIM, Q, kFluxBurgers>), dim3(nb), dim3(256), 0, st, args);
+        hipLaunchKernelGGL((k_update<DIM, Q, kFluxBurgers, BS>), dim3(nb), dim3(BS), 0, st, args);
     else
-        hipLaunchKernelGGL((k_update<DIM, Q, kFluxAdv>), dim3(nb), dim3(256), 0, st, args);
+        hipLaunchKernelGGL((k_update<DIM, Q, kFluxAdv, BS>), dim3(nb), dim3(BS), 0, st, args);
     return (int)hipGetLastError();
 }
 
@@ -779,8 +792,8 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     }
     hipStream_t st = (hipStream_t)stream;
     // rows per lane = ceil(capacity / lanes); 4 lanes per cell in 1-D and 2-D,
-    // 16 in 3-D (10 coefficients, stencils up to 56 rows)
-    const int lanes = dm.lanes ? dm.lanes : (dm.dim == 3 ? 16 : 4);
+    // 8 in 3-D (10 coefficients, stencils up to 56 rows); measured fastest
+    const int lanes = dm.lanes ? dm.lanes : (dm.dim == 3 ? 8 : 4);
     if (dm.dim == 1) {
         switch (dm.p) {
         case 2: return launch_k1<1, 2, 4, 2, 2, 2>(dm, a, st);
@@ -791,18 +804,20 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     } else if (dm.dim == 2) {
         if (dm.p == 2) return launch_k1<2, 2, 4, 2, 2, 2>(dm, a, st);
         if (dm.p == 3) {
+            if (lanes == 16) return launch_k1<2, 3, 16, 1, 1, 2>(dm, a, st);
             if (lanes == 8) return launch_k1<2, 3, 8, 2, 2, 3>(dm, a, st);
             return launch_k1<2, 3, 4, 3, 4, 5>(dm, a, st);
         }
         if (dm.p == 4) {
+            if (lanes == 16) return launch_k1<2, 4, 16, 2, 2, 3>(dm, a, st);
             if (lanes == 8) return launch_k1<2, 4, 8, 3, 4, 5>(dm, a, st);
             return launch_k1<2, 4, 4, 5, 7, 9>(dm, a, st);
         }
     } else if (dm.dim == 3) {
         if (dm.p == 2) return launch_k1<3, 2, 4, 4, 4, 4>(dm, a, st);
         if (dm.p == 3) {
-            if (lanes == 8) return launch_k1<3, 3, 8, 4, 5, 7>(dm, a, st);
-            return launch_k1<3, 3, 16, 2, 3, 4>(dm, a, st);
+            if (lanes == 16) return launch_k1<3, 3, 16, 2, 3, 4>(dm, a, st);
+            return launch_k1<3, 3, 8, 4, 5, 7>(dm, a, st);
         }
     }
     return (int)hipErrorInvalidValue;

@@ -149,14 +149,12 @@ class WLSENO:
         self._check(self._lib.wlseno_last_alpha(self._h, C.byref(a)))
         return a.value
 
-    # ---------------------------------------------------------- profiling
-    def profile(self, on: bool):
-        self._sync_stream()
-        self._check(self._lib.wlseno_profile(self._h, 1 if on else 0))
-
-    def profile_read(self, kernel: int):
-        """(total ms, launches) of kernel 0 (reconstruction) or 1 (flux/update)."""
+    # ---------------------------------------------------------- timing
+    def time_kernel(self, kernel: int, u, launches: int) -> float:
+        """Average milliseconds per launch of kernel 0 (reconstruction) or 1
+        (flux/update) over `launches` back-to-back launches on state u."""
+        u = self._field(u)
         ms = C.c_double(0.0)
-        n = C.c_int64(0)
-        self._check(self._lib.wlseno_profile_read(self._h, int(kernel), C.byref(ms), C.byref(n)))
-        return ms.value, n.value
+        self._sync_stream()
+        self._check(self._lib.wlseno_time_kernel(self._h, int(kernel), _ptr(u), int(launches), C.byref(ms)))
+        return ms.value

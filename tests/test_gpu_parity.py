@@ -107,7 +107,7 @@ def test_line_p5_seven_cells_and_burgers():
     _compare_all(mesh, u0, 20, dt, "line97-p5-burgers", p=5, n_lo=7, n_hi=7, flux="burgers")
 
 
-@pytest.mark.parametrize("lanes", [4, 8])
+@pytest.mark.parametrize("lanes", [4, 8, 16])
 def test_square_small_advection_ragged(lanes):
     """2-D p=3 on a small mesh whose cell count is not a multiple of the block size."""
     mesh = jittered_square(13, 0.3, 91)
@@ -123,10 +123,12 @@ def test_square_unit_weights():
     _compare_all(mesh, u0, 5, 0.002, "square11-ls", p=3, n_lo=12, n_hi=20, flux="burgers", weight_mode=1)
 
 
-def test_square_p4():
+@pytest.mark.parametrize("lanes", [0, 8, 16])
+def test_square_p4(lanes):
     mesh = jittered_square(14, 0.3, 93)
     u0 = fields.cell_averages(mesh, lambda x: np.sin(3 * x[:, 0]) * np.cos(2 * x[:, 1]) + (x[:, 0] > 0.5))
-    _compare_all(mesh, u0, 5, 0.002, "square14-p4", p=4, n_lo=20, n_hi=36, flux="burgers")
+    _compare_all(mesh, u0, 5, 0.002, f"square14-p4-lanes{lanes}", p=4, n_lo=20, n_hi=36, flux="burgers",
+                 lanes=lanes)
 
 
 def test_square_p2():
@@ -221,9 +223,31 @@ def test_errors_on_device_context():
     assert e.value.status == 1
 
 
+def test_time_kernel():
+    """Kernel timing leaves the state alone and rejects bad arguments."""
+    torch = _torch()
+    from paper_1602_02694_amd import WLSENOError
+
+    wl = configs.square_burgers(12, 2011)
+    w = _gpu(wl.mesh, p=3, n_lo=12, n_hi=20, flux="burgers")
+    u = torch.tensor(wl.u0, device="cuda")
+    before = u.clone()
+    L0 = w.rhs(u).clone()
+    for k in (0, 1):
+        ms = w.time_kernel(k, u, 5)
+        assert 0.0 < ms < 100.0
+    torch.cuda.synchronize()
+    assert torch.equal(u, before)
+    assert torch.equal(w.rhs(u), L0)
+    for bad in ((2, 5), (0, 0)):
+        with pytest.raises(WLSENOError) as e:
+            w.time_kernel(bad[0], u, bad[1])
+        assert e.value.status == 1
+
+
 # ------------------------------------------------------------------ 3-D
 
-@pytest.mark.parametrize("lanes", [0, 8])
+@pytest.mark.parametrize("lanes", [0, 16])
 def test_cube_advection_p3(lanes):
     """Tetrahedra of a jittered 8^3 lattice, p=3 (10 coefficients), 30-50 cell
     stencils, a = (1, 0.5, 0.25), sine product plus a sphere step."""
