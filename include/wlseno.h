@@ -78,10 +78,11 @@ typedef struct {
     int32_t n_lo, n_hi;  /* stencil size rule: grow rings until >= n_lo cells, keep the n_hi nearest */
     int32_t flux;        /* WLSENO_FLUX_* */
     int32_t weight_mode; /* 0: WLS-ENO weights (eq. weight); 1: unit weights (plain least squares) */
-    int32_t lanes;       /* lanes per cell in the reconstruction kernel: 0 = automatic (4 in 1-D and
-                            2-D, 8 in 3-D); 8 and 16 are also compiled for 2-D p = 3, 4 and
-                            3-D p = 3.  Other values are EINVAL; other (dim, p) pairs use the
-                            automatic choice.  Results agree to rounding either way. */
+    int32_t lanes;       /* lanes per cell in the reconstruction kernel: 0 = automatic (2 for
+                            2-D p = 3, 8 in 3-D, 4 otherwise); 2, 4, 8 and 16 are compiled for
+                            2-D p = 3, 4, 8 and 16 for 2-D p = 4, 8 and 16 for 3-D p = 3.
+                            Other values are EINVAL; a value not compiled for (dim, p) uses
+                            the automatic choice.  Results agree to rounding either way. */
     double eps;          /* epsilon in beta_j = (u_j - u_i)^2 + eps h^2 */
     double alpha_w;      /* centre weight factor alpha > 1 in eq. (weight) */
     double rank_tol;     /* numerical rank: |R_kk| > rank_tol |R_11| */

@@ -108,6 +108,7 @@ void upload_build(wlseno_ctx *c)
     dm.geo = upload(c, b.geo);
     dm.vrel = upload(c, b.vrel);
     dm.normal = upload(c, b.normal);
+    dm.nsum = upload(c, b.nsum);
     dm.rvol = upload(c, b.rvol);
     dm.sptr = upload(c, b.sptr);
     dm.scol = upload(c, b.scol);

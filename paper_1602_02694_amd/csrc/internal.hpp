@@ -74,6 +74,7 @@ struct Build {
     std::vector<int32_t> qperm;     // [F][nc]: 2 bits per point q: sibling's point index of own point q
     std::vector<double> normal;     // [F][nc][dim] outward normals scaled by the facet measure (|f| n);
                                     // the sibling's is the exact negation
+    std::vector<double> nsum;       // [F][nc] sum of the unit normal's components (Burgers bound)
     std::vector<double> area;       // [F][nc] facet measures (host only)
     std::vector<double> rvol;       // nc: 1/|tau|
 };
@@ -94,6 +95,7 @@ struct DevMesh {
     double eh2 = 0.0, alpha_w = 1.5, rank_tol = 1e-12, period = 0.0, gamma = 1.4;
     double vel[3] = {0, 0, 0};
     const double *geo = nullptr, *vrel = nullptr, *normal = nullptr, *rvol = nullptr;   // normal = |f| n
+    const double *nsum = nullptr;   // [F][nc] sum_d n_d of the unit normal
     const int32_t *sptr = nullptr, *scol = nullptr, *sib = nullptr, *qperm = nullptr, *perm = nullptr;
     const int32_t *spad = nullptr;
     int64_t spad_off[kMaxBuckets + 1] = {0, 0, 0, 0};

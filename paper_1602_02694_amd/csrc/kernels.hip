@@ -109,13 +109,14 @@ __device__ __forceinline__ double quad_bcast(double x, int l)
     }
 }
 
-// Sum over a group of G = 4, 8 or 16 lanes.  Beyond the quad, partial sums
+// Sum over a group of G = 2, 4, 8 or 16 lanes.  Beyond the quad, partial sums
 // are exchanged with row_half_mirror (lane i <-> 7-i) and row_mirror
 // (i <-> 15-i): every lane adds the same two operands, so all lanes of the
 // group hold identical bits.
 template <int G>
 __device__ __forceinline__ double group_sum(double x)
 {
+    if constexpr (G == 2) return x + dpp_d<0xB1>(x);   // quad_perm [1,0,3,2]
     x = quad_sum(x);
     if constexpr (G >= 8) x = x + dpp_d<0x141>(x);
     if constexpr (G >= 16) x = x + dpp_d<0x140>(x);
@@ -126,6 +127,10 @@ __device__ __forceinline__ double group_sum(double x)
 template <int G>
 __device__ __forceinline__ double group_bcast(double x, int l, int g)
 {
+    if constexpr (G == 2) {
+        // lane l of this lane's pair: quad_perm [0,0,2,2] or [1,1,3,3]
+        return (l & 1) ? dpp_d<0xF5>(x) : dpp_d<0xA0>(x);
+    }
     const double t = quad_bcast(x, l & 3);          // lane l&3 of this lane's quad
     if constexpr (G == 4) {
         return t;
@@ -140,6 +145,24 @@ __device__ __forceinline__ double group_bcast(double x, int l, int g)
         const int d = (g >> 2) ^ (l >> 2);
         return d == 0 ? t : (d == 1 ? t1 : (d == 3 ? t2 : t3));
     }
+}
+
+// Maximum over the wavefront, valid in lane 0: DPP within rows of 16, then
+// the four row results read back by lane.
+__device__ __forceinline__ double wave_max(double x)
+{
+    x = fmax(x, dpp_d<0xB1>(x));
+    x = fmax(x, dpp_d<0x4E>(x));
+    x = fmax(x, dpp_d<0x141>(x));
+    x = fmax(x, dpp_d<0x140>(x));
+    double m = x;
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(x), 16 * r);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(x), 16 * r);
+        m = fmax(m, __hiloint2double(hi, lo));
+    }
+    return m;
 }
 
 // pw[d][a] = x_d^a / a!
@@ -161,8 +184,16 @@ __device__ __forceinline__ void facet_point(const double *vr, int lf, int q, dou
     if constexpr (DIM == 1) {
         x[0] = vr[lf == 0 ? 1 : 0];
     } else if constexpr (DIM == 2) {
-        const double *a = vr + ((lf + 1) % 3) * 2;
-        const double *b = vr + ((lf + 2) % 3) * 2;
+        // vertices lf+1 and lf+2 (mod 3), picked by selects so that vr may
+        // live in registers
+        const int ia = lf == 2 ? 0 : lf + 1;
+        const int ib = lf == 0 ? 2 : lf - 1;
+        double a[2], b[2];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            a[d] = ia == 0 ? vr[d] : (ia == 1 ? vr[2 + d] : vr[4 + d]);
+            b[d] = ib == 0 ? vr[d] : (ib == 1 ? vr[2 + d] : vr[4 + d]);
+        }
         double t;
         if constexpr (Q == 1) {
             t = 0.5;
@@ -197,7 +228,7 @@ __device__ __forceinline__ double quad_weight(int q)
 
 struct RArgs {
     int64_t nc;
-    const double *u, *geo, *vrel, *normal;
+    const double *u, *geo, *vrel, *nsum;
     const int32_t *spad, *sib, *perm;
     double *fv;
     double *coef_user, *fv_user;
@@ -266,16 +297,60 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
 #pragma unroll
     for (int d = 0; d < DIM; ++d) xc[d] = gc[d];
     const double uc = a.u[c];
+    // vertex offsets for the facet points, loaded up front so that their
+    // latency overlaps the stencil gather (1-D and 2-D: 2 or 6 doubles)
+    constexpr int NVR = DIM < 3 ? F * DIM : 1;
+    double vreg[NVR];
+    if constexpr (DIM < 3) {
+#pragma unroll
+        for (int t = 0; t < NVR; ++t) vreg[t] = a.vrel[c * NVR + t];
+    }
+    // Loads run unconditionally (indices clamped into the cell's own records)
+    // so that every load of a phase is in flight at once: first the facet
+    // siblings and stencil ids, then the neighbours' averages and geometry.
+    int32_t sb[F];
+#pragma unroll
+    for (int lf = 0; lf < F; ++lf) sb[lf] = a.sib[lf * a.nc + c];
+    int32_t jid[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * G + g;
+        jid[s] = srow[r < stride ? r : stride - 1];
+    }
+    double unb[F];
+#pragma unroll
+    for (int lf = 0; lf < F; ++lf) unb[lf] = a.u[sb[lf] >= 0 ? (sb[lf] >> 2) : c];
+    int32_t jrow[RPL];
+    double ug[RPL], gx[RPL][DIM + NMOM];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * G + g;
+        const bool valid = live && r < stride && jid[s] >= 0;
+        jrow[s] = valid ? jid[s] : -1;
+        const int64_t j = valid ? (int64_t)jid[s] : c;
+        ug[s] = a.u[j];
+#pragma unroll
+        for (int t = 0; t < DIM + NMOM; ++t) gx[s][t] = a.geo[j * GS + t];
+    }
+
+    // Burgers: sum of the unit normal's components on this lane's facets
+    constexpr int FPL = (F + G - 1) / G;   // facets per lane (lane g: g, g+G, ...)
+    double nsm[FPL];
+    if constexpr (FLUX == kFluxBurgers) {
+#pragma unroll
+        for (int t = 0; t < FPL; ++t) {
+            const int lf = g + t * G < F ? g + t * G : F - 1;
+            nsm[t] = a.nsum[lf * a.nc + c];
+        }
+    }
+
     // indicator of the centre: smallest over its facet neighbours
     double bmin = -1.0;
 #pragma unroll
     for (int lf = 0; lf < F; ++lf) {
-        const int32_t s = a.sib[lf * a.nc + c];
-        if (s >= 0) {
-            const double du = a.u[s >> 2] - uc;
-            const double bt = du * du + a.eh2;
-            bmin = (bmin < 0.0 || bt < bmin) ? bt : bmin;
-        }
+        const double du = unb[lf] - uc;
+        const double bt = du * du + a.eh2;
+        bmin = (sb[lf] >= 0 && (bmin < 0.0 || bt < bmin)) ? bt : bmin;
     }
     bmin = bmin < 0.0 ? a.eh2 : bmin;
 
@@ -284,21 +359,18 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         const int r = s * G + g;
-        const int32_t jj = (live && r < stride) ? srow[r] : -1;
-        const bool valid = jj >= 0;
-        const int32_t j = valid ? jj : (int32_t)c;
-        const double *gj = a.geo + (int64_t)j * GS;
+        const bool valid = jrow[s] >= 0;
         double dl[DIM];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) dl[d] = gj[d] - xc[d];
+        for (int d = 0; d < DIM; ++d) dl[d] = gx[s][d] - xc[d];
         if constexpr (DIM == 1) {
             const double L = a.period;
             if (L > 0.0) dl[0] = dl[0] > 0.5 * L ? dl[0] - L : (dl[0] < -0.5 * L ? dl[0] + L : dl[0]);
         }
         double nu[NMOM > 0 ? NMOM : 1];
 #pragma unroll
-        for (int t = 0; t < NMOM; ++t) nu[t] = gj[DIM + t];
-        const double uj = a.u[j];
+        for (int t = 0; t < NMOM; ++t) nu[t] = gx[s][DIM + t];
+        const double uj = ug[s];
         double pw[DIM][P];
         scaled_powers<DIM, P>(dl, pw);
         // average over cell j of the Taylor monomial k about x_c:
@@ -493,67 +565,68 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
 #pragma unroll
     for (int k = 0; k < M; ++k)
         if ((k % G) == g) lc[pm[k]] = sc[k] * y[k];
-    __syncthreads();
+    // the G lanes of a cell are in one wavefront, whose LDS accesses complete
+    // in order: a wavefront-scope fence suffices
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double coef[M];
 #pragma unroll
     for (int o = 0; o < M; ++o) coef[o] = lc[o];
 
-    // evaluate at the facet points: lane g handles facet g
-    const int lf = g < F ? g : 0;
-    const double *vr = a.vrel + c * F * DIM;
-    double fq[Q];
+    // evaluate at the facet points: lane g handles facets g, g+G, ...
+    const double *vr = DIM < 3 ? vreg : a.vrel + c * F * DIM;
+    double am = 0.0;   // Burgers: max |u sum_d n_d| over this lane's facet points
+    const bool user = live && (a.coef_user || a.fv_user || a.rank_user);
+    const int64_t uid = user ? (int64_t)a.perm[c] : 0;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        double x[DIM];
-        facet_point<DIM, Q>(vr, lf, q, x);
-        double pw[DIM][P];
-        scaled_powers<DIM, P>(x, pw);
-        double val = 0.0;
+    for (int t = 0; t < FPL; ++t) {
+        const int lf0 = g + t * G;
+        if (FPL * G > F && lf0 >= F) break;   // lanes beyond the last facet
+        const int lf = lf0 < F ? lf0 : 0;
+        double fq[Q];
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            double ph = coef[k];
+        for (int q = 0; q < Q; ++q) {
+            double x[DIM];
+            facet_point<DIM, Q>(vr, lf, q, x);
+            double pw[DIM][P];
+            scaled_powers<DIM, P>(x, pw);
+            double val = 0.0;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) ph *= pw[d][B.e[k][d]];
-            val += ph;
+            for (int k = 0; k < M; ++k) {
+                double ph = coef[k];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) ph *= pw[d][B.e[k][d]];
+                val += ph;
+            }
+            fq[q] = val;
         }
-        fq[q] = val;
-    }
-    const bool writer = live && g < F;
-    if (writer) {
+        if (live) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) a.fv[(lf * a.nc + c) * Q + q] = fq[q];
+            for (int q = 0; q < Q; ++q) a.fv[(lf * a.nc + c) * Q + q] = fq[q];
+            if (a.fv_user) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) a.fv_user[(uid * F + lf) * Q + q] = fq[q];
+            }
+            if constexpr (FLUX == kFluxBurgers) {
+                const double sn = nsm[t];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) am = fmax(am, fabs(fq[q] * sn));
+            }
+        }
     }
-    if (live && (a.coef_user || a.fv_user || a.rank_user)) {
-        const int64_t uid = a.perm[c];
+    if (live) {
         if (a.coef_user) {
 #pragma unroll
             for (int o = 0; o < M; ++o)
                 if ((o % G) == g) a.coef_user[uid * M + o] = coef[o];
         }
-        if (a.fv_user && g < F) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) a.fv_user[(uid * F + lf) * Q + q] = fq[q];
-        }
         if (a.rank_user && g == 0) a.rank_user[uid] = rank;
     }
 
     if constexpr (FLUX == kFluxBurgers) {
-        // global Lax-Friedrichs alpha: max |u sum_d n_d| over all facet points
-        double am = 0.0;
-        if (writer) {
-            double sm = 0.0, mm = 0.0;
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) {
-                const double md = a.normal[(lf * a.nc + c) * DIM + d];   // |f| n
-                sm += md;
-                mm += md * md;
-            }
-            const double sn = sm / sqrt(mm);
-#pragma unroll
-            for (int q = 0; q < Q; ++q) am = fmax(am, fabs(fq[q] * sn));
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) am = fmax(am, __shfl_xor(am, o));
+        // global Lax-Friedrichs alpha: wave maximum into one of the slots
+        am = wave_max(am);
         if ((threadIdx.x & 63) == 0) {
             const int sl = (int)((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % kAlphaSlots);
             atomicMax(a.alpha_acc + sl * 16, (unsigned long long)__double_as_longlong(am));
@@ -770,7 +843,7 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     a.u = u;
     a.geo = dm.geo;
     a.vrel = dm.vrel;
-    a.normal = dm.normal;
+    a.nsum = dm.nsum;
     a.spad = dm.spad;
     a.sib = dm.sib;
     a.perm = dm.perm;
@@ -791,9 +864,11 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
         if (b < kMaxBuckets) a.stride[b] = b < dm.nbuckets ? dm.bucket_cap[b] : 0;
     }
     hipStream_t st = (hipStream_t)stream;
-    // rows per lane = ceil(capacity / lanes); 4 lanes per cell in 1-D and 2-D,
-    // 8 in 3-D (10 coefficients, stencils up to 56 rows); measured fastest
-    const int lanes = dm.lanes ? dm.lanes : (dm.dim == 3 ? 8 : 4);
+    // rows per lane = ceil(capacity / lanes).  Measured fastest: 2 lanes per
+    // cell for 2-D p=3 (6 coefficients), 8 in 3-D (10 coefficients, stencils
+    // up to 56 rows), 4 otherwise.  Fewer lanes replicate less of the
+    // per-column work (pivot search, exchanges, broadcasts) across a cell.
+    const int lanes = dm.lanes ? dm.lanes : (dm.dim == 3 ? 8 : (dm.dim == 2 && dm.p == 3 ? 2 : 4));
     if (dm.dim == 1) {
         switch (dm.p) {
         case 2: return launch_k1<1, 2, 4, 2, 2, 2>(dm, a, st);
@@ -804,6 +879,7 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     } else if (dm.dim == 2) {
         if (dm.p == 2) return launch_k1<2, 2, 4, 2, 2, 2>(dm, a, st);
         if (dm.p == 3) {
+            if (lanes == 2) return launch_k1<2, 3, 2, 6, 8, 10>(dm, a, st);
             if (lanes == 16) return launch_k1<2, 3, 16, 1, 1, 2>(dm, a, st);
             if (lanes == 8) return launch_k1<2, 3, 8, 2, 2, 3>(dm, a, st);
             return launch_k1<2, 3, 4, 3, 4, 5>(dm, a, st);

@@ -438,8 +438,8 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     if (prm.flux != WLSENO_FLUX_ADVECTION && prm.flux != WLSENO_FLUX_BURGERS)
         throw Error{WLSENO_EUNSUPPORTED, "flux must be advection or Burgers"};
     if (prm.weight_mode != 0 && prm.weight_mode != 1) throw inval("weight_mode must be 0 or 1");
-    if (prm.lanes != 0 && prm.lanes != 4 && prm.lanes != 8 && prm.lanes != 16)
-        throw inval("lanes must be 0, 4, 8 or 16");
+    if (prm.lanes != 0 && prm.lanes != 2 && prm.lanes != 4 && prm.lanes != 8 && prm.lanes != 16)
+        throw inval("lanes must be 0, 2, 4, 8 or 16");
     if (!(prm.eps >= 0.0) || !(prm.alpha_w > 0.0) || !(prm.rank_tol >= 0.0))
         throw inval("eps >= 0, alpha_w > 0 and rank_tol >= 0 required");
     Build b;
@@ -608,6 +608,7 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     b.dsib.assign(nc * F, -1);
     b.qperm.assign(nc * F, 0);
     b.normal.assign(nc * F * dim, 0.0);
+    b.nsum.assign(nc * F, 0.0);
     b.area.assign(nc * F, 0.0);
     double min_ins = INFINITY;
     auto own_normal = [&](int64_t u, int lf, double *n, double *ar) {
@@ -651,6 +652,7 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
             if (s < 0) {
                 own_normal(u, lf, n, &ar);
                 for (int k = 0; k < dim; ++k) b.normal[(lf * nc + d) * dim + k] = ar * n[k];
+                for (int k = 0; k < dim; ++k) b.nsum[lf * nc + d] += n[k];
                 b.area[lf * nc + d] = ar;
             } else {
                 int64_t u2 = s >> 2;
@@ -666,6 +668,7 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
                 }
                 // scaled by the facet measure; the sibling's is the exact negation
                 for (int k = 0; k < dim; ++k) b.normal[(lf * nc + d) * dim + k] = ar * n[k];
+                for (int k = 0; k < dim; ++k) b.nsum[lf * nc + d] += n[k];
                 b.area[lf * nc + d] = ar;
                 b.dsib[lf * nc + d] = (int32_t)((d2 << 2) | lf2);
                 // sibling point index of each own point

@@ -107,7 +107,7 @@ def test_line_p5_seven_cells_and_burgers():
     _compare_all(mesh, u0, 20, dt, "line97-p5-burgers", p=5, n_lo=7, n_hi=7, flux="burgers")
 
 
-@pytest.mark.parametrize("lanes", [4, 8, 16])
+@pytest.mark.parametrize("lanes", [2, 4, 8, 16])
 def test_square_small_advection_ragged(lanes):
     """2-D p=3 on a small mesh whose cell count is not a multiple of the block size."""
     mesh = jittered_square(13, 0.3, 91)
@@ -184,11 +184,11 @@ def test_conservation_and_determinism_gpu():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("lanes", [0, 8])
+@pytest.mark.parametrize("lanes", [0, 4, 8])
 def test_square_burgers_full_size(lanes):
     """The benchmark workload: ~19.6k triangles, p=3, Burgers, 12-20 cell stencils.
     One rhs, the reconstruction, and 10 RK3 steps against the oracle, with the
-    automatic lane count (4 lanes per cell) and with 8."""
+    automatic lane count (2 lanes per cell) and with 4 and 8."""
     wl = configs.square_burgers()
     s = wl.settings
     u0 = wl.u0
