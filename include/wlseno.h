@@ -62,7 +62,7 @@ typedef enum {
 enum {
     WLSENO_FLUX_ADVECTION = 0, /* F(u) = a u; Lax-Friedrichs alpha = |a.n| per facet */
     WLSENO_FLUX_BURGERS = 1,   /* F(u) = (u^2/2)(1,..,1); alpha = global max |u sum_d n_d| */
-    WLSENO_FLUX_EULER = 2      /* reserved: conserved-variable Euler system */
+    WLSENO_FLUX_EULER = 2      /* 2-D Euler, conserved variables (rho, rho u, rho v, E), gamma-law gas */
 };
 
 /* mesh flags */
@@ -97,10 +97,11 @@ typedef struct {
     int32_t faces_per_cell;  /* dim + 1 */
     int32_t points_per_face; /* facet quadrature points */
     int32_t min_stencil, max_stencil;
-    int32_t reserved;
+    int32_t n_mesh;          /* meshes in the context (1 unless built from a batch) */
     int64_t n_cell;
     int64_t nnz;             /* total stencil entries */
-    double h;                /* mean edge length used in eps h^2 (1-D: mean width) */
+    double h;                /* mean edge length used in eps h^2 (1-D: mean width); for a
+                                batch each mesh uses its own, and this is the union's */
     double min_insphere;     /* min over cells of 2 dim |tau| / |d tau| (CFL length) */
 } wlseno_info;
 
@@ -175,8 +176,32 @@ wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev);
 wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps);
 
 /* The Lax-Friedrichs alpha used by the last rhs stage (Burgers/Euler; 0 for
- * advection), read back from the device (synchronises the stream). */
+ * advection; for a batch the largest over its meshes), read back from the
+ * device (synchronises the stream). */
 wlseno_status wlseno_last_alpha(wlseno_t ctx, double *alpha);
+
+/* Batches of independent meshes (several meshes stepped by one set of
+ * launches).  Each call appends one mesh (host arrays, copied; no flags) and
+ * returns its index in *mesh_id (nullable).  The meshes must share dim.  The
+ * batch replaces any mesh given by wlseno_mesh_upload, and wlseno_mesh_upload
+ * replaces the batch.  After wlseno_stencil_build every call works on the
+ * concatenation: cells of mesh 0 first, then mesh 1, ...; fields are
+ * double[n_vars][sum of n_cell].  Stencils never cross meshes (they share no
+ * vertex); each mesh uses its own eps h^2 and its own Lax-Friedrichs alpha
+ * (Burgers, Euler).  Sizes: the total must fit 32-bit cell indices, as for a
+ * single mesh.  EINVAL for a bad mesh or a dim that differs from the first. */
+wlseno_status wlseno_batch_add_mesh(wlseno_t ctx, int dim, int64_t n_vert, const double *xyz, int64_t n_cell,
+                                    const int32_t *cells, int32_t *mesh_id);
+
+/* n_steps TVD RK3 steps of the whole batch in place, mesh k with time step
+ * dt_per_mesh[k] (host array of n_mesh finite doubles).  wlseno_step on a
+ * batch uses one dt for every mesh.  EINVAL for null pointers, n_steps < 0 or
+ * a non-finite step. */
+wlseno_status wlseno_batch_step(wlseno_t ctx, double *u_dev, const double *dt_per_mesh, int n_steps);
+
+/* The Lax-Friedrichs alpha of each mesh in the last rhs stage (host array of
+ * n_mesh doubles; 0 for advection).  Synchronises the stream. */
+wlseno_status wlseno_batch_last_alpha(wlseno_t ctx, double *alpha_per_mesh);
 
 /* Kernel timing for measurement.  Reconstructs u_dev (user order, n_cell
  * doubles on the device, not modified) once, then records a HIP event on the

@@ -17,6 +17,7 @@ EXPORTS = [
     "wlseno_params_default", "wlseno_create", "wlseno_destroy", "wlseno_last_error", "wlseno_set_stream",
     "wlseno_mesh_upload", "wlseno_stencil_build", "wlseno_get_info", "wlseno_get_stencil",
     "wlseno_reconstruct", "wlseno_rhs", "wlseno_step", "wlseno_last_alpha", "wlseno_time_kernel",
+    "wlseno_batch_add_mesh", "wlseno_batch_step", "wlseno_batch_last_alpha",
 ]
 
 
@@ -33,7 +34,7 @@ class Info(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("m", C.c_int32), ("n_vars", C.c_int32), ("faces_per_cell", C.c_int32),
         ("points_per_face", C.c_int32), ("min_stencil", C.c_int32), ("max_stencil", C.c_int32),
-        ("reserved", C.c_int32), ("n_cell", C.c_int64), ("nnz", C.c_int64), ("h", C.c_double),
+        ("n_mesh", C.c_int32), ("n_cell", C.c_int64), ("nnz", C.c_int64), ("h", C.c_double),
         ("min_insphere", C.c_double),
     ]
 
@@ -74,6 +75,9 @@ def load():
     lib.wlseno_step.argtypes = [vp, vp, C.c_double, C.c_int]
     lib.wlseno_last_alpha.argtypes = [vp, dp]
     lib.wlseno_time_kernel.argtypes = [vp, C.c_int, vp, C.c_int, dp]
+    lib.wlseno_batch_add_mesh.argtypes = [vp, C.c_int, C.c_int64, dp, C.c_int64, ip, C.POINTER(C.c_int32)]
+    lib.wlseno_batch_step.argtypes = [vp, vp, dp, C.c_int]
+    lib.wlseno_batch_last_alpha.argtypes = [vp, dp]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name not in ("wlseno_params_default", "wlseno_last_error"):

@@ -26,6 +26,15 @@ struct wlseno_ctx {
     std::vector<void *> allocs;
     double *ubuf = nullptr, *kbuf = nullptr, *tbuf = nullptr;
     int last_parity = 0;
+    // batch of independent meshes, concatenated in the order they were added
+    struct Part {
+        int64_t nv, nc;
+    };
+    int batch_dim = 0;
+    std::vector<Part> parts;
+    std::vector<double> batch_xyz;
+    std::vector<int32_t> batch_cells;
+    std::vector<double> dt_host;   // per-mesh time steps last sent to the device
 };
 
 namespace {
@@ -100,6 +109,16 @@ void upload_build(wlseno_ctx *c)
     for (int t = 0; t < kMaxBuckets; ++t) dm.bucket_cap[t] = b.bucket_cap[t];
     for (int t = 0; t <= kMaxBuckets; ++t) dm.bucket_cell0[t] = b.bucket_cell0[t];
     dm.eh2 = b.prm.eps * m.h * m.h;
+    dm.nmesh = m.nmesh;
+    dm.slots_per_mesh = m.nmesh > 1 ? kAlphaSlotsBatch : kAlphaSlots;
+    if (m.nmesh > 1) {
+        std::vector<double> eh2(m.nmesh);
+        for (int k = 0; k < m.nmesh; ++k) eh2[k] = b.prm.eps * m.mesh_h[k] * m.mesh_h[k];
+        dm.mid = upload(c, b.mid);
+        dm.eh2_tab = upload(c, eh2);
+        dm.dt_tab = (double *)dev_alloc(c, m.nmesh * sizeof(double));
+        c->dt_host.assign(m.nmesh, NAN);
+    }
     dm.alpha_w = b.prm.alpha_w;
     dm.rank_tol = b.prm.rank_tol;
     dm.period = m.periodic ? m.period : 0.0;
@@ -119,8 +138,9 @@ void upload_build(wlseno_ctx *c)
     dm.perm = upload(c, b.perm);
     const size_t nfv = (size_t)b.nvars * m.nc * b.nf * b.nq;
     dm.fv = (double *)dev_alloc(c, nfv * sizeof(double));
-    dm.alpha = (unsigned long long *)dev_alloc(c, 2 * kAlphaSlots * 16 * sizeof(unsigned long long));
-    check_hip(hipMemset(dm.alpha, 0, 2 * kAlphaSlots * 16 * sizeof(unsigned long long)), "hipMemset");
+    const size_t nslot = 2 * (size_t)dm.alpha_slots() * 16;
+    dm.alpha = (unsigned long long *)dev_alloc(c, nslot * sizeof(unsigned long long));
+    check_hip(hipMemset(dm.alpha, 0, nslot * sizeof(unsigned long long)), "hipMemset");
     const size_t nu = (size_t)b.nvars * m.nc;
     c->ubuf = (double *)dev_alloc(c, nu * sizeof(double));
     c->kbuf = (double *)dev_alloc(c, nu * sizeof(double));
@@ -242,6 +262,48 @@ wlseno_status wlseno_mesh_upload(wlseno_t ctx, int dim, int64_t n_vert, const do
     ctx->have_mesh = true;
     ctx->have_build = false;
     ctx->build = Build{};
+    ctx->parts.clear();
+    ctx->batch_xyz.clear();
+    ctx->batch_cells.clear();
+    API_END(ctx)
+}
+
+wlseno_status wlseno_batch_add_mesh(wlseno_t ctx, int dim, int64_t n_vert, const double *xyz, int64_t n_cell,
+                                    const int32_t *cells, int32_t *mesh_id)
+{
+    API_BEGIN(ctx)
+    // validates the mesh on its own and gives its mean edge length
+    HostMesh one;
+    mesh_setup(one, dim, n_vert, xyz, n_cell, cells, 0);
+    if (!ctx->parts.empty() && dim != ctx->batch_dim) throw Error{WLSENO_EINVAL, "all meshes of a batch share dim"};
+    int64_t nv0 = 0, nc0 = 0;
+    for (const auto &pt : ctx->parts) {
+        nv0 += pt.nv;
+        nc0 += pt.nc;
+    }
+    if (nc0 + n_cell > (int64_t)(INT32_MAX / 8) || nv0 + n_vert > (int64_t)INT32_MAX)
+        throw Error{WLSENO_EINVAL, "batch too large for 32-bit indices"};
+    ctx->batch_dim = dim;
+    ctx->batch_xyz.insert(ctx->batch_xyz.end(), xyz, xyz + n_vert * dim);
+    for (int64_t t = 0; t < n_cell * (dim + 1); ++t) ctx->batch_cells.push_back((int32_t)(cells[t] + nv0));
+    ctx->parts.push_back({n_vert, n_cell});
+    // the union of the meshes so far (disjoint, so stencils stay within a mesh)
+    HostMesh m;
+    mesh_setup(m, dim, nv0 + n_vert, ctx->batch_xyz.data(), nc0 + n_cell, ctx->batch_cells.data(), 0);
+    m.nmesh = (int)ctx->parts.size();
+    m.mesh_of.resize(m.nc);
+    m.mesh_h = ctx->mesh.mesh_h;
+    if (ctx->parts.size() == 1) m.mesh_h.clear();
+    m.mesh_h.push_back(one.h);
+    int64_t at = 0;
+    for (int k = 0; k < m.nmesh; ++k)
+        for (int64_t i = 0; i < ctx->parts[k].nc; ++i) m.mesh_of[at++] = k;
+    free_device(ctx);
+    ctx->mesh = std::move(m);
+    ctx->have_mesh = true;
+    ctx->have_build = false;
+    ctx->build = Build{};
+    if (mesh_id) *mesh_id = (int32_t)ctx->parts.size() - 1;
     API_END(ctx)
 }
 
@@ -273,6 +335,7 @@ wlseno_status wlseno_get_info(wlseno_t ctx, wlseno_info *out)
     out->points_per_face = b.nq;
     out->min_stencil = b.min_stencil;
     out->max_stencil = b.max_stencil;
+    out->n_mesh = ctx->mesh.nmesh;
     out->n_cell = ctx->mesh.nc;
     out->nnz = (int64_t)b.col.size();
     out->h = ctx->mesh.h;
@@ -317,6 +380,45 @@ wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev)
     API_END(ctx)
 }
 
+namespace {
+
+// n_steps of TVD RK3; dt_mesh (batches) holds one time step per mesh.
+void run_steps(wlseno_ctx *ctx, double *u_dev, double dt, const double *dt_mesh, int n_steps)
+{
+    const bool batch = ctx->dm.nmesh > 1;
+    if (batch) {
+        bool changed = false;
+        for (int k = 0; k < ctx->dm.nmesh; ++k) {
+            const double v = dt_mesh ? dt_mesh[k] : dt;
+            if (!std::isfinite(v)) throw Error{WLSENO_EINVAL, "time steps must be finite"};
+            changed = changed || !(ctx->dt_host[k] == v);
+            ctx->dt_host[k] = v;
+        }
+        if (changed)
+            check_hip(hipMemcpyAsync(ctx->dm.dt_tab, ctx->dt_host.data(), ctx->dt_host.size() * sizeof(double),
+                                     hipMemcpyHostToDevice, ctx->stream),
+                      "hipMemcpyAsync");
+    }
+    // stage coefficients c dt; for a batch the kernel multiplies c by the mesh's dt
+    const double h = batch ? 1.0 : dt;
+    double *u = ctx->ubuf, *k = ctx->kbuf;
+    check_launch(launch_permute(ctx->dm, u_dev, u, true, ctx->stream), "permute");
+    check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
+    int par = 0;
+    for (int s = 0; s < n_steps; ++s) {
+        // k1 = u + dt L(u); k2 = 3/4 u + 1/4 k1 + 1/4 dt L(k1); u = 1/3 u + 2/3 k2 + 2/3 dt L(k2)
+        stage(ctx, u, u, u, k, 1.0, 0.0, h, 1, par);
+        par ^= 1;
+        stage(ctx, k, u, k, k, 0.75, 0.25, 0.25 * h, 1, par);
+        par ^= 1;
+        stage(ctx, k, u, k, u, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * h, 1, par);
+        par ^= 1;
+    }
+    check_launch(launch_permute(ctx->dm, u, u_dev, false, ctx->stream), "permute");
+}
+
+}  // namespace
+
 wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps)
 {
     API_BEGIN(ctx)
@@ -324,40 +426,68 @@ wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps)
     if (!std::isfinite(dt) || n_steps < 0) throw Error{WLSENO_EINVAL, "dt must be finite and n_steps >= 0"};
     need_device(ctx);
     if (n_steps == 0) return WLSENO_OK;
-    double *u = ctx->ubuf, *k = ctx->kbuf;
-    check_launch(launch_permute(ctx->dm, u_dev, u, true, ctx->stream), "permute");
-    check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
-    int par = 0;
-    for (int s = 0; s < n_steps; ++s) {
-        // k1 = u + dt L(u); k2 = 3/4 u + 1/4 k1 + 1/4 dt L(k1); u = 1/3 u + 2/3 k2 + 2/3 dt L(k2)
-        stage(ctx, u, u, u, k, 1.0, 0.0, dt, 1, par);
-        par ^= 1;
-        stage(ctx, k, u, k, k, 0.75, 0.25, 0.25 * dt, 1, par);
-        par ^= 1;
-        stage(ctx, k, u, k, u, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt, 1, par);
-        par ^= 1;
-    }
-    check_launch(launch_permute(ctx->dm, u, u_dev, false, ctx->stream), "permute");
+    run_steps(ctx, u_dev, dt, nullptr, n_steps);
     API_END(ctx)
 }
+
+wlseno_status wlseno_batch_step(wlseno_t ctx, double *u_dev, const double *dt_per_mesh, int n_steps)
+{
+    API_BEGIN(ctx)
+    if (!u_dev || !dt_per_mesh) throw Error{WLSENO_EINVAL, "null pointer"};
+    if (n_steps < 0) throw Error{WLSENO_EINVAL, "n_steps >= 0 required"};
+    need_device(ctx);
+    for (int k = 0; k < ctx->mesh.nmesh; ++k)
+        if (!std::isfinite(dt_per_mesh[k])) throw Error{WLSENO_EINVAL, "time steps must be finite"};
+    if (n_steps == 0) return WLSENO_OK;
+    if (ctx->dm.nmesh == 1)
+        run_steps(ctx, u_dev, dt_per_mesh[0], nullptr, n_steps);
+    else
+        run_steps(ctx, u_dev, 0.0, dt_per_mesh, n_steps);
+    API_END(ctx)
+}
+
+namespace {
+
+// Per-mesh maxima of the alpha slots of the last stage's parity.
+std::vector<double> read_alpha(wlseno_ctx *ctx)
+{
+    const DevMesh &dm = ctx->dm;
+    const size_t n = (size_t)dm.alpha_slots();
+    std::vector<unsigned long long> slots(n * 16);
+    check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    check_hip(hipMemcpy(slots.data(), dm.alpha + (size_t)ctx->last_parity * n * 16,
+                        slots.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost),
+              "hipMemcpy");
+    std::vector<double> out(dm.nmesh, 0.0);
+    for (int k = 0; k < dm.nmesh; ++k)
+        for (int t = 0; t < dm.slots_per_mesh; ++t) {
+            double v;
+            std::memcpy(&v, &slots[((size_t)k * dm.slots_per_mesh + t) * 16], sizeof(double));
+            out[k] = v > out[k] ? v : out[k];
+        }
+    return out;
+}
+
+}  // namespace
 
 wlseno_status wlseno_last_alpha(wlseno_t ctx, double *alpha)
 {
     API_BEGIN(ctx)
     if (!alpha) throw Error{WLSENO_EINVAL, "alpha is NULL"};
     need_device(ctx);
-    std::vector<unsigned long long> slots(kAlphaSlots * 16);
-    check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    check_hip(hipMemcpy(slots.data(), ctx->dm.alpha + (size_t)ctx->last_parity * kAlphaSlots * 16,
-                        slots.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost),
-              "hipMemcpy");
     double a = 0.0;
-    for (int s = 0; s < kAlphaSlots; ++s) {
-        double v;
-        std::memcpy(&v, &slots[s * 16], sizeof(double));
-        a = v > a ? v : a;
-    }
+    for (double v : read_alpha(ctx)) a = v > a ? v : a;
     *alpha = a;
+    API_END(ctx)
+}
+
+wlseno_status wlseno_batch_last_alpha(wlseno_t ctx, double *alpha_per_mesh)
+{
+    API_BEGIN(ctx)
+    if (!alpha_per_mesh) throw Error{WLSENO_EINVAL, "alpha_per_mesh is NULL"};
+    need_device(ctx);
+    const std::vector<double> a = read_alpha(ctx);
+    for (size_t k = 0; k < a.size(); ++k) alpha_per_mesh[k] = a[k];
     API_END(ctx)
 }
 

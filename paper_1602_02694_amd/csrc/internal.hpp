@@ -43,6 +43,11 @@ struct HostMesh {
     std::vector<int32_t> e2c_ptr, e2c;   // 3-D: edge -> incident cells
     std::vector<int32_t> cell_edges;     // 3-D: nc*6 edge ids
     double h = 0.0;                  // mean edge length (1-D: mean width)
+    // batches of independent meshes: mesh of each cell (user order; empty for
+    // one mesh) and each mesh's own mean edge length
+    int nmesh = 1;
+    std::vector<int32_t> mesh_of;
+    std::vector<double> mesh_h;
 };
 
 // Everything derived for one parameter set, in device cell order.
@@ -77,6 +82,7 @@ struct Build {
     std::vector<double> nsum;       // [F][nc] sum of the unit normal's components (Burgers bound)
     std::vector<double> area;       // [F][nc] facet measures (host only)
     std::vector<double> rvol;       // nc: 1/|tau|
+    std::vector<int32_t> mid;       // batches: mesh of each device cell (empty for one mesh)
 };
 
 void mesh_setup(HostMesh &mesh, int dim, int64_t nv, const double *xyz, int64_t nc,
@@ -100,10 +106,18 @@ struct DevMesh {
     const int32_t *spad = nullptr;
     int64_t spad_off[kMaxBuckets + 1] = {0, 0, 0, 0};
     double *fv = nullptr;                  // [nvars][F][nc][Q], device order
-    unsigned long long *alpha = nullptr;   // 2 parities x 64 slots of max bits
+    // Lax-Friedrichs alpha maxima (u64 bits, one slot per 128 bytes): two
+    // parities of nmesh x slots_per_mesh slots
+    unsigned long long *alpha = nullptr;
+    int nmesh = 1, slots_per_mesh = 64;
+    const int32_t *mid = nullptr;          // batches: mesh of each device cell
+    const double *eh2_tab = nullptr;       // batches: eps h^2 of each mesh
+    double *dt_tab = nullptr;              // batches: time step of each mesh
+    int64_t alpha_slots() const { return (int64_t)nmesh * slots_per_mesh; }
 };
 
-constexpr int kAlphaSlots = 64;
+constexpr int kAlphaSlots = 64;       // slots of a single mesh
+constexpr int kAlphaSlotsBatch = 8;   // slots per mesh of a batch
 
 // Returns hipSuccess (0) or an error code; `supported` tells whether the
 // (dim, p, stencil size) combination has a compiled variant.
@@ -113,6 +127,7 @@ int launch_clear_alpha(const DevMesh &dm, void *stream);
 int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *coef_user,
                        double *fv_user, int32_t *rank_user, void *stream);
 // out = L (mode 0) or A*u0 + B*prev + Cdt*L (mode 1).
+// Batches: Cdt is the stage coefficient, multiplied by each mesh's time step.
 int launch_update(const DevMesh &dm, const double *u0, const double *prev, double *out, double A,
                   double B, double Cdt, int mode, int parity, void *stream);
 

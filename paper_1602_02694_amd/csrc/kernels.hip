@@ -33,6 +33,7 @@ namespace {
 constexpr int kFluxAdv = WLSENO_FLUX_ADVECTION;
 constexpr double kPivotTie = 1e-10;
 constexpr int kFluxBurgers = WLSENO_FLUX_BURGERS;
+constexpr int kFluxEuler = WLSENO_FLUX_EULER;
 
 constexpr int binom(int n, int k)
 {
@@ -177,23 +178,14 @@ __device__ __forceinline__ void scaled_powers(const double (&x)[DIM], double (&p
     }
 }
 
-// Facet point q of facet lf, relative to the centroid.
+// Point q of a 1-D or 2-D facet with end points a and b (relative to the
+// centroid): 1-D the point itself; 2-D Gauss-Legendre nodes along the edge.
 template <int DIM, int Q>
-__device__ __forceinline__ void facet_point(const double *vr, int lf, int q, double (&x)[DIM])
+__device__ __forceinline__ void edge_point(const double (&a)[DIM], const double (&b)[DIM], int q, double (&x)[DIM])
 {
     if constexpr (DIM == 1) {
-        x[0] = vr[lf == 0 ? 1 : 0];
-    } else if constexpr (DIM == 2) {
-        // vertices lf+1 and lf+2 (mod 3), picked by selects so that vr may
-        // live in registers
-        const int ia = lf == 2 ? 0 : lf + 1;
-        const int ib = lf == 0 ? 2 : lf - 1;
-        double a[2], b[2];
-#pragma unroll
-        for (int d = 0; d < 2; ++d) {
-            a[d] = ia == 0 ? vr[d] : (ia == 1 ? vr[2 + d] : vr[4 + d]);
-            b[d] = ib == 0 ? vr[d] : (ib == 1 ? vr[2 + d] : vr[4 + d]);
-        }
+        x[0] = a[0];
+    } else {
         double t;
         if constexpr (Q == 1) {
             t = 0.5;
@@ -203,18 +195,25 @@ __device__ __forceinline__ void facet_point(const double *vr, int lf, int q, dou
             t = q == 0 ? 0.5 - h : 0.5 + h;
         }
 #pragma unroll
-        for (int d = 0; d < 2; ++d) x[d] = a[d] + t * (b[d] - a[d]);
-    } else {
+        for (int d = 0; d < DIM; ++d) x[d] = a[d] + t * (b[d] - a[d]);
+    }
+}
+
+// Point q of facet lf of a tetrahedron (vertex offsets vr from the centroid):
+// the degree-2 rule with barycentric coordinates (2/3, 1/6, 1/6).
+template <int DIM, int Q>
+__device__ __forceinline__ void facet_point(const double *vr, int lf, int q, double (&x)[DIM])
+{
+    static_assert(DIM == 3, "tetrahedral facets only");
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            double s = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double s = 0.0;
 #pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const double w = (t == q) ? (2.0 / 3.0) : (1.0 / 6.0);
-                s += w * vr[((lf + 1 + t) % 4) * 3 + d];
-            }
-            x[d] = s;
+        for (int t = 0; t < 3; ++t) {
+            const double w = (t == q) ? (2.0 / 3.0) : (1.0 / 6.0);
+            s += w * vr[((lf + 1 + t) % 4) * 3 + d];
         }
+        x[d] = s;
     }
 }
 
@@ -228,13 +227,16 @@ __device__ __forceinline__ double quad_weight(int q)
 
 struct RArgs {
     int64_t nc;
-    const double *u, *geo, *vrel, *nsum;
+    const double *u, *geo, *vrel, *nsum, *normal;
     const int32_t *spad, *sib, *perm;
     double *fv;
     double *coef_user, *fv_user;
     int32_t *rank_user;
-    unsigned long long *alpha_acc;   // 64 slots (stride 16) of this stage's parity
-    double eh2, alpha_w, rank_tol, period;
+    unsigned long long *alpha_acc;   // this stage's parity: nmesh x spm slots (stride 16)
+    const int32_t *mid;              // batches: mesh of each cell (else null)
+    const double *eh2_tab;           // batches: eps h^2 per mesh
+    int spm;                         // alpha slots per mesh
+    double eh2, alpha_w, rank_tol, period, gamma;
     int weight_mode;
     // stencil-size buckets: cells [cell0[b], cell0[b+1]) run with rpl[b] rows
     // per lane, in workgroups [blk0[b], blk0[b+1])
@@ -275,7 +277,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 }
 
 // --------------------------------------------------------------- K1
-// Reconstruction of one cell by the 4 lanes of a quad (g = lane in the quad).
+// Reconstruction of one cell by a group of G lanes (g = lane in the group),
+// component by component (V = 1, or DIM + 2 conserved variables for Euler).
 template <int DIM, int P, int G, int RPL, int FLUX>
 __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, int64_t cell_begin, int64_t cell_end,
                                                  const int32_t *spad, int stride, int g, double *lds, int slot)
@@ -287,61 +290,88 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     constexpr int NMOM = M - 1 - DIM;
     constexpr int GS = geo_stride<DIM, P>();
     constexpr int RS = (M + G - 1) / G;
+    constexpr int V = FLUX == kFluxEuler ? DIM + 2 : 1;
+    constexpr int CPB = 256 / G;
 
     const bool live = cell < cell_end;
     const int64_t c = live ? cell : cell_end - 1;
     const int32_t *srow = spad + (c - cell_begin) * stride;
+    const int64_t N = a.nc;
+    const int32_t mesh = a.mid ? a.mid[c] : 0;
+    const double eh2 = a.mid ? a.eh2_tab[mesh] : a.eh2;
 
     const double *gc = a.geo + c * GS;
     double xc[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) xc[d] = gc[d];
-    const double uc = a.u[c];
-    // vertex offsets for the facet points, loaded up front so that their
-    // latency overlaps the stencil gather (1-D and 2-D: 2 or 6 doubles)
-    constexpr int NVR = DIM < 3 ? F * DIM : 1;
-    double vreg[NVR];
-    if constexpr (DIM < 3) {
+    // 1-D and 2-D: the end points of this lane's facets, relative to the
+    // centroid (1-D: the facet point itself; 2-D: the edge's two vertices).
+    // With one facet per lane they are loaded up front, so that their latency
+    // overlaps the gather; with more, at the evaluation (registers).
+    constexpr int FPL = (F + G - 1) / G;   // facets per lane (lane g: g, g+G, ...)
+    constexpr bool kEarly = FPL == 1;
+    double ea[FPL][DIM], eb[FPL][DIM];
+    auto load_ends = [&](int t) {
+        const int lf = g + t * G < F ? g + t * G : F - 1;
+        const int ia = DIM == 1 ? (lf == 0 ? 1 : 0) : (lf == 2 ? 0 : lf + 1);
+        const int ib = DIM == 1 ? ia : (lf == 0 ? 2 : lf - 1);
 #pragma unroll
-        for (int t = 0; t < NVR; ++t) vreg[t] = a.vrel[c * NVR + t];
-    }
+        for (int d = 0; d < DIM; ++d) {
+            ea[t][d] = a.vrel[(c * F + ia) * DIM + d];
+            eb[t][d] = a.vrel[(c * F + ib) * DIM + d];
+        }
+    };
+    if constexpr (DIM < 3 && kEarly) load_ends(0);
     // Loads run unconditionally (indices clamped into the cell's own records)
     // so that every load of a phase is in flight at once: first the facet
     // siblings and stencil ids, then the neighbours' averages and geometry.
     int32_t sb[F];
 #pragma unroll
-    for (int lf = 0; lf < F; ++lf) sb[lf] = a.sib[lf * a.nc + c];
+    for (int lf = 0; lf < F; ++lf) sb[lf] = a.sib[lf * N + c];
     int32_t jid[RPL];
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         const int r = s * G + g;
         jid[s] = srow[r < stride ? r : stride - 1];
     }
-    double unb[F];
-#pragma unroll
-    for (int lf = 0; lf < F; ++lf) unb[lf] = a.u[sb[lf] >= 0 ? (sb[lf] >> 2) : c];
     int32_t jrow[RPL];
-    double ug[RPL], gx[RPL][DIM + NMOM];
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         const int r = s * G + g;
-        const bool valid = live && r < stride && jid[s] >= 0;
-        jrow[s] = valid ? jid[s] : -1;
-        const int64_t j = valid ? (int64_t)jid[s] : c;
-        ug[s] = a.u[j];
+        jrow[s] = (live && r < stride && jid[s] >= 0) ? jid[s] : -1;
+    }
+    // Burgers: sum of the unit normal's components; Euler: the area-scaled
+    // normal, on this lane's facets (for the Lax-Friedrichs alpha bound)
+    double nsm[FPL];
+    double nrm[FLUX == kFluxEuler ? FPL : 1][DIM];
+#pragma unroll
+    for (int t = 0; t < FPL; ++t) {
+        const int lf = g + t * G < F ? g + t * G : F - 1;
+        if constexpr (FLUX == kFluxBurgers) nsm[t] = a.nsum[lf * N + c];
+        if constexpr (FLUX == kFluxEuler) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) nrm[t][d] = a.normal[(lf * N + c) * DIM + d];
+        }
+    }
+    double *lfv = lds + (CPB * M) + slot * (V * F * Q);   // systems: this cell's facet values, [V][F][Q]
+    double am = 0.0;   // Lax-Friedrichs alpha bound over this lane's facet points
+    const bool user = live && (a.fv_user || a.rank_user || a.coef_user);
+    const int64_t uid = user ? (int64_t)a.perm[c] : 0;
+
+#pragma unroll 1
+    for (int v = 0; v < V; ++v) {
+    const double *uv = a.u + (int64_t)v * N;
+    const double uc = uv[c];
+    double unb[F];
+#pragma unroll
+    for (int lf = 0; lf < F; ++lf) unb[lf] = uv[sb[lf] >= 0 ? (sb[lf] >> 2) : c];
+    double ug[RPL], gx[RPL][DIM + NMOM];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int64_t j = jrow[s] >= 0 ? (int64_t)jrow[s] : c;
+        ug[s] = uv[j];
 #pragma unroll
         for (int t = 0; t < DIM + NMOM; ++t) gx[s][t] = a.geo[j * GS + t];
-    }
-
-    // Burgers: sum of the unit normal's components on this lane's facets
-    constexpr int FPL = (F + G - 1) / G;   // facets per lane (lane g: g, g+G, ...)
-    double nsm[FPL];
-    if constexpr (FLUX == kFluxBurgers) {
-#pragma unroll
-        for (int t = 0; t < FPL; ++t) {
-            const int lf = g + t * G < F ? g + t * G : F - 1;
-            nsm[t] = a.nsum[lf * a.nc + c];
-        }
     }
 
     // indicator of the centre: smallest over its facet neighbours
@@ -349,10 +379,10 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
 #pragma unroll
     for (int lf = 0; lf < F; ++lf) {
         const double du = unb[lf] - uc;
-        const double bt = du * du + a.eh2;
+        const double bt = du * du + eh2;
         bmin = (sb[lf] >= 0 && (bmin < 0.0 || bt < bmin)) ? bt : bmin;
     }
-    bmin = bmin < 0.0 ? a.eh2 : bmin;
+    bmin = bmin < 0.0 ? eh2 : bmin;
 
     // weighted rows  W A  and  W u
     double A[RPL][M], bv[RPL];
@@ -396,7 +426,7 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
         if (a.weight_mode == 0) {
             const double du = uj - uc;
             const double num = (r == 0) ? a.alpha_w : 1.0;
-            const double den = (r == 0) ? bmin : du * du + a.eh2;
+            const double den = (r == 0) ? bmin : du * du + eh2;
             w = num * rcp_nr(den);
         }
         w = valid ? w : 0.0;
@@ -573,22 +603,24 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     double coef[M];
 #pragma unroll
     for (int o = 0; o < M; ++o) coef[o] = lc[o];
+    if (live && a.rank_user && g == 0) a.rank_user[(int64_t)v * N + uid] = rank;
 
     // evaluate at the facet points: lane g handles facets g, g+G, ...
-    const double *vr = DIM < 3 ? vreg : a.vrel + c * F * DIM;
-    double am = 0.0;   // Burgers: max |u sum_d n_d| over this lane's facet points
-    const bool user = live && (a.coef_user || a.fv_user || a.rank_user);
-    const int64_t uid = user ? (int64_t)a.perm[c] : 0;
 #pragma unroll
     for (int t = 0; t < FPL; ++t) {
         const int lf0 = g + t * G;
         if (FPL * G > F && lf0 >= F) break;   // lanes beyond the last facet
         const int lf = lf0 < F ? lf0 : 0;
-        double fq[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             double x[DIM];
-            facet_point<DIM, Q>(vr, lf, q, x);
+            if constexpr (DIM < 3 && !kEarly) {
+                if (q == 0) load_ends(t);
+            }
+            if constexpr (DIM < 3)
+                edge_point<DIM, Q>(ea[t], eb[t], q, x);
+            else
+                facet_point<DIM, Q>(a.vrel + c * F * DIM, lf, q, x);
             double pw[DIM][P];
             scaled_powers<DIM, P>(x, pw);
             double val = 0.0;
@@ -599,37 +631,114 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
                 for (int d = 0; d < DIM; ++d) ph *= pw[d][B.e[k][d]];
                 val += ph;
             }
-            fq[q] = val;
-        }
-        if (live) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) a.fv[(lf * a.nc + c) * Q + q] = fq[q];
-            if (a.fv_user) {
-#pragma unroll
-                for (int q = 0; q < Q; ++q) a.fv_user[(uid * F + lf) * Q + q] = fq[q];
-            }
-            if constexpr (FLUX == kFluxBurgers) {
-                const double sn = nsm[t];
-#pragma unroll
-                for (int q = 0; q < Q; ++q) am = fmax(am, fabs(fq[q] * sn));
+            if constexpr (V == 1) {
+                // scalar: straight out, with the Burgers alpha bound
+                if (live) {
+                    a.fv[(lf * N + c) * Q + q] = val;
+                    if (a.fv_user) a.fv_user[(uid * F + lf) * Q + q] = val;
+                    if constexpr (FLUX == kFluxBurgers) am = fmax(am, fabs(val * nsm[t]));
+                }
+            } else {
+                lfv[(v * F + lf) * Q + q] = val;
             }
         }
     }
-    if (live) {
-        if (a.coef_user) {
+    if (live && a.coef_user) {
 #pragma unroll
-            for (int o = 0; o < M; ++o)
-                if ((o % G) == g) a.coef_user[uid * M + o] = coef[o];
+        for (int o = 0; o < M; ++o)
+            if ((o % G) == g) a.coef_user[((int64_t)v * N + uid) * M + o] = coef[o];
+    }
+    }   // components
+
+    if constexpr (V > 1) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // Euler: keep the cell averages at every facet point when any facet
+    // state of the reconstruction has non-positive density or pressure
+    bool fallback = false;
+    {
+        double bad = 0.0;
+#pragma unroll
+        for (int t = 0; t < FPL; ++t) {
+            const int lf0 = g + t * G;
+            if (FPL * G > F && lf0 >= F) break;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                double U[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) U[v] = lfv[(v * F + lf0) * Q + q];
+                double ke = 0.0;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) ke += U[1 + d] * U[1 + d];
+                ke = 0.5 * ke / U[0];
+                const double pr = (a.gamma - 1.0) * (U[DIM + 1] - ke);
+                bad = (U[0] > 0.0 && pr > 0.0) ? bad : 1.0;
+            }
         }
-        if (a.rank_user && g == 0) a.rank_user[uid] = rank;
+        fallback = group_sum<G>(bad) > 0.0;
     }
 
-    if constexpr (FLUX == kFluxBurgers) {
-        // global Lax-Friedrichs alpha: wave maximum into one of the slots
-        am = wave_max(am);
-        if ((threadIdx.x & 63) == 0) {
-            const int sl = (int)((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % kAlphaSlots);
-            atomicMax(a.alpha_acc + sl * 16, (unsigned long long)__double_as_longlong(am));
+    // facet values out, Lax-Friedrichs alpha bound over this lane's points
+#pragma unroll
+    for (int t = 0; t < FPL; ++t) {
+        const int lf0 = g + t * G;
+        if (FPL * G > F && lf0 >= F) break;
+        const int lf = lf0 < F ? lf0 : 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            double U[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) U[v] = fallback ? a.u[(int64_t)v * N + c] : lfv[(v * F + lf) * Q + q];
+            if (live) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) a.fv[((v * F + lf) * N + c) * Q + q] = U[v];
+                if (a.fv_user) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) a.fv_user[(((int64_t)v * N + uid) * F + lf) * Q + q] = U[v];
+                }
+                if constexpr (FLUX == kFluxEuler) {
+                    // |v.n| + c with the unit normal n = m / |m|
+                    double mn = 0.0, mm = 0.0;
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d) {
+                        mn += U[1 + d] * nrm[t][d];
+                        mm += nrm[t][d] * nrm[t][d];
+                    }
+                    double ke = 0.0;
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d) ke += U[1 + d] * U[1 + d];
+                    ke = 0.5 * ke / U[0];
+                    const double pr = (a.gamma - 1.0) * (U[DIM + 1] - ke);
+                    const double sr = fabs(mn / U[0]) / sqrt(mm) + sqrt(a.gamma * pr / U[0]);
+                    am = fmax(am, sr);   // fmax ignores a NaN bound
+                }
+            }
+        }
+    }
+    if (live && a.coef_user && fallback) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int o = 0; o < M; ++o)
+                if ((o % G) == g)
+                    a.coef_user[((int64_t)v * N + uid) * M + o] = o == 0 ? a.u[(int64_t)v * N + c] : 0.0;
+    }
+    }   // systems
+
+    if constexpr (FLUX != kFluxAdv) {
+        // global Lax-Friedrichs alpha of the cell's mesh: the wave maximum into
+        // one of the mesh's slots; a wave that spans meshes (batches, at mesh
+        // boundaries) posts lane by lane
+        const int wv = (int)((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % a.spm);
+        const int m0 = __builtin_amdgcn_readfirstlane(mesh);
+        if (__ballot(mesh != m0) == 0) {
+            am = wave_max(am);
+            if ((threadIdx.x & 63) == 0)
+                atomicMax(a.alpha_acc + ((int64_t)m0 * a.spm + wv) * 16, (unsigned long long)__double_as_longlong(am));
+        } else if (am > 0.0) {
+            atomicMax(a.alpha_acc + ((int64_t)mesh * a.spm + wv) * 16, (unsigned long long)__double_as_longlong(am));
         }
     }
 }
@@ -639,7 +748,8 @@ template <int DIM, int P, int FLUX, int G, int R0, int R1, int R2>
 __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
 {
     constexpr int CPB = 256 / G;   // cells per workgroup
-    __shared__ double lds[CPB * Basis<DIM, P>::M];
+    // per cell: M coefficients; for the Euler system also its facet values [V][F][Q]
+    __shared__ double lds[CPB * (Basis<DIM, P>::M + (FLUX == kFluxEuler ? (DIM + 2) * (DIM + 1) * num_q<DIM, P>() : 0))];
     const int L = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int g = (int)(threadIdx.x % G);
     const int slot = (int)(threadIdx.x / G);
@@ -665,25 +775,49 @@ struct UArgs {
     const int32_t *sib, *qperm;
     const double *u0, *prev;
     double *out;
-    const unsigned long long *alpha_rd;   // this stage's parity (64 slots, stride 16)
+    const unsigned long long *alpha_rd;   // this stage's parity (nmesh x spm slots, stride 16)
     unsigned long long *alpha_clr;        // next stage's parity, cleared by block 0
+    const int32_t *mid;                   // batches: mesh of each cell (else null)
+    const double *dt_tab;                 // batches: time step per mesh (Cdt is then the coefficient)
+    int spm, nslot;                       // slots per mesh, slots per parity
     double A, B, Cdt;
     double vel[3];
+    double gamma;
     int mode;
 };
 
-// |f| times the Lax-Friedrichs flux for the area-scaled normal m = |f| n.
-template <int DIM, int FLUX>
-__device__ __forceinline__ double lf_flux(double ua, double ub, const double (&m)[DIM], double alpha,
-                                          const double (&vel)[3])
+// Euler normal flux F(U).m for the area-scaled normal m (linear in m).
+template <int DIM, int V>
+__device__ __forceinline__ void euler_flux(const double (&U)[V], const double (&m)[DIM], double gamma, double (&f)[V])
+{
+    const double rho = U[0];
+    double ke = 0.0, vm = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        ke += U[1 + d] * U[1 + d];
+        vm += U[1 + d] / rho * m[d];
+    }
+    ke = 0.5 * ke / rho;
+    const double pr = (gamma - 1.0) * (U[DIM + 1] - ke);
+    f[0] = rho * vm;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) f[1 + d] = U[1 + d] * vm + pr * m[d];
+    f[DIM + 1] = (U[DIM + 1] + pr) * vm;
+}
+
+// |f| times the Lax-Friedrichs flux for the area-scaled normal m = |f| n, for
+// every component: out = 1/2 [(F(ua) + F(ub)).m - alpha |m| (ub - ua)], with
+// alpha = |a.n| per facet for advection and the global bound otherwise.
+template <int DIM, int FLUX, int V>
+__device__ __forceinline__ void lf_flux(const double (&ua)[V], const double (&ub)[V], const double (&m)[DIM],
+                                        double alpha, const double (&vel)[3], double gamma, double (&out)[V])
 {
     if constexpr (FLUX == kFluxAdv) {
-        // alpha = |a.n| per facet, so |f| alpha = |a.m|
         double am = 0.0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) am += vel[d] * m[d];
-        return 0.5 * ((am * ua + am * ub) - fabs(am) * (ub - ua));
-    } else {
+        out[0] = 0.5 * ((am * ua[0] + am * ub[0]) - fabs(am) * (ub[0] - ua[0]));
+    } else if constexpr (FLUX == kFluxBurgers) {
         double sm = 0.0, mm = 0.0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
@@ -691,7 +825,17 @@ __device__ __forceinline__ double lf_flux(double ua, double ub, const double (&m
             mm += m[d] * m[d];
         }
         const double af = alpha * sqrt(mm);
-        return 0.5 * ((0.5 * ua * ua * sm + 0.5 * ub * ub * sm) - af * (ub - ua));
+        out[0] = 0.5 * ((0.5 * ua[0] * ua[0] * sm + 0.5 * ub[0] * ub[0] * sm) - af * (ub[0] - ua[0]));
+    } else {
+        double mm = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) mm += m[d] * m[d];
+        const double af = alpha * sqrt(mm);
+        double fa[V], fb[V];
+        euler_flux<DIM, V>(ua, m, gamma, fa);
+        euler_flux<DIM, V>(ub, m, gamma, fb);
+#pragma unroll
+        for (int v = 0; v < V; ++v) out[v] = 0.5 * ((fa[v] + fb[v]) - af * (ub[v] - ua[v]));
     }
 }
 
@@ -699,20 +843,36 @@ template <int DIM, int Q, int FLUX, int BS>
 __global__ void __launch_bounds__(BS) k_update(UArgs a)
 {
     constexpr int F = DIM + 1;
+    constexpr int V = FLUX == kFluxEuler ? DIM + 2 : 1;
     const unsigned N = (unsigned)a.nc;
     const unsigned c = (unsigned)xcd_block((int)blockIdx.x, (int)gridDim.x) * (unsigned)BS + threadIdx.x;
     double alpha = 0.0;
-    if constexpr (FLUX == kFluxBurgers) {
-        const int lane = (int)(threadIdx.x & 63);
-        double v = __longlong_as_double((long long)a.alpha_rd[lane * 16]);
+    if constexpr (FLUX != kFluxAdv) {
+        if (blockIdx.x == 0)
+            for (int t = (int)threadIdx.x; t < a.nslot; t += BS) a.alpha_clr[t * 16] = 0ull;
+        if (!a.mid) {
+            // one mesh: its 64 slots, one per lane, reduced over the wave
+            const int lane = (int)(threadIdx.x & 63);
+            double v = __longlong_as_double((long long)a.alpha_rd[lane * 16]);
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-        alpha = v;
-        if (blockIdx.x == 0 && threadIdx.x < kAlphaSlots) a.alpha_clr[threadIdx.x * 16] = 0ull;
+            for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+            alpha = v;
+        }
     }
     if (c >= N) return;
+    double cdt = a.Cdt;
+    if (a.mid) {
+        const int32_t mesh = a.mid[c];
+        cdt = a.Cdt * a.dt_tab[mesh];
+        if constexpr (FLUX != kFluxAdv) {
+            for (int t = 0; t < a.spm; ++t)
+                alpha = fmax(alpha, __longlong_as_double((long long)a.alpha_rd[((int64_t)mesh * a.spm + t) * 16]));
+        }
+    }
     double vel[3] = {a.vel[0], a.vel[1], a.vel[2]};
-    double tot = 0.0;
+    double tot[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) tot[v] = 0.0;
 #pragma unroll
     for (int lf = 0; lf < F; ++lf) {
         const unsigned fc = lf * N + c;
@@ -720,19 +880,25 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
         double m[DIM];
 #pragma unroll
         for (int d = 0; d < DIM; ++d) m[d] = a.snormal[fc * DIM + d];
-        const double *own = a.fv + fc * Q;
-        double facc = 0.0;
+        double facc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) facc[v] = 0.0;
         if (s < 0) {
             // transmissive boundary: outside state equals inside state
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
-                facc += quad_weight<DIM, Q>(q) * lf_flux<DIM, FLUX>(own[q], own[q], m, alpha, vel);
+            for (int q = 0; q < Q; ++q) {
+                double uo[V], fl[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) uo[v] = a.fv[((v * F + lf) * N + c) * Q + q];
+                lf_flux<DIM, FLUX, V>(uo, uo, m, alpha, vel, a.gamma, fl);
+#pragma unroll
+                for (int v = 0; v < V; ++v) facc[v] += quad_weight<DIM, Q>(q) * fl[v];
+            }
         } else {
             // both cells evaluate the facet from identical operands in the
             // orientation of the lower-numbered cell; the other one negates
             const unsigned j = (unsigned)s >> 2;
             const unsigned l2 = (unsigned)s & 3u;
-            const double *oth = a.fv + (l2 * N + j) * Q;
             const bool owner = c < j;
             int32_t qp = 0;
             if constexpr (DIM == 3) qp = owner ? a.qperm[fc] : a.qperm[l2 * N + j];
@@ -743,21 +909,33 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
             for (int q = 0; q < Q; ++q) {
                 // the sibling's point matching point q: reversed along an edge in 2-D
                 const int qo = DIM == 3 ? ((qp >> (2 * q)) & 3) : (Q - 1 - q);
-                const double ua = owner ? own[q] : oth[q];
-                const double ub = owner ? oth[qo] : own[qo];
-                facc += quad_weight<DIM, Q>(q) * lf_flux<DIM, FLUX>(ua, ub, mm, alpha, vel);
+                double ua[V], ub[V], fl[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const double own_q = a.fv[((v * F + lf) * N + c) * Q + q];
+                    const double own_qo = a.fv[((v * F + lf) * N + c) * Q + qo];
+                    const double oth_q = a.fv[((v * F + l2) * N + j) * Q + q];
+                    const double oth_qo = a.fv[((v * F + l2) * N + j) * Q + qo];
+                    ua[v] = owner ? own_q : oth_q;
+                    ub[v] = owner ? oth_qo : own_qo;
+                }
+                lf_flux<DIM, FLUX, V>(ua, ub, mm, alpha, vel, a.gamma, fl);
+#pragma unroll
+                for (int v = 0; v < V; ++v) facc[v] += quad_weight<DIM, Q>(q) * fl[v];
             }
-            facc = owner ? facc : -facc;
+#pragma unroll
+            for (int v = 0; v < V; ++v) facc[v] = owner ? facc[v] : -facc[v];
         }
-        tot += facc;
+#pragma unroll
+        for (int v = 0; v < V; ++v) tot[v] += facc[v];
     }
-    const double L = -tot * a.rvol[c];
-    double o;
-    if (a.mode == 0)
-        o = L;
-    else
-        o = a.A * a.u0[c] + a.B * a.prev[c] + a.Cdt * L;
-    a.out[c] = o;
+    const double rv = a.rvol[c];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const unsigned vc = v * N + c;
+        const double L = -tot[v] * rv;
+        a.out[vc] = a.mode == 0 ? L : a.A * a.u0[vc] + a.B * a.prev[vc] + cdt * L;
+    }
 }
 
 // ------------------------------------------------------------- helpers
@@ -774,10 +952,10 @@ __global__ void k_permute(int64_t nc, int nvars, const int32_t *perm, const doub
         out[v * nc + u] = in[v * nc + d];
 }
 
-__global__ void k_clear_alpha(unsigned long long *alpha)
+__global__ void k_clear_alpha(unsigned long long *alpha, int nslot)
 {
-    const int t = threadIdx.x;
-    if (t < 2 * kAlphaSlots) alpha[t * 16] = 0ull;
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t < nslot) alpha[(int64_t)t * 16] = 0ull;
 }
 
 // ------------------------------------------------------------ dispatch
@@ -794,10 +972,16 @@ int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
     }
     args.blk0[kMaxBuckets] = nb;
     if (nb == 0) return 0;
-    if (dm.flux == kFluxBurgers)
+    if (dm.flux == kFluxBurgers) {
         hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
-    else
+    } else if (dm.flux == kFluxEuler) {
+        if constexpr (DIM == 2)
+            hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxEuler, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
+        else
+            return (int)hipErrorInvalidValue;
+    } else {
         hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxAdv, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
+    }
     return (int)hipGetLastError();
 }
 
@@ -806,10 +990,16 @@ int launch_k23(const DevMesh &dm, const UArgs &args, hipStream_t st)
 {
     constexpr int BS = 256;   // 64 and 128 measured no faster, also on small meshes
     const int nb = blocks_for(dm.nc, BS);
-    if (dm.flux == kFluxBurgers)
+    if (dm.flux == kFluxBurgers) {
         hipLaunchKernelGGL((k_update<DIM, Q, kFluxBurgers, BS>), dim3(nb), dim3(BS), 0, st, args);
-    else
+    } else if (dm.flux == kFluxEuler) {
+        if constexpr (DIM == 2)
+            hipLaunchKernelGGL((k_update<DIM, Q, kFluxEuler, BS>), dim3(nb), dim3(BS), 0, st, args);
+        else
+            return (int)hipErrorInvalidValue;
+    } else {
         hipLaunchKernelGGL((k_update<DIM, Q, kFluxAdv, BS>), dim3(nb), dim3(BS), 0, st, args);
+    }
     return (int)hipGetLastError();
 }
 
@@ -844,6 +1034,7 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     a.geo = dm.geo;
     a.vrel = dm.vrel;
     a.nsum = dm.nsum;
+    a.normal = dm.normal;
     a.spad = dm.spad;
     a.sib = dm.sib;
     a.perm = dm.perm;
@@ -851,11 +1042,15 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     a.coef_user = coef_user;
     a.fv_user = fv_user;
     a.rank_user = rank_user;
-    a.alpha_acc = dm.alpha + (size_t)parity * kAlphaSlots * 16;
+    a.alpha_acc = dm.alpha + (size_t)parity * dm.alpha_slots() * 16;
+    a.mid = dm.mid;
+    a.eh2_tab = dm.eh2_tab;
+    a.spm = dm.slots_per_mesh;
     a.eh2 = dm.eh2;
     a.alpha_w = dm.alpha_w;
     a.rank_tol = dm.rank_tol;
     a.period = dm.period;
+    a.gamma = dm.gamma;
     a.weight_mode = dm.weight_mode;
     // bucket b covers the variant's b-th rows-per-lane value; unused buckets are empty
     for (int b = 0; b <= kMaxBuckets; ++b) {
@@ -912,14 +1107,19 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
     a.u0 = u0;
     a.prev = prev;
     a.out = out;
-    a.alpha_rd = dm.alpha + (size_t)parity * kAlphaSlots * 16;
-    a.alpha_clr = dm.alpha + (size_t)(parity ^ 1) * kAlphaSlots * 16;
+    a.alpha_rd = dm.alpha + (size_t)parity * dm.alpha_slots() * 16;
+    a.alpha_clr = dm.alpha + (size_t)(parity ^ 1) * dm.alpha_slots() * 16;
+    a.mid = dm.mid;
+    a.dt_tab = dm.dt_tab;
+    a.spm = dm.slots_per_mesh;
+    a.nslot = (int)dm.alpha_slots();
     a.A = A;
     a.B = B;
     a.Cdt = Cdt;
     a.vel[0] = dm.vel[0];
     a.vel[1] = dm.vel[1];
     a.vel[2] = dm.vel[2];
+    a.gamma = dm.gamma;
     a.mode = mode;
     hipStream_t st = (hipStream_t)stream;
     if (dm.dim == 1) return launch_k23<1, 1>(dm, a, st);
@@ -941,7 +1141,8 @@ int launch_permute(const DevMesh &dm, const double *in, double *out, bool to_dev
 
 int launch_clear_alpha(const DevMesh &dm, void *stream)
 {
-    hipLaunchKernelGGL(k_clear_alpha, dim3(1), dim3(2 * kAlphaSlots), 0, (hipStream_t)stream, dm.alpha);
+    const int n = (int)(2 * dm.alpha_slots());
+    hipLaunchKernelGGL(k_clear_alpha, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, dm.alpha, n);
     return (int)hipGetLastError();
 }
 

@@ -435,8 +435,11 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     if (prm.p < 2 || prm.p > 5) throw inval("p must be in 2..5");
     if (dim == 3 && prm.p > 3) throw Error{WLSENO_EUNSUPPORTED, "3-D supports p <= 3"};
     if (dim == 2 && prm.p > 4) throw Error{WLSENO_EUNSUPPORTED, "2-D supports p <= 4"};
-    if (prm.flux != WLSENO_FLUX_ADVECTION && prm.flux != WLSENO_FLUX_BURGERS)
-        throw Error{WLSENO_EUNSUPPORTED, "flux must be advection or Burgers"};
+    if (prm.flux != WLSENO_FLUX_ADVECTION && prm.flux != WLSENO_FLUX_BURGERS && prm.flux != WLSENO_FLUX_EULER)
+        throw inval("flux must be advection, Burgers or Euler");
+    if (prm.flux == WLSENO_FLUX_EULER && dim != 2)
+        throw Error{WLSENO_EUNSUPPORTED, "the Euler system is compiled for 2-D meshes"};
+    if (prm.flux == WLSENO_FLUX_EULER && !(prm.gamma > 1.0)) throw inval("gamma > 1 required");
     if (prm.weight_mode != 0 && prm.weight_mode != 1) throw inval("weight_mode must be 0 or 1");
     if (prm.lanes != 0 && prm.lanes != 2 && prm.lanes != 4 && prm.lanes != 8 && prm.lanes != 16)
         throw inval("lanes must be 0, 2, 4, 8 or 16");
@@ -447,7 +450,7 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     b.m = num_coeffs(dim, prm.p);
     b.nq = points_per_face(dim, prm.p);
     b.nf = nvc;
-    b.nvars = 1;
+    b.nvars = prm.flux == WLSENO_FLUX_EULER ? dim + 2 : 1;
     if (prm.n_lo < 1 || prm.n_hi < prm.n_lo) throw inval("need 1 <= n_lo <= n_hi");
     if (prm.n_hi < b.m) throw inval("n_hi must be at least the number of coefficients m");
     if (prm.n_hi > 64) throw Error{WLSENO_EUNSUPPORTED, "n_hi above 64"};
@@ -601,6 +604,10 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
             b.geo[d * b.gs + dim + t] = mu / af;
         }
         b.rvol[d] = 1.0 / m.vol[u];
+    }
+    if (!m.mesh_of.empty()) {
+        b.mid.resize(nc);
+        for (int64_t d = 0; d < nc; ++d) b.mid[d] = m.mesh_of[b.perm[d]];
     }
 
     // facets: normals, areas, sibling map, point correspondence

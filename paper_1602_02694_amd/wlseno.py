@@ -70,6 +70,18 @@ class WLSENO:
         self.dim = int(dim)
         self.n_cell = int(c.shape[0])
 
+    def batch_add_mesh(self, dim, verts, cells) -> int:
+        """Append one mesh to the context's batch; returns its index."""
+        v = np.ascontiguousarray(np.asarray(verts, dtype=np.float64).reshape(-1, dim))
+        c = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, dim + 1))
+        mid = C.c_int32(-1)
+        self._check(self._lib.wlseno_batch_add_mesh(
+            self._h, int(dim), v.shape[0], v.ctypes.data_as(C.POINTER(C.c_double)), c.shape[0],
+            c.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(mid)))
+        self.dim = int(dim)
+        self.n_cell = (self.n_cell or 0) + int(c.shape[0]) if mid.value > 0 else int(c.shape[0])
+        return mid.value
+
     def stencil_build(self, p=3, n_lo=12, n_hi=20, flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2,
                       alpha_w=1.5, rank_tol=1e-12, weight_mode=0, gamma=1.4, lanes=0):
         prm = N.Params()
@@ -87,7 +99,7 @@ class WLSENO:
     def info(self) -> dict:
         inf = N.Info()
         self._check(self._lib.wlseno_get_info(self._h, C.byref(inf)))
-        return {k: getattr(inf, k) for k, _ in N.Info._fields_ if k != "reserved"}
+        return {k: getattr(inf, k) for k, _ in N.Info._fields_}
 
     def stencil(self):
         inf = self.info()
@@ -142,6 +154,21 @@ class WLSENO:
         self._sync_stream()
         self._check(self._lib.wlseno_step(self._h, _ptr(u), float(dt), int(n_steps)))
         return u
+
+    def batch_step(self, u, dts, n_steps):
+        """Advance a batch in place by n_steps TVD RK3 steps, mesh k with dts[k]."""
+        u = self._field(u)
+        d = np.ascontiguousarray(np.asarray(dts, dtype=np.float64))
+        self._sync_stream()
+        self._check(self._lib.wlseno_batch_step(self._h, _ptr(u), d.ctypes.data_as(C.POINTER(C.c_double)),
+                                                int(n_steps)))
+        return u
+
+    def batch_last_alpha(self):
+        a = np.zeros(self.info()["n_mesh"])
+        self._sync_stream()
+        self._check(self._lib.wlseno_batch_last_alpha(self._h, a.ctypes.data_as(C.POINTER(C.c_double))))
+        return a
 
     def last_alpha(self) -> float:
         a = C.c_double(0.0)

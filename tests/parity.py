@@ -33,9 +33,16 @@ U64 = 2.0 ** -53
 
 
 def rel_errors(g, o, floor=FLOOR, scale=None):
+    """|g - o| / max(|o|, floor * max|o|, scale); the max is taken per leading
+    index (per field component) for arrays of two or more dimensions."""
     g = np.asarray(g, dtype=np.float64)
     o = np.asarray(o, dtype=np.float64)
-    mx = np.max(np.abs(o)) if o.size else 0.0
+    if o.size == 0:
+        mx = 0.0
+    elif o.ndim >= 2:
+        mx = np.max(np.abs(o), axis=tuple(range(1, o.ndim)), keepdims=True)
+    else:
+        mx = np.max(np.abs(o))
     sc = np.maximum(np.abs(o), floor * mx)
     if scale is not None:
         sc = np.maximum(sc, np.asarray(scale, dtype=np.float64).reshape(sc.shape))
@@ -43,12 +50,26 @@ def rel_errors(g, o, floor=FLOOR, scale=None):
     return np.abs(g - o) / sc
 
 
-def flux_scale(o, fval):
+def flux_scale(o, fval, alpha=0.0):
     """Per-cell magnitude of the flux sum that forms the right-hand side:
     S_i = (1/|tau_i|) sum_f |f| sum_q w_q |F(u_q).n_f| from the oracle's own
     facet values.  L_i is a difference of such fluxes divided by |tau_i|, so
-    its rounding error is relative to S_i rather than to |L_i|."""
+    its rounding error is relative to S_i rather than to |L_i|.  For the Euler
+    system, per component, with the dissipation term alpha |u_q| added to
+    |F(u_q).n_f| (it is of the same size); the result is (V, nc)."""
     m = o.mesh
+    if o.flux == "euler":
+        fv = np.asarray(fval)                                  # (V, nc, F, Q)
+        gamma = o._P.gamma
+        rho, mx, my, E = fv[0], fv[1], fv[2], fv[3]
+        n = m.normal                                           # (nc, F, 2)
+        vn = (mx * n[:, :, 0, None] + my * n[:, :, 1, None]) / rho
+        pr = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / rho)
+        Fn = np.stack([rho * vn, mx * vn + pr * n[:, :, 0, None], my * vn + pr * n[:, :, 1, None],
+                       (E + pr) * vn])
+        fl = np.abs(Fn) + alpha * np.abs(fv)
+        per_face = fl @ m.qw                                   # (V, nc, F)
+        return (per_face * m.area[None]).sum(axis=2) / m.vol[None]
     fv = np.asarray(fval)[0]                                   # (nc, F, Q)
     if o.flux == "burgers":
         sn = np.abs(m.normal.sum(axis=2))                      # (nc, F)

@@ -137,3 +137,35 @@ def test_null_context_and_create_errors(lib):
     assert lib.wlseno_create(-5, C.byref(h)) == 1
     assert b"device" in lib.wlseno_last_error(None)
     assert lib.wlseno_destroy(None) == 0
+
+
+def test_batch_stencils_are_the_meshes_own(lib):
+    """A batch's stencils are each mesh's own (oracle builder), with cell ids
+    offset by the cells of the meshes before it; n_mesh and each mesh's h."""
+    from oracle.mesh import OracleMesh
+    from paper_1602_02694_amd import WLSENO, WLSENOError
+
+    meshes = [jittered_square(n, 0.3, 700 + n) for n in (7, 11, 5)]
+    w = WLSENO(device=-1)
+    for k, m in enumerate(meshes):
+        assert w.batch_add_mesh(2, m.verts, m.cells) == k
+    w.stencil_build(p=3, n_lo=12, n_hi=20)
+    inf = w.info()
+    assert inf["n_mesh"] == 3 and inf["n_cell"] == sum(m.n_cell for m in meshes)
+    rp, col = w.stencil()
+    off = 0
+    for m in meshes:
+        om = OracleMesh(2, m.verts, m.cells, p=3)
+        orp, ocol = om.stencils(12, 20)
+        seg = slice(rp[off], rp[off + m.n_cell])
+        assert np.array_equal(np.diff(rp[off:off + m.n_cell + 1]), np.diff(orp))
+        assert np.array_equal(col[seg], ocol + off)
+        off += m.n_cell
+    # a mesh of another dimension cannot join; a single upload replaces the batch
+    line = periodic_line(20, 0.1, 5)
+    with pytest.raises(WLSENOError) as e:
+        w.batch_add_mesh(1, line.verts, line.cells)
+    assert e.value.status == 1
+    w.mesh_upload(2, meshes[0].verts, meshes[0].cells)
+    w.stencil_build(p=3, n_lo=12, n_hi=20)
+    assert w.info()["n_mesh"] == 1 and w.info()["n_cell"] == meshes[0].n_cell
