@@ -1,6 +1,6 @@
 """Benchmark of the WLS-ENO finite-volume path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload square|square-large]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload square|square-large|cube|batch]
 
 One "step" is one third-order TVD Runge-Kutta step of the whole hot path
 (three right-hand sides: reconstruction, Lax-Friedrichs flux, update) over the
@@ -17,7 +17,10 @@ host's cores, together with the GPU-vs-oracle parity of that sample.
 `--workload square-large` runs the 1000x1000-point companion mesh (~2.0 M
 triangles) on which HBM traffic is measured (profiles/traffic.json holds the
 calibrated rocprofv3 FETCH_SIZE/WRITE_SIZE per launch, valid while the kernel
-source hash matches).
+source hash matches).  `--workload cube` runs 2.68 M tetrahedra (p = 3,
+linear advection); `--workload batch` runs 64 independent 2-D Euler meshes
+(p = 4, ~1.25 M cells) as one batch and, for comparison, one context per
+mesh (`per_mesh_loop`).
 """
 
 from __future__ import annotations
@@ -62,13 +65,14 @@ def recon_flops(n, m, dim, F, Q):
     return build + weights + form + scale + qr + back + evalf
 
 
-def update_bytes(nc, dim, F, Q):
+def update_bytes(nc, dim, F, Q, V=1):
     """Compulsory HBM bytes of one flux/update launch: sibling ids (4F),
-    area-scaled normals (8 F dim), the cell's own facet values (8 F Q; the
-    neighbour's copy of a facet value is counted once, as its own), 1/|tau|,
-    the state and stage inputs (one array in the first RK stage, two in the
-    others: 8 x 4/3 on average) and the output."""
-    return nc * (4 * F + 8 * F * dim + 8 * F * Q + 8 + 8 * 4.0 / 3.0 + 8)
+    area-scaled normals (8 F dim), the cell's own facet values (8 F Q per
+    component; the neighbour's copy of a facet value is counted once, as its
+    own), 1/|tau|, the state and stage inputs (one array in the first RK
+    stage, two in the others: 8 x 4/3 on average) and the output, per
+    component."""
+    return nc * (4 * F + 8 * F * dim + 8 + V * (8 * F * Q + 8 * 4.0 / 3.0 + 8))
 
 
 def traffic_record(kernel, workload):
@@ -121,12 +125,131 @@ def make_workload(name):
     return Workload(f"{shape}{mesh.n_cell}-{kind}-p{cfg['p']}", mesh, u0, dict(cfg))
 
 
+def insphere_diameters(mesh):
+    """2 dim |tau| / |d tau| per cell (the CFL length), from the vertices."""
+    v = mesh.verts[mesh.cells]                                  # (nc, d+1, d)
+    d = mesh.dim
+    if d == 2:
+        e = [v[:, 1] - v[:, 0], v[:, 2] - v[:, 1], v[:, 0] - v[:, 2]]
+        area = 0.5 * np.abs(e[0][:, 0] * (-e[2][:, 1]) - e[0][:, 1] * (-e[2][:, 0]))
+        per = sum(np.linalg.norm(x, axis=1) for x in e)
+        return 4.0 * area / per
+    raise ValueError("2-D meshes only")
+
+
+def run_batch(args, torch, WLSENO):
+    """The batched Euler workload: 64 meshes stepped by one set of launches per
+    stage, against the same meshes stepped one context at a time."""
+    from workloads import configs
+
+    t = time.time()
+    wls = configs.batched_euler(64, 3001)
+    cells = [w.mesh.n_cell for w in wls]
+    log(f"[bench] 64 meshes, {sum(cells)} cells ({min(cells)}-{max(cells)}) in {time.time() - t:.1f}s")
+    s0 = wls[0].settings
+    kw = dict(p=s0["p"], n_lo=s0["n_lo"], n_hi=s0["n_hi"], flux="euler", gamma=s0["gamma"])
+    t = time.time()
+    wb = WLSENO(device=0)
+    for w in wls:
+        wb.batch_add_mesh(2, w.mesh.verts, w.mesh.cells)
+    wb.stencil_build(**kw)
+    info = wb.info()
+    log(f"[bench] batch setup {time.time() - t:.1f}s")
+    u0 = np.concatenate([w.u0 for w in wls], axis=1)
+    u_init = torch.tensor(u0.reshape(-1), device="cuda")
+    wb.rhs(u_init)
+    alphas = wb.batch_last_alpha()
+    dts = np.array([0.5 * insphere_diameters(w.mesh).min() / a for w, a in zip(wls, alphas)])
+    # batched: warm-up, then K steps timed
+    u = u_init.clone()
+    wb.batch_step(u, dts, args.warmup)
+    torch.cuda.synchronize()
+    u = u_init.clone()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    wb.batch_step(u, dts, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - ts
+    nc = int(info["n_cell"])
+    value = nc * args.steps / elapsed
+    log(f"[bench] batch: {args.steps} steps in {elapsed * 1e3:.2f} ms -> {value:.4g} cell-updates/s")
+    # the same meshes, one context each, stepped one after another
+    singles = []
+    for w, dt in zip(wls, dts):
+        c = WLSENO(device=0)
+        c.mesh_upload(2, w.mesh.verts, w.mesh.cells)
+        c.stencil_build(**kw)
+        singles.append((c, torch.tensor(w.u0.reshape(-1), device="cuda"), dt))
+    for c, ui, dt in singles:
+        c.step(ui.clone(), dt, args.warmup)
+    torch.cuda.synchronize()
+    work = [ui.clone() for _, ui, _ in singles]
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for (c, _, dt), ui in zip(singles, work):
+        c.step(ui, dt, args.steps)
+    torch.cuda.synchronize()
+    el_loop = time.perf_counter() - ts
+    log(f"[bench] per-mesh loop: {el_loop * 1e3:.2f} ms -> {nc * args.steps / el_loop:.4g} cell-updates/s")
+    ub = u.reshape(4, -1)
+    off = 0
+    same = True
+    for ui, w in zip(work, wls):
+        n = w.mesh.n_cell
+        same = same and bool(torch.equal(ui.reshape(4, -1), ub[:, off:off + n]))
+        off += n
+    k1 = wb.time_kernel(0, u_init, 3 * args.steps)
+    k2 = wb.time_kernel(1, u_init, 3 * args.steps)
+    rp, _ = wb.stencil()
+    nsz = np.diff(rp)
+    F, Q, m = info["faces_per_cell"], info["points_per_face"], info["m"]
+    flops = 4.0 * float(np.sum(recon_flops(nsz, m, 2, F, Q)))
+    achieved = flops / (k1 * 1e-3) / 1e12
+    log(f"[bench] k_reconstruct avg {k1 * 1e3:.2f} us, k_update avg {k2 * 1e3:.2f} us; "
+        f"{flops / nc:.0f} flop/cell")
+    ub_bytes = update_bytes(nc, 2, F, Q, V=4)
+    ach_u = ub_bytes / (k2 * 1e-3) / 1e9
+    return {
+        "metric": "cell-updates/s (p=4, 2-D Euler, 64-mesh batch, FP64)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch64-euler-p4-{nc}",
+            "mesh": "64 Delaunay triangulations of jittered lattices, 5k-50k cells each (log-uniform, seed 3001)",
+            "n_cell": nc,
+            "p": 4,
+            "stencil_cells": [int(nsz.min()), int(nsz.max())],
+            "flux": "2-D Euler (gamma 1.4), per-mesh global Lax-Friedrichs alpha, quadrant Riemann data",
+            "time_integrator": "TVD RK3, per-mesh dt, HIP-graph replay",
+        },
+        "per_mesh_loop": {"value": nc * args.steps / el_loop, "ms_per_step": el_loop * 1e3 / args.steps,
+                          "batch_speedup": el_loop / elapsed, "bitwise_equal_to_batch": same},
+        "roofline": {"bound": "alu", "kernel": "k_reconstruct", "achieved": achieved,
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic_record("k_reconstruct", "batch"), "avg_launch_us": k1 * 1e3,
+                     "flops_per_launch": flops},
+        "roofline_update": {"bound": "hbm", "kernel": "k_update", "achieved": ach_u, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": ach_u / HBM_PEAK_GBS,
+                            "traffic": traffic_record("k_update", "batch"), "avg_launch_us": k2 * 1e3,
+                            "bytes_per_launch": ub_bytes},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="square", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="square", choices=sorted(WORKLOADS) + ["batch"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables the CPU leg)")
     args = ap.parse_args()
@@ -139,6 +262,9 @@ def main():
 
     from paper_1602_02694_amd import WLSENO
 
+    if args.workload == "batch":
+        print(json.dumps(run_batch(args, torch, WLSENO)), flush=True)
+        return
     wl = make_workload(args.workload)
     cfg = wl.settings
     mesh = wl.mesh

@@ -180,6 +180,13 @@ wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps);
  * device (synchronises the stream). */
 wlseno_status wlseno_last_alpha(wlseno_t ctx, double *alpha);
 
+/* wlseno_step and wlseno_batch_step replay pairs of RK3 steps from a HIP
+ * graph captured on first use (per context, per time step; recaptured when
+ * the time step or the stencil build changes), and launch an odd last step
+ * directly.  enable = 0 launches every kernel directly; results are
+ * identical either way.  The default is enabled. */
+wlseno_status wlseno_set_graphs(wlseno_t ctx, int enable);
+
 /* Batches of independent meshes (several meshes stepped by one set of
  * launches).  Each call appends one mesh (host arrays, copied; no flags) and
  * returns its index in *mesh_id (nullable).  The meshes must share dim.  The

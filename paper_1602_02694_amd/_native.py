@@ -17,7 +17,7 @@ EXPORTS = [
     "wlseno_params_default", "wlseno_create", "wlseno_destroy", "wlseno_last_error", "wlseno_set_stream",
     "wlseno_mesh_upload", "wlseno_stencil_build", "wlseno_get_info", "wlseno_get_stencil",
     "wlseno_reconstruct", "wlseno_rhs", "wlseno_step", "wlseno_last_alpha", "wlseno_time_kernel",
-    "wlseno_batch_add_mesh", "wlseno_batch_step", "wlseno_batch_last_alpha",
+    "wlseno_batch_add_mesh", "wlseno_batch_step", "wlseno_batch_last_alpha", "wlseno_set_graphs",
 ]
 
 
@@ -78,6 +78,7 @@ def load():
     lib.wlseno_batch_add_mesh.argtypes = [vp, C.c_int, C.c_int64, dp, C.c_int64, ip, C.POINTER(C.c_int32)]
     lib.wlseno_batch_step.argtypes = [vp, vp, dp, C.c_int]
     lib.wlseno_batch_last_alpha.argtypes = [vp, dp]
+    lib.wlseno_set_graphs.argtypes = [vp, C.c_int]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name not in ("wlseno_params_default", "wlseno_last_error"):

@@ -35,6 +35,12 @@ struct wlseno_ctx {
     std::vector<double> batch_xyz;
     std::vector<int32_t> batch_cells;
     std::vector<double> dt_host;   // per-mesh time steps last sent to the device
+    // RK3 steps replayed from a captured HIP graph: two steps (six stages,
+    // parities 0,1,0,1,0,1), captured on a private stream for one stage scale
+    bool use_graphs = true;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t step2 = nullptr;
+    double step2_h = 0.0;
 };
 
 namespace {
@@ -51,8 +57,18 @@ void check_launch(int e, const char *what)
     if (e != 0) throw Error{WLSENO_EDEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)e)};
 }
 
+void drop_graph(wlseno_ctx *c)
+{
+    if (c->step2) {
+        (void)hipSetDevice(c->device);
+        (void)hipGraphExecDestroy(c->step2);
+    }
+    c->step2 = nullptr;
+}
+
 void free_device(wlseno_ctx *c)
 {
+    drop_graph(c);
     if (c->device >= 0) {
         (void)hipSetDevice(c->device);
         for (void *p : c->allocs) (void)hipFree(p);
@@ -154,11 +170,50 @@ void upload_build(wlseno_ctx *c)
 
 // One right-hand-side stage: K1 then K2/K3 (flux, divergence, RK combination).
 void stage(wlseno_ctx *c, const double *in, const double *u0, const double *prev, double *out, double A,
-           double B, double Cdt, int mode, int parity)
+           double B, double Cdt, int mode, int parity, hipStream_t st)
 {
-    check_launch(launch_reconstruct(c->dm, in, parity, nullptr, nullptr, nullptr, c->stream), "reconstruct");
-    check_launch(launch_update(c->dm, u0, prev, out, A, B, Cdt, mode, parity, c->stream), "update");
+    check_launch(launch_reconstruct(c->dm, in, parity, nullptr, nullptr, nullptr, st), "reconstruct");
+    check_launch(launch_update(c->dm, u0, prev, out, A, B, Cdt, mode, parity, st), "update");
     c->last_parity = parity;
+}
+
+// One TVD RK3 step on the device-order state ubuf, starting at `par`:
+// k1 = u + dt L(u); k2 = 3/4 u + 1/4 k1 + 1/4 dt L(k1); u = 1/3 u + 2/3 k2 + 2/3 dt L(k2)
+int rk3_step(wlseno_ctx *c, double h, int par, hipStream_t st)
+{
+    double *u = c->ubuf, *k = c->kbuf;
+    stage(c, u, u, u, k, 1.0, 0.0, h, 1, par, st);
+    par ^= 1;
+    stage(c, k, u, k, k, 0.75, 0.25, 0.25 * h, 1, par, st);
+    par ^= 1;
+    stage(c, k, u, k, u, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * h, 1, par, st);
+    return par ^ 1;
+}
+
+// The two-step graph for stage scale h, captured on first use.
+hipGraphExec_t step2_graph(wlseno_ctx *c, double h)
+{
+    if (c->step2 && std::memcmp(&c->step2_h, &h, sizeof h) == 0) return c->step2;
+    drop_graph(c);
+    if (!c->cap) check_hip(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    check_hip(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipGraph_t g = nullptr;
+    try {
+        int par = rk3_step(c, h, 0, c->cap);
+        rk3_step(c, h, par, c->cap);
+    } catch (...) {
+        (void)hipStreamEndCapture(c->cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    check_hip(hipStreamEndCapture(c->cap, &g), "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    check_hip(e, "hipGraphInstantiate");
+    c->step2 = ex;
+    c->step2_h = h;
+    return ex;
 }
 
 }  // namespace
@@ -233,8 +288,17 @@ wlseno_status wlseno_destroy(wlseno_t ctx)
 {
     if (!ctx) return WLSENO_OK;
     free_device(ctx);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
     return WLSENO_OK;
+}
+
+wlseno_status wlseno_set_graphs(wlseno_t ctx, int enable)
+{
+    API_BEGIN(ctx)
+    ctx->use_graphs = enable != 0;
+    if (!ctx->use_graphs) drop_graph(ctx);
+    API_END(ctx)
 }
 
 const char *wlseno_last_error(wlseno_t ctx)
@@ -375,7 +439,7 @@ wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev)
     need_device(ctx);
     check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
     check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
-    stage(ctx, ctx->ubuf, nullptr, nullptr, ctx->tbuf, 0.0, 0.0, 1.0, 0, 0);
+    stage(ctx, ctx->ubuf, nullptr, nullptr, ctx->tbuf, 0.0, 0.0, 1.0, 0, 0, ctx->stream);
     check_launch(launch_permute(ctx->dm, ctx->tbuf, dudt_dev, false, ctx->stream), "permute");
     API_END(ctx)
 }
@@ -401,20 +465,16 @@ void run_steps(wlseno_ctx *ctx, double *u_dev, double dt, const double *dt_mesh,
     }
     // stage coefficients c dt; for a batch the kernel multiplies c by the mesh's dt
     const double h = batch ? 1.0 : dt;
-    double *u = ctx->ubuf, *k = ctx->kbuf;
-    check_launch(launch_permute(ctx->dm, u_dev, u, true, ctx->stream), "permute");
+    check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
     check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
-    int par = 0;
-    for (int s = 0; s < n_steps; ++s) {
-        // k1 = u + dt L(u); k2 = 3/4 u + 1/4 k1 + 1/4 dt L(k1); u = 1/3 u + 2/3 k2 + 2/3 dt L(k2)
-        stage(ctx, u, u, u, k, 1.0, 0.0, h, 1, par);
-        par ^= 1;
-        stage(ctx, k, u, k, k, 0.75, 0.25, 0.25 * h, 1, par);
-        par ^= 1;
-        stage(ctx, k, u, k, u, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * h, 1, par);
-        par ^= 1;
+    int s = 0;
+    if (ctx->use_graphs && n_steps >= 2) {
+        hipGraphExec_t ex = step2_graph(ctx, h);
+        for (; s + 2 <= n_steps; s += 2) check_hip(hipGraphLaunch(ex, ctx->stream), "hipGraphLaunch");
+        ctx->last_parity = 1;
     }
-    check_launch(launch_permute(ctx->dm, u, u_dev, false, ctx->stream), "permute");
+    for (; s < n_steps; ++s) rk3_step(ctx, h, s & 1 ? 1 : 0, ctx->stream);
+    check_launch(launch_permute(ctx->dm, ctx->ubuf, u_dev, false, ctx->stream), "permute");
 }
 
 }  // namespace

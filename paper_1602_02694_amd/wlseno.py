@@ -155,6 +155,10 @@ class WLSENO:
         self._check(self._lib.wlseno_step(self._h, _ptr(u), float(dt), int(n_steps)))
         return u
 
+    def set_graphs(self, enable: bool):
+        """Replay RK3 step pairs from a captured HIP graph (default) or launch directly."""
+        self._check(self._lib.wlseno_set_graphs(self._h, 1 if enable else 0))
+
     def batch_step(self, u, dts, n_steps):
         """Advance a batch in place by n_steps TVD RK3 steps, mesh k with dts[k]."""
         u = self._field(u)
