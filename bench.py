@@ -244,6 +244,70 @@ def run_batch(args, torch, WLSENO):
     }
 
 
+def run_adjoint(torch, WLSENO, steps=100, ckpt=10, directions=32):
+    """Adjoint workload: ~200 k triangles, p = 3, linear advection a = (1, 0.5),
+    zero outside state at boundary facets (no inflow),
+    loss 1/2 ||u(T) - u_target||^2 after `steps` RK3 steps; the gradient with
+    respect to u0 from the checkpointed adjoint and its time against the
+    forward run's.  Central differences along random directions check it on
+    the WLS-ENO scheme and on its equal-weight limit (unit weights: a linear
+    scheme, so differences are exact up to rounding)."""
+    from workloads import configs
+
+    t = time.time()
+    wl = configs.square_advection_adjoint(317, 5001)
+    mesh = wl.mesh
+    s = wl.settings
+    out = {"workload": f"tri{mesh.n_cell}-advection-p3, {steps} steps, checkpoint every {ckpt}"}
+    u0 = torch.tensor(wl.u0, device="cuda")
+    tg = torch.tensor(s["target"], device="cuda")
+    for weight_mode, tag in ((0, "wls_eno"), (1, "equal_weights")):
+        w = WLSENO(device=0)
+        w.mesh_upload(2, mesh.verts, mesh.cells)
+        w.stencil_build(p=s["p"], n_lo=s["n_lo"], n_hi=s["n_hi"], flux="advection", velocity=s["velocity"],
+                        bc=s["bc"], weight_mode=weight_mode)
+        dt = 0.5 * w.info()["min_insphere"] / float(np.hypot(*s["velocity"][:2]))
+
+        def forward(x):
+            y = x.clone()
+            w.step(y, dt, steps)
+            return y
+
+        gT = forward(u0) - tg
+        g0 = w.step_adjoint(u0, dt, steps, gT, ckpt)          # warm-up (tables, buffers)
+        torch.cuda.synchronize()
+        if weight_mode == 0:
+            log(f"[bench] adjoint workload: {mesh.n_cell} cells, ready in {time.time() - t:.1f}s")
+            reps = 3
+            ts = time.perf_counter()
+            for _ in range(reps):
+                forward(u0)
+            torch.cuda.synchronize()
+            t_fwd = (time.perf_counter() - ts) / reps
+            ts = time.perf_counter()
+            for _ in range(reps):
+                g0 = w.step_adjoint(u0, dt, steps, gT, ckpt)
+            torch.cuda.synchronize()
+            t_adj = (time.perf_counter() - ts) / reps
+            log(f"[bench] forward {t_fwd * 1e3:.2f} ms, adjoint {t_adj * 1e3:.2f} ms for {steps} steps")
+            out.update({"forward_ms": t_fwd * 1e3, "adjoint_ms": t_adj * 1e3, "adjoint_over_forward": t_adj / t_fwd})
+
+        rng = np.random.default_rng(5003)
+        worst = 0.0
+        for _ in range(directions):
+            d = torch.tensor(rng.standard_normal(mesh.n_cell), device="cuda")
+            h = 1e-6 * float(u0.abs().max()) / float(d.abs().max())
+            Jd = (forward(u0 + h * d) - forward(u0 - h * d)) / (2 * h)
+            fd = float(torch.dot(gT, Jd))
+            ad = float(torch.dot(g0, d))
+            worst = max(worst, abs(fd - ad) / max(abs(ad), 1e-300))
+        log(f"[bench] {tag}: adjoint vs central differences, {directions} directions: max rel err {worst:.3e}, "
+            f"max |g0| {float(g0.abs().max()):.3e}")
+        out[f"fd_{tag}"] = {"directions": directions, "max_rel_err": worst, "tolerance": 1e-6,
+                            "pass": worst <= 1e-6, "max_abs_gradient": float(g0.abs().max())}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +316,8 @@ def main():
     ap.add_argument("--workload", default="square", choices=sorted(WORKLOADS) + ["batch"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables the CPU leg)")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward measurement of the default workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design is "
@@ -403,6 +469,8 @@ def main():
         }
         out["parity"] = {"steps": S, "max_rel_err_vs_oracle": err, "tolerance": 1e-12, "pass": err <= 1e-12}
         log(f"[bench] oracle {nc * S / cpu_t:.4g} cell-updates/s; GPU vs oracle after {S} steps: {err:.3e}")
+    if args.workload == "square" and not args.no_adjoint:
+        out["adjoint"] = run_adjoint(torch, WLSENO)
     print(json.dumps(out), flush=True)
 
 

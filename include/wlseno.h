@@ -88,6 +88,10 @@ typedef struct {
     double rank_tol;     /* numerical rank: |R_kk| > rank_tol |R_11| */
     double velocity[3];  /* advection velocity a */
     double gamma;        /* ratio of specific heats (Euler) */
+    int32_t bc;          /* outside state at boundary facet points: 0 = the inside state
+                            (transmissive); 1 = zero (a zero far field: with the upwind flux
+                            of linear advection, outflow as before and no inflow); 1 is
+                            EINVAL for the Euler system */
 } wlseno_params;
 
 typedef struct {
@@ -209,6 +213,27 @@ wlseno_status wlseno_batch_step(wlseno_t ctx, double *u_dev, const double *dt_pe
 /* The Lax-Friedrichs alpha of each mesh in the last rhs stage (host array of
  * n_mesh doubles; 0 for advection).  Synchronises the stream. */
 wlseno_status wlseno_batch_last_alpha(wlseno_t ctx, double *alpha_per_mesh);
+
+/* Adjoint (scalar linear advection on a single mesh; other cases return
+ * EUNSUPPORTED).  The right-hand side L(u) is differentiated on its active
+ * branch: stencils, pivot order, numerical rank and the facet neighbour that
+ * gives the centre's smallest indicator are held at their values at u, while
+ * the weights' dependence on u (eq. for beta and omega) is differentiated.
+ *
+ * out_dev = J(u)^T v_dev with J = dL/du at u_dev (all double[n_cell] on the
+ * device, user order; out_dev must not alias an input).  Deterministic: each
+ * cell's contributions are summed over the transposed stencil in a fixed
+ * order, without atomics. */
+wlseno_status wlseno_rhs_vjp(wlseno_t ctx, const double *u_dev, const double *v_dev, double *out_dev);
+
+/* g0_dev = (d u(T) / d u0)^T gT_dev, where u(T) is n_steps TVD RK3 steps of
+ * size dt from u0_dev: the gradient of any loss of u(T) with respect to u0
+ * given its gradient gT with respect to u(T).  The forward trajectory is
+ * stored every ckpt_every steps and recomputed in between (memory: n_steps /
+ * ckpt_every + 3 ckpt_every states).  EINVAL for null pointers, a
+ * non-finite dt, n_steps < 0 or ckpt_every < 1. */
+wlseno_status wlseno_step_adjoint(wlseno_t ctx, const double *u0_dev, double dt, int n_steps, int ckpt_every,
+                                  const double *gT_dev, double *g0_dev);
 
 /* Kernel timing for measurement.  Reconstructs u_dev (user order, n_cell
  * doubles on the device, not modified) once, then records a HIP event on the

@@ -73,7 +73,7 @@ class _Problem(C.Structure):
     _fields_ = [
         ("dim", C.c_int), ("p", C.c_int), ("m", C.c_int), ("nvars", C.c_int),
         ("flux", C.c_int), ("weight_mode", C.c_int),
-        ("nc", C.c_int), ("nq", C.c_int), ("periodic", C.c_int),
+        ("nc", C.c_int), ("nq", C.c_int), ("periodic", C.c_int), ("bc", C.c_int),
         ("period", C.c_double), ("eps", C.c_double), ("alpha_w", C.c_double),
         ("rank_tol", C.c_double), ("h", C.c_double), ("gamma", C.c_double),
         ("adv", C.c_double * 3),
@@ -143,7 +143,7 @@ class Oracle:
 
     def __init__(self, dim, verts, cells, periodic=False, *, p=3, n_lo=None, n_hi=None,
                  flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2, alpha_w=1.5,
-                 rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None, extended=False):
+                 rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None, extended=False, bc=0):
         self.extended = bool(extended)
         self.mesh = OracleMesh(dim, verts, cells, periodic, p=p)
         om = self.mesh
@@ -177,6 +177,7 @@ class Oracle:
         P.dim, P.p, P.m, P.nvars = om.dim, self.p, self.m, self.nvars
         P.flux, P.weight_mode = FLUX[flux], int(weight_mode)
         P.nc, P.nq, P.periodic = om.nc, om.nq, int(om.periodic)
+        P.bc = int(bc)
         P.period, P.eps, P.alpha_w, P.rank_tol = om.period, eps, alpha_w, rank_tol
         P.h, P.gamma = self.h, gamma
         for d in range(3):
@@ -248,6 +249,6 @@ class Oracle:
 def from_workload(wl, **kw) -> Oracle:
     s = dict(wl.settings)
     args = dict(p=s["p"], n_lo=s["n_lo"], n_hi=s["n_hi"], flux=s["flux"],
-                velocity=s.get("velocity", (1.0, 0.0, 0.0)), gamma=s.get("gamma", 1.4))
+                velocity=s.get("velocity", (1.0, 0.0, 0.0)), gamma=s.get("gamma", 1.4), bc=s.get("bc", 0))
     args.update(kw)
     return Oracle(wl.mesh.dim, wl.mesh.verts, wl.mesh.cells, wl.mesh.periodic, **args)

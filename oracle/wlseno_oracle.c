@@ -52,6 +52,7 @@ enum { OR_ADVECTION = 0, OR_BURGERS = 1, OR_EULER = 2 };
 typedef struct {
     int dim, p, m, nvars, flux, weight_mode;
     int nc, nq, periodic;
+    int bc;               /* boundary facets: 0 outside state = inside state; 1 outside state = 0 */
     double period, eps, alpha_w, rank_tol, h, gamma;
     double adv[3];
     const int *exps;      /* m x 3 exponents of the Taylor basis */
@@ -593,7 +594,9 @@ static void divergence_cell(const or_problem *P, int i, const real *u, const rea
             real um[OR_MAXV], up[OR_MAXV], fh[OR_MAXV];
             for (int var = 0; var < V; ++var) um[var] = fval[fval_index(P, var, i, lf, q)];
             if (j < 0) {
-                for (int var = 0; var < V; ++var) up[var] = um[var];   /* transmissive */
+                /* transmissive (u+ = u-), or a zero far field (u+ = 0): with the
+                 * upwind flux of linear advection, outflow unchanged and no inflow */
+                for (int var = 0; var < V; ++var) up[var] = P->bc == 1 ? 0.0 : um[var];
             } else {
                 const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
                 real dx[OR_MAXDIM];

@@ -18,6 +18,7 @@ EXPORTS = [
     "wlseno_mesh_upload", "wlseno_stencil_build", "wlseno_get_info", "wlseno_get_stencil",
     "wlseno_reconstruct", "wlseno_rhs", "wlseno_step", "wlseno_last_alpha", "wlseno_time_kernel",
     "wlseno_batch_add_mesh", "wlseno_batch_step", "wlseno_batch_last_alpha", "wlseno_set_graphs",
+    "wlseno_rhs_vjp", "wlseno_step_adjoint",
 ]
 
 
@@ -26,7 +27,7 @@ class Params(C.Structure):
         ("p", C.c_int32), ("n_lo", C.c_int32), ("n_hi", C.c_int32), ("flux", C.c_int32),
         ("weight_mode", C.c_int32), ("lanes", C.c_int32),
         ("eps", C.c_double), ("alpha_w", C.c_double), ("rank_tol", C.c_double),
-        ("velocity", C.c_double * 3), ("gamma", C.c_double),
+        ("velocity", C.c_double * 3), ("gamma", C.c_double), ("bc", C.c_int32),
     ]
 
 
@@ -79,6 +80,8 @@ def load():
     lib.wlseno_batch_step.argtypes = [vp, vp, dp, C.c_int]
     lib.wlseno_batch_last_alpha.argtypes = [vp, dp]
     lib.wlseno_set_graphs.argtypes = [vp, C.c_int]
+    lib.wlseno_rhs_vjp.argtypes = [vp, vp, vp, vp]
+    lib.wlseno_step_adjoint.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, vp, vp]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name not in ("wlseno_params_default", "wlseno_last_error"):

@@ -41,6 +41,13 @@ struct wlseno_ctx {
     hipStream_t cap = nullptr;
     hipGraphExec_t step2 = nullptr;
     double step2_h = 0.0;
+    // adjoint: transposed stencil, contributions, cotangents, checkpoints
+    bool adj_ready = false;
+    int64_t *tptr = nullptr;
+    int32_t *tidx = nullptr;
+    double *contrib = nullptr, *ga = nullptr, *gb = nullptr, *gc = nullptr;
+    double *ck = nullptr, *seg = nullptr;
+    size_t ck_cap = 0, seg_cap = 0;   // doubles
 };
 
 namespace {
@@ -76,6 +83,11 @@ void free_device(wlseno_ctx *c)
     c->allocs.clear();
     c->dm = DevMesh{};
     c->ubuf = c->kbuf = c->tbuf = nullptr;
+    c->adj_ready = false;
+    c->tptr = nullptr;
+    c->tidx = nullptr;
+    c->contrib = c->ga = c->gb = c->gc = c->ck = c->seg = nullptr;
+    c->ck_cap = c->seg_cap = 0;
 }
 
 void *dev_alloc(wlseno_ctx *c, size_t bytes)
@@ -85,6 +97,27 @@ void *dev_alloc(wlseno_ctx *c, size_t bytes)
     if (e != hipSuccess) throw Error{WLSENO_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
     c->allocs.push_back(p);
     return p;
+}
+
+// A device buffer of at least n doubles held in *p (capacity *cap), grown
+// after the stream has drained.
+double *dev_grow(wlseno_ctx *c, double **p, size_t *cap, size_t n)
+{
+    if (*p && *cap >= n) return *p;
+    if (*p) {
+        check_hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+        for (auto it = c->allocs.begin(); it != c->allocs.end(); ++it)
+            if (*it == *p) {
+                c->allocs.erase(it);
+                break;
+            }
+        (void)hipFree(*p);
+        *p = nullptr;
+        *cap = 0;
+    }
+    *p = (double *)dev_alloc(c, n * sizeof(double));
+    *cap = n;
+    return *p;
 }
 
 template <class T>
@@ -139,6 +172,7 @@ void upload_build(wlseno_ctx *c)
     dm.rank_tol = b.prm.rank_tol;
     dm.period = m.periodic ? m.period : 0.0;
     dm.gamma = b.prm.gamma;
+    dm.bc = b.prm.bc;
     for (int d = 0; d < 3; ++d) dm.vel[d] = b.prm.velocity[d];
     dm.geo = upload(c, b.geo);
     dm.vrel = upload(c, b.vrel);
@@ -254,6 +288,7 @@ void wlseno_params_default(wlseno_params *out)
     out->rank_tol = 1e-12;
     out->velocity[0] = 1.0;
     out->gamma = 1.4;
+    out->bc = 0;
 }
 
 wlseno_status wlseno_create(int device, wlseno_t *out)
@@ -441,6 +476,107 @@ wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev)
     check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
     stage(ctx, ctx->ubuf, nullptr, nullptr, ctx->tbuf, 0.0, 0.0, 1.0, 0, 0, ctx->stream);
     check_launch(launch_permute(ctx->dm, ctx->tbuf, dudt_dev, false, ctx->stream), "permute");
+    API_END(ctx)
+}
+
+namespace {
+
+// Transposed-stencil tables and cotangent buffers, built on first use.
+void adjoint_setup(wlseno_ctx *c)
+{
+    if (c->adj_ready) return;
+    if (!adjoint_supported(c->dm))
+        throw Error{WLSENO_EUNSUPPORTED, "the adjoint covers scalar linear advection on a single mesh"};
+    std::vector<int64_t> tptr;
+    std::vector<int32_t> tidx;
+    transpose_tables(c->build, c->dm.nc, c->dm.nf, tptr, tidx);
+    c->tptr = upload(c, tptr);
+    c->tidx = upload(c, tidx);
+    const size_t nct = (size_t)c->build.spad_off[kMaxBuckets] + (size_t)c->dm.nf * c->dm.nc;
+    c->contrib = (double *)dev_alloc(c, nct * sizeof(double));
+    c->ga = (double *)dev_alloc(c, c->dm.nc * sizeof(double));
+    c->gb = (double *)dev_alloc(c, c->dm.nc * sizeof(double));
+    c->gc = (double *)dev_alloc(c, c->dm.nc * sizeof(double));
+    c->adj_ready = true;
+}
+
+// out = A x + B y + C z + D J(u)^T v (device order; null vectors count as zero).
+void vjp(wlseno_ctx *c, const double *u, const double *v, const double *x, const double *y, const double *z,
+         double *out, double A, double B, double C, double D)
+{
+    double *cfn = c->contrib + c->build.spad_off[kMaxBuckets];
+    check_launch(launch_adjoint(c->dm, u, v, c->contrib, cfn, c->stream), "adjoint");
+    check_launch(launch_adjoint_gather(c->dm, c->tptr, c->tidx, c->contrib, x, y, z, out, A, B, C, D, c->stream),
+                 "adjoint gather");
+}
+
+}  // namespace
+
+wlseno_status wlseno_rhs_vjp(wlseno_t ctx, const double *u_dev, const double *v_dev, double *out_dev)
+{
+    API_BEGIN(ctx)
+    if (!u_dev || !v_dev || !out_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
+    if (out_dev == u_dev || out_dev == v_dev) throw Error{WLSENO_EINVAL, "out_dev must not alias an input"};
+    need_device(ctx);
+    adjoint_setup(ctx);
+    check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
+    check_launch(launch_permute(ctx->dm, v_dev, ctx->ga, true, ctx->stream), "permute");
+    vjp(ctx, ctx->ubuf, ctx->ga, nullptr, nullptr, nullptr, ctx->gb, 0.0, 0.0, 0.0, 1.0);
+    check_launch(launch_permute(ctx->dm, ctx->gb, out_dev, false, ctx->stream), "permute");
+    API_END(ctx)
+}
+
+wlseno_status wlseno_step_adjoint(wlseno_t ctx, const double *u0_dev, double dt, int n_steps, int ckpt_every,
+                                  const double *gT_dev, double *g0_dev)
+{
+    API_BEGIN(ctx)
+    if (!u0_dev || !gT_dev || !g0_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
+    if (!std::isfinite(dt) || n_steps < 0 || ckpt_every < 1)
+        throw Error{WLSENO_EINVAL, "dt finite, n_steps >= 0 and ckpt_every >= 1 required"};
+    need_device(ctx);
+    adjoint_setup(ctx);
+    const int64_t nc = ctx->dm.nc;
+    const int nseg = n_steps == 0 ? 0 : (n_steps + ckpt_every - 1) / ckpt_every;
+    const int E = n_steps < ckpt_every ? n_steps : ckpt_every;
+    dev_grow(ctx, &ctx->ck, &ctx->ck_cap, (size_t)(nseg > 0 ? nseg : 1) * nc);
+    dev_grow(ctx, &ctx->seg, &ctx->seg_cap, (size_t)(E > 0 ? E : 1) * 3 * nc);
+    double *u = ctx->ubuf;
+    const size_t bytes = (size_t)nc * sizeof(double);
+    // forward sweep: the state at the start of every segment
+    check_launch(launch_permute(ctx->dm, u0_dev, u, true, ctx->stream), "permute");
+    for (int sg = 0; sg < nseg; ++sg) {
+        check_hip(hipMemcpyAsync(ctx->ck + (size_t)sg * nc, u, bytes, hipMemcpyDeviceToDevice, ctx->stream),
+                  "hipMemcpyAsync");
+        const int s_end = (sg + 1) * ckpt_every < n_steps ? (sg + 1) * ckpt_every : n_steps;
+        if (sg + 1 < nseg)
+            for (int s = sg * ckpt_every; s < s_end; ++s) rk3_step(ctx, dt, 0, ctx->stream);
+    }
+    // reverse sweep, segment by segment: recompute its stage states, then
+    // transpose each RK3 step (g = cotangent of the step's output):
+    //   g2 = 2/3 g + 2/3 dt J(U2)^T g;  g1 = 1/4 g2 + 1/4 dt J(U1)^T g2;
+    //   g  = 1/3 g + 3/4 g2 + g1 + dt J(U)^T g1
+    double *g = ctx->ga, *g2 = ctx->gb, *g1 = ctx->gc;
+    check_launch(launch_permute(ctx->dm, gT_dev, g, true, ctx->stream), "permute");
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int s0 = sg * ckpt_every;
+        const int ns = (s0 + ckpt_every < n_steps ? s0 + ckpt_every : n_steps) - s0;
+        check_hip(hipMemcpyAsync(u, ctx->ck + (size_t)sg * nc, bytes, hipMemcpyDeviceToDevice, ctx->stream),
+                  "hipMemcpyAsync");
+        for (int t = 0; t < ns; ++t) {
+            double *U = ctx->seg + (size_t)(3 * t) * nc, *U1 = U + nc, *U2 = U1 + nc;
+            check_hip(hipMemcpyAsync(U, u, bytes, hipMemcpyDeviceToDevice, ctx->stream), "hipMemcpyAsync");
+            stage(ctx, U, U, U, U1, 1.0, 0.0, dt, 1, 0, ctx->stream);
+            stage(ctx, U1, U, U1, U2, 0.75, 0.25, 0.25 * dt, 1, 0, ctx->stream);
+            if (t + 1 < ns) stage(ctx, U2, U, U2, u, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt, 1, 0, ctx->stream);
+        }
+        for (int t = ns - 1; t >= 0; --t) {
+            const double *U = ctx->seg + (size_t)(3 * t) * nc, *U1 = U + nc, *U2 = U1 + nc;
+            vjp(ctx, U2, g, g, nullptr, nullptr, g2, 2.0 / 3.0, 0.0, 0.0, 2.0 / 3.0 * dt);
+            vjp(ctx, U1, g2, g2, nullptr, nullptr, g1, 0.25, 0.0, 0.0, 0.25 * dt);
+            vjp(ctx, U, g1, g, g2, g1, g, 1.0 / 3.0, 0.75, 1.0, dt);
+        }
+    }
+    check_launch(launch_permute(ctx->dm, g, g0_dev, false, ctx->stream), "permute");
     API_END(ctx)
 }
 

@@ -93,6 +93,7 @@ void build_setup(const HostMesh &mesh, const wlseno_params &prm, Build &b);
 struct DevMesh {
     int dim = 0, p = 0, m = 0, nq = 0, nf = 0, nvars = 1, gs = 0;
     int flux = 0, weight_mode = 0, max_stencil = 0;
+    int bc = 0;   // boundary facets: 0 outside state = inside state, 1 outside state = 0
     int lanes = 0;   // lanes per cell in the reconstruction: 0 = automatic, 4 or 8
     int64_t nc = 0;
     int nbuckets = 0;
@@ -123,6 +124,19 @@ constexpr int kAlphaSlotsBatch = 8;   // slots per mesh of a batch
 // (dim, p, stencil size) combination has a compiled variant.
 bool reconstruct_supported(const DevMesh &dm);
 int launch_permute(const DevMesh &dm, const double *in, double *out, bool to_device_order, void *stream);
+// Transposed Jacobian of the advection right-hand side: per-cell
+// contributions (padded stencil slots cpad, facet slots cfn [F][nc]), then
+// their sums over the transposed stencil, combined as
+// out = A x + B y + C z + D (J^T v) (null vectors count as zero).
+bool adjoint_supported(const DevMesh &dm);
+int launch_adjoint(const DevMesh &dm, const double *u, const double *v, double *cpad, double *cfn, void *stream);
+int launch_adjoint_gather(const DevMesh &dm, const int64_t *tptr, const int32_t *tidx, const double *contrib,
+                          const double *x, const double *y, const double *z, double *out, double A, double B,
+                          double C, double D, void *stream);
+// Transposed stencil: for each device cell j, the contribution indices t
+// (padded slots first, then npad + lf nc + i for facet slots) that read j,
+// in increasing t.
+void transpose_tables(const Build &b, int64_t nc, int nf, std::vector<int64_t> &tptr, std::vector<int32_t> &tidx);
 int launch_clear_alpha(const DevMesh &dm, void *stream);
 int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *coef_user,
                        double *fv_user, int32_t *rank_user, void *stream);

@@ -276,6 +276,225 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
+// ------------------------------------------------------ per-cell solve
+
+// Centroid offset of a stencil cell (record gxs: centroid, then moments) from
+// x_c, wrapped into the period on a periodic line.
+template <int DIM>
+__device__ __forceinline__ void centroid_offset(const double *gxs, const double (&xc)[DIM], double period,
+                                                double (&dl)[DIM])
+{
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) dl[d] = gxs[d] - xc[d];
+    if constexpr (DIM == 1) {
+        if (period > 0.0)
+            dl[0] = dl[0] > 0.5 * period ? dl[0] - period : (dl[0] < -0.5 * period ? dl[0] + period : dl[0]);
+    }
+}
+
+// Average over a stencil cell of every Taylor monomial about x_c, from its
+// centroid offset dl and centred moments nu(a) = mu(a)/a! (2 <= |a| <= p-1):
+//   sum_{t <= k} (dl^{a_k - a_t} / (a_k - a_t)!) nu(a_t),  nu(0) = 1, nu(|a| = 1) = 0.
+template <int DIM, int P>
+__device__ __forceinline__ void taylor_row(const double (&dl)[DIM], const double *nu, double (&row)[Basis<DIM, P>::M])
+{
+    constexpr Basis<DIM, P> B{};
+    constexpr int M = Basis<DIM, P>::M;
+    double pw[DIM][P];
+    scaled_powers<DIM, P>(dl, pw);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        double acc = 1.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) acc *= pw[d][B.e[k][d]];
+#pragma unroll
+        for (int t = 1 + DIM; t < M; ++t) {
+            if (B.le(t, k)) {
+                double ph = nu[t - 1 - DIM];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) ph *= pw[d][B.e[k][d] - B.e[t][d]];
+                acc += ph;
+            }
+        }
+        row[k] = acc;
+    }
+}
+
+// Column scaling S = diag(1 / ||(W A)_k||): sc[k], and A <- A S.
+template <int M, int G, int RPL>
+__device__ __forceinline__ void scale_columns(double (&A)[RPL][M], double (&sc)[M])
+{
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) t = fma(A[s][k], A[s][k], t);
+        t = group_sum<G>(t);
+        sc[k] = t > 0.0 ? rsq_nr(t) : 0.0;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) A[s][k] *= sc[k];
+    }
+}
+
+// Householder QR with column pivoting of the rows A (row r = s G + g in lane
+// g, slot s) and right-hand side bv, in place.  R row k goes to lane k % G,
+// slot k / G of Rs (with (Q^T b)_k in cs); rd = diag R, rinv = 1 / diag R,
+// pm = the column order, sc is permuted along.
+template <int M, int G, int RPL, int RS>
+__device__ __forceinline__ void qrcp(double (&A)[RPL][M], double (&bv)[RPL], double (&sc)[M], int g, int (&pm)[M],
+                                     double (&rd)[M], double (&rinv)[M], double (&Rs)[RS][M], double (&cs)[RS])
+{
+    // Householder QR with column pivoting.  Rows < k are retired into the
+    // owner lane's R store (Rs, cs) and zeroed in A, so every reduction runs
+    // over all slots without row predicates.  Column exchanges and row
+    // retirement run under lane masks (cells of a wave pivot independently);
+    // an exchange no cell of the wave needs is skipped.
+#pragma unroll
+    for (int k = 0; k < M; ++k) pm[k] = k;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+        cs[s] = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) Rs[s][k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        double best;
+        if (k == 0) {
+            // After the scaling every nonzero column has unit norm and column 0
+            // (the weights themselves) is never zero, so under the tie rule the
+            // first pivot is always column 0: no search, no exchange.
+            double t = 0.0;
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) t = fma(A[s][0], A[s][0], t);
+            best = group_sum<G>(t);
+        } else {
+            double eta[M];
+#pragma unroll
+            for (int cc = k; cc < M; ++cc) {
+                double t = 0.0;
+#pragma unroll
+                for (int s = 0; s < RPL; ++s) t = fma(A[s][cc], A[s][cc], t);
+                eta[cc] = group_sum<G>(t);
+            }
+            // pivot: lowest column index among those within a relative kPivotTie
+            // of the largest partial norm (rounding must not order ties)
+            double mx[M];
+#pragma unroll
+            for (int cc = k; cc < M; ++cc) mx[cc] = eta[cc];
+#pragma unroll
+            for (int w = 1; w < M - k; w *= 2)
+#pragma unroll
+                for (int cc = k; cc + w < M; cc += 2 * w) mx[cc] = fmax(mx[cc], mx[cc + w]);
+            const double tie = mx[k] * (1.0 - kPivotTie);
+            unsigned msk = 0u;
+#pragma unroll
+            for (int cc = k; cc < M; ++cc) msk |= (eta[cc] >= tie) ? (1u << cc) : 0u;
+            const int piv = msk ? __builtin_ctz(msk) : k;
+            best = eta[k];
+#pragma unroll
+            for (int cc = k + 1; cc < M; ++cc) {
+                if (piv == cc) {
+                    best = eta[cc];
+#pragma unroll
+                    for (int s = 0; s < RPL; ++s) {
+                        const double t0 = A[s][k];
+                        A[s][k] = A[s][cc];
+                        A[s][cc] = t0;
+                    }
+                    // a pivot exchanges whole columns: the R entries of retired rows too
+#pragma unroll
+                    for (int s = 0; s < RS; ++s) {
+                        if (s * G < k) {
+                            const double t0 = Rs[s][k];
+                            Rs[s][k] = Rs[s][cc];
+                            Rs[s][cc] = t0;
+                        }
+                    }
+                    const double s0 = sc[k];
+                    sc[k] = sc[cc];
+                    sc[cc] = s0;
+                    const int p0 = pm[k];
+                    pm[k] = pm[cc];
+                    pm[cc] = p0;
+                }
+            }
+        }
+        const double alpha = group_bcast<G>(A[k / G][k], k % G, g);
+        const bool nz = best > 0.0;
+        // beta = -sign(alpha) ||x||, and 1/beta, from one reciprocal square root
+        const double rs = nz ? rsq_nr(best) : 0.0;
+        const double beta = nz ? -copysign(best * rs, alpha) : 0.0;
+        const double rb = -copysign(rs, alpha);
+        const double tau = (beta - alpha) * rb;
+        const double scal = nz ? rcp_nr(alpha - beta) : 0.0;
+        const bool own = g == (k % G);
+        double v[RPL];
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) v[s] = A[s][k] * scal;
+        v[k / G] = own ? 1.0 : v[k / G];
+#pragma unroll
+        for (int cc = k + 1; cc < M; ++cc) {
+            double t = 0.0;
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) t = fma(v[s], A[s][cc], t);
+            const double tw = tau * group_sum<G>(t);
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) A[s][cc] = fma(-tw, v[s], A[s][cc]);
+        }
+        {
+            double t = 0.0;
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) t = fma(v[s], bv[s], t);
+            const double tw = tau * group_sum<G>(t);
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) bv[s] = fma(-tw, v[s], bv[s]);
+        }
+        rd[k] = beta;
+        rinv[k] = rb;
+        if (own) {
+#pragma unroll
+            for (int cc = k + 1; cc < M; ++cc) {
+                Rs[k / G][cc] = A[k / G][cc];
+                A[k / G][cc] = 0.0;
+            }
+            cs[k / G] = bv[k / G];
+            bv[k / G] = 0.0;
+        }
+    }
+}
+
+// Numerical rank: leading k with |R_kk| > tol |R_11|.
+template <int M>
+__device__ __forceinline__ int num_rank(const double (&rd)[M], double tol)
+{
+    const double thr = tol * fabs(rd[0]);
+    int rank = 0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        ok = ok && (fabs(rd[k]) > thr);
+        rank += ok ? 1 : 0;
+    }
+    return rank;
+}
+
+// Back substitution R_{1:r,1:r} y = c_{1:r} (c_k held by the owner lane of
+// row k), y_k = 0 beyond the rank; y ends up in every lane of the group.
+template <int M, int G, int RS>
+__device__ __forceinline__ void back_solve(const double (&Rs)[RS][M], const double (&cs)[RS], const double (&rinv)[M],
+                                           int rank, int g, double (&y)[M])
+{
+#pragma unroll
+    for (int k = M - 1; k >= 0; --k) {
+        double acc = cs[k / G];
+#pragma unroll
+        for (int j = k + 1; j < M; ++j) acc = fma(-Rs[k / G][j], y[j], acc);
+        const double yk = group_bcast<G>(acc, k % G, g) * rinv[k];
+        y[k] = (k < rank) ? yk : 0.0;
+    }
+}
+
 // --------------------------------------------------------------- K1
 // Reconstruction of one cell by a group of G lanes (g = lane in the group),
 // component by component (V = 1, or DIM + 2 conserved variables for Euler).
@@ -391,37 +610,10 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
         const int r = s * G + g;
         const bool valid = jrow[s] >= 0;
         double dl[DIM];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) dl[d] = gx[s][d] - xc[d];
-        if constexpr (DIM == 1) {
-            const double L = a.period;
-            if (L > 0.0) dl[0] = dl[0] > 0.5 * L ? dl[0] - L : (dl[0] < -0.5 * L ? dl[0] + L : dl[0]);
-        }
-        double nu[NMOM > 0 ? NMOM : 1];
-#pragma unroll
-        for (int t = 0; t < NMOM; ++t) nu[t] = gx[s][DIM + t];
+        centroid_offset<DIM>(gx[s], xc, a.period, dl);
         const double uj = ug[s];
-        double pw[DIM][P];
-        scaled_powers<DIM, P>(dl, pw);
-        // average over cell j of the Taylor monomial k about x_c:
-        //   sum_{t <= k} (delta^{a_k - a_t} / (a_k - a_t)!) nu_j(a_t), nu(0) = 1, nu(|a|=1) = 0
         double row[M];
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            double acc = 1.0;
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) acc *= pw[d][B.e[k][d]];
-#pragma unroll
-            for (int t = 1 + DIM; t < M; ++t) {
-                if (B.le(t, k)) {
-                    double ph = nu[t - 1 - DIM];
-#pragma unroll
-                    for (int d = 0; d < DIM; ++d) ph *= pw[d][B.e[k][d] - B.e[t][d]];
-                    acc += ph;
-                }
-            }
-            row[k] = acc;
-        }
+        taylor_row<DIM, P>(dl, gx[s] + DIM, row);
         double w = 1.0;
         if (a.weight_mode == 0) {
             const double du = uj - uc;
@@ -435,160 +627,18 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
         bv[s] = w * uj;
     }
 
-    // column scaling S = diag(1 / ||(W A)_k||)
     double sc[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        double t = 0.0;
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) t = fma(A[s][k], A[s][k], t);
-        t = group_sum<G>(t);
-        sc[k] = t > 0.0 ? rsq_nr(t) : 0.0;
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) A[s][k] *= sc[k];
-    }
-
-    // Householder QR with column pivoting.  Rows < k are retired into the
-    // owner lane's R store (Rs, cs) and zeroed in A, so every reduction runs
-    // over all slots without row predicates.  Column exchanges and row
-    // retirement run under lane masks (cells of a wave pivot independently);
-    // an exchange no cell of the wave needs is skipped.
+    scale_columns<M, G, RPL>(A, sc);
     int pm[M];
     double rd[M], rinv[M];
     double Rs[RS][M], cs[RS];
-#pragma unroll
-    for (int k = 0; k < M; ++k) pm[k] = k;
-#pragma unroll
-    for (int s = 0; s < RS; ++s) {
-        cs[s] = 0.0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) Rs[s][k] = 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        double best;
-        if (k == 0) {
-            // After the scaling every nonzero column has unit norm and column 0
-            // (the weights themselves) is never zero, so under the tie rule the
-            // first pivot is always column 0: no search, no exchange.
-            double t = 0.0;
-#pragma unroll
-            for (int s = 0; s < RPL; ++s) t = fma(A[s][0], A[s][0], t);
-            best = group_sum<G>(t);
-        } else {
-            double eta[M];
-#pragma unroll
-            for (int cc = k; cc < M; ++cc) {
-                double t = 0.0;
-#pragma unroll
-                for (int s = 0; s < RPL; ++s) t = fma(A[s][cc], A[s][cc], t);
-                eta[cc] = group_sum<G>(t);
-            }
-            // pivot: lowest column index among those within a relative kPivotTie
-            // of the largest partial norm (rounding must not order ties)
-            double mx[M];
-#pragma unroll
-            for (int cc = k; cc < M; ++cc) mx[cc] = eta[cc];
-#pragma unroll
-            for (int w = 1; w < M - k; w *= 2)
-#pragma unroll
-                for (int cc = k; cc + w < M; cc += 2 * w) mx[cc] = fmax(mx[cc], mx[cc + w]);
-            const double tie = mx[k] * (1.0 - kPivotTie);
-            unsigned msk = 0u;
-#pragma unroll
-            for (int cc = k; cc < M; ++cc) msk |= (eta[cc] >= tie) ? (1u << cc) : 0u;
-            const int piv = msk ? __builtin_ctz(msk) : k;
-            best = eta[k];
-#pragma unroll
-            for (int cc = k + 1; cc < M; ++cc) {
-                if (piv == cc) {
-                    best = eta[cc];
-#pragma unroll
-                    for (int s = 0; s < RPL; ++s) {
-                        const double t0 = A[s][k];
-                        A[s][k] = A[s][cc];
-                        A[s][cc] = t0;
-                    }
-                    // a pivot exchanges whole columns: the R entries of retired rows too
-#pragma unroll
-                    for (int s = 0; s < RS; ++s) {
-                        if (s * G < k) {
-                            const double t0 = Rs[s][k];
-                            Rs[s][k] = Rs[s][cc];
-                            Rs[s][cc] = t0;
-                        }
-                    }
-                    const double s0 = sc[k];
-                    sc[k] = sc[cc];
-                    sc[cc] = s0;
-                    const int p0 = pm[k];
-                    pm[k] = pm[cc];
-                    pm[cc] = p0;
-                }
-            }
-        }
-        const double alpha = group_bcast<G>(A[k / G][k], k % G, g);
-        const bool nz = best > 0.0;
-        // beta = -sign(alpha) ||x||, and 1/beta, from one reciprocal square root
-        const double rs = nz ? rsq_nr(best) : 0.0;
-        const double beta = nz ? -copysign(best * rs, alpha) : 0.0;
-        const double rb = -copysign(rs, alpha);
-        const double tau = (beta - alpha) * rb;
-        const double scal = nz ? rcp_nr(alpha - beta) : 0.0;
-        const bool own = g == (k % G);
-        double v[RPL];
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) v[s] = A[s][k] * scal;
-        v[k / G] = own ? 1.0 : v[k / G];
-#pragma unroll
-        for (int cc = k + 1; cc < M; ++cc) {
-            double t = 0.0;
-#pragma unroll
-            for (int s = 0; s < RPL; ++s) t = fma(v[s], A[s][cc], t);
-            const double tw = tau * group_sum<G>(t);
-#pragma unroll
-            for (int s = 0; s < RPL; ++s) A[s][cc] = fma(-tw, v[s], A[s][cc]);
-        }
-        {
-            double t = 0.0;
-#pragma unroll
-            for (int s = 0; s < RPL; ++s) t = fma(v[s], bv[s], t);
-            const double tw = tau * group_sum<G>(t);
-#pragma unroll
-            for (int s = 0; s < RPL; ++s) bv[s] = fma(-tw, v[s], bv[s]);
-        }
-        rd[k] = beta;
-        rinv[k] = rb;
-        if (own) {
-#pragma unroll
-            for (int cc = k + 1; cc < M; ++cc) {
-                Rs[k / G][cc] = A[k / G][cc];
-                A[k / G][cc] = 0.0;
-            }
-            cs[k / G] = bv[k / G];
-            bv[k / G] = 0.0;
-        }
-    }
+    qrcp<M, G, RPL, RS>(A, bv, sc, g, pm, rd, rinv, Rs, cs);
 
     // numerical rank and back substitution on the leading r x r block
-    // (R_kk = beta_k, whose reciprocal the factorisation kept)
-    const double thr = a.rank_tol * fabs(rd[0]);
-    int rank = 0;
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        ok = ok && (fabs(rd[k]) > thr);
-        rank += ok ? 1 : 0;
-    }
+    const int rank = num_rank<M>(rd, a.rank_tol);
     double y[M];
-#pragma unroll
-    for (int k = M - 1; k >= 0; --k) {
-        double acc = cs[k / G];
-#pragma unroll
-        for (int j = k + 1; j < M; ++j) acc = fma(-Rs[k / G][j], y[j], acc);
-        const double yk = group_bcast<G>(acc, k % G, g) * rinv[k];
-        y[k] = (k < rank) ? yk : 0.0;
-    }
+    back_solve<M, G, RS>(Rs, cs, rinv, rank, g, y);
+
     // coefficients in the original basis order, v = S E y, through LDS: lane g
     // stores the entries k = g, g+G, ... at their original positions
     double *lc = lds + slot * M;
@@ -768,6 +818,310 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
     }
 }
 
+// ------------------------------------------------------------ adjoint
+// Transposed Jacobian of the advection right-hand side, v -> J(u)^T v, in two
+// kernels: k_adjoint writes, per cell i, the contribution of (dL/du)^T v
+// through cell i's reconstruction to every cell its stencil reads (one value
+// per padded stencil slot, one per facet slot for the centre weight's
+// smallest-indicator neighbour); k_adjoint_gather sums them per cell over the
+// transposed stencil in a fixed order.
+
+struct AArgs {
+    int64_t nc;
+    const double *u, *v;               // state and cotangent of L(u), device order
+    const double *geo, *vrel, *normal, *rvol;
+    const int32_t *spad, *sib;
+    double *cpad, *cfn;                // contributions: padded stencil slots; facet slots [F][nc]
+    double eh2, alpha_w, rank_tol, period;
+    int weight_mode, bc;
+    double vel[3];
+    int64_t cell0[kMaxBuckets + 1];
+    int blk0[kMaxBuckets + 1];
+    int64_t spad_off[kMaxBuckets + 1];
+    int stride[kMaxBuckets];
+};
+
+template <int DIM, int P, int G, int RPL>
+__device__ __forceinline__ void adjoint_cell(const AArgs &a, int64_t cell, int64_t cell_begin, int64_t cell_end,
+                                             int64_t pad_off, int stride, int g, double *lds, int slot)
+{
+    constexpr Basis<DIM, P> B{};
+    constexpr int M = Basis<DIM, P>::M;
+    constexpr int F = DIM + 1;
+    constexpr int Q = num_q<DIM, P>();
+    constexpr int GS = geo_stride<DIM, P>();
+    constexpr int RS = (M + G - 1) / G;
+    constexpr int FPL = (F + G - 1) / G;
+    constexpr int CPB = 256 / G;
+
+    const bool live = cell < cell_end;
+    const int64_t c = live ? cell : cell_end - 1;
+    const int32_t *srow = a.spad + pad_off + (c - cell_begin) * stride;
+    const int64_t N = a.nc;
+    const double eh2 = a.eh2;
+
+    double xc[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xc[d] = a.geo[c * GS + d];
+    const double uc = a.u[c];
+    int32_t sb[F];
+#pragma unroll
+    for (int lf = 0; lf < F; ++lf) sb[lf] = a.sib[lf * N + c];
+    int32_t jrow[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * G + g;
+        const int32_t j = srow[r < stride ? r : stride - 1];
+        jrow[s] = (live && r < stride && j >= 0) ? j : -1;
+    }
+    // centre indicator: smallest over the facet neighbours (first one on ties)
+    double bmin = -1.0, unbmin = uc;
+    int lfmin = -1;
+#pragma unroll
+    for (int lf = 0; lf < F; ++lf) {
+        const double un = a.u[sb[lf] >= 0 ? (sb[lf] >> 2) : c];
+        const double du = un - uc;
+        const double bt = du * du + eh2;
+        const bool take = sb[lf] >= 0 && (bmin < 0.0 || bt < bmin);
+        bmin = take ? bt : bmin;
+        unbmin = take ? un : unbmin;
+        lfmin = take ? lf : lfmin;
+    }
+    bmin = bmin < 0.0 ? eh2 : bmin;
+
+    // the forward solve again: weighted rows, scaling, QRCP, coefficients
+    double A[RPL][M], bv[RPL], wt[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * G + g;
+        const int64_t j = jrow[s] >= 0 ? (int64_t)jrow[s] : c;
+        double dl[DIM];
+        centroid_offset<DIM>(a.geo + j * GS, xc, a.period, dl);
+        double row[M];
+        taylor_row<DIM, P>(dl, a.geo + j * GS + DIM, row);
+        const double uj = a.u[j];
+        double w = 1.0;
+        if (a.weight_mode == 0) {
+            const double du = uj - uc;
+            const double num = (r == 0) ? a.alpha_w : 1.0;
+            const double den = (r == 0) ? bmin : du * du + eh2;
+            w = num * rcp_nr(den);
+        }
+        w = jrow[s] >= 0 ? w : 0.0;
+        wt[s] = w;
+#pragma unroll
+        for (int k = 0; k < M; ++k) A[s][k] = w * row[k];
+        bv[s] = w * uj;
+    }
+    double sc[M];
+    scale_columns<M, G, RPL>(A, sc);
+    int pm[M];
+    double rd[M], rinv[M];
+    double Rs[RS][M], cs[RS];
+    qrcp<M, G, RPL, RS>(A, bv, sc, g, pm, rd, rinv, Rs, cs);
+    const int rank = num_rank<M>(rd, a.rank_tol);
+    double y[M];
+    back_solve<M, G, RS>(Rs, cs, rinv, rank, g, y);
+    double *lc = lds + slot * M;            // coefficients, then lambda
+    double *lg = lds + (CPB + slot) * M;    // cotangent of the coefficients
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+        if ((k % G) == g) lc[pm[k]] = sc[k] * y[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double coef[M];
+#pragma unroll
+    for (int o = 0; o < M; ++o) coef[o] = lc[o];
+
+    // cotangent of this cell's facet values: facet point value a enters its
+    // own cell's L with -rvol_i w_q dF/da and the neighbour's with
+    // +rvol_j w_q dF/da (upwind flux with the area-scaled normal m)
+    const double vi = a.v[c], rvi = a.rvol[c];
+    double gco[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) gco[k] = 0.0;
+#pragma unroll
+    for (int t = 0; t < FPL; ++t) {
+        const int lf0 = g + t * G;
+        const bool has = lf0 < F;
+        const int lf = has ? lf0 : 0;
+        const int32_t sj = sb[lf];
+        double am = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) am += a.vel[d] * a.normal[(lf * N + c) * DIM + d];
+        const int64_t jn = sj >= 0 ? (int64_t)(sj >> 2) : c;   // clamped: loads stay in bounds
+        const double vj = sj >= 0 ? a.v[jn] : 0.0;
+        const double rvj = sj >= 0 ? a.rvol[jn] : 0.0;
+        // boundary: F = am a (transmissive) or 1/2 (am + |am|) a (zero outside state)
+        const double dfb = a.bc ? 0.5 * (am + fabs(am)) : am;
+        const double coefa = sj >= 0 ? 0.5 * (am + fabs(am)) * (rvj * vj - rvi * vi) : -rvi * vi * dfb;
+        double ea[DIM], eb[DIM];
+        if constexpr (DIM < 3) {
+            const int ia = DIM == 1 ? (lf == 0 ? 1 : 0) : (lf == 2 ? 0 : lf + 1);
+            const int ib = DIM == 1 ? ia : (lf == 0 ? 2 : lf - 1);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                ea[d] = a.vrel[(c * F + ia) * DIM + d];
+                eb[d] = a.vrel[(c * F + ib) * DIM + d];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            double x[DIM];
+            if constexpr (DIM < 3)
+                edge_point<DIM, Q>(ea, eb, q, x);
+            else
+                facet_point<DIM, Q>(a.vrel + c * F * DIM, lf, q, x);
+            double pw[DIM][P];
+            scaled_powers<DIM, P>(x, pw);
+            const double ga = (has && live) ? quad_weight<DIM, Q>(q) * coefa : 0.0;
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                double ph = ga;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) ph *= pw[d][B.e[k][d]];
+                gco[k] += ph;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) gco[k] = group_sum<G>(gco[k]);
+
+    // lambda = S E_r (R^T R)^-1 E_r^T S gco on the leading rank columns:
+    // forward substitution R^T z = E^T S gco, then R l = z
+    if (g == 0) {
+#pragma unroll
+        for (int o = 0; o < M; ++o) lg[o] = gco[o];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double z[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < k; ++j) t += (g == (j % G)) ? Rs[j / G][k] * z[j] : 0.0;
+        t = group_sum<G>(t);
+        const double gy = sc[k] * lg[pm[k]];
+        z[k] = (k < rank) ? (gy - t) * rinv[k] : 0.0;
+    }
+    double lam[M];
+#pragma unroll
+    for (int k = M - 1; k >= 0; --k) {
+        double acc = z[k];
+#pragma unroll
+        for (int j = k + 1; j < M; ++j) acc = fma(-Rs[k / G][j], lam[j], acc);
+        const double lk = group_bcast<G>(acc, k % G, g) * rinv[k];
+        lam[k] = (k < rank) ? lk : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+        if ((k % G) == g) lc[pm[k]] = sc[k] * lam[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double lo[M];
+#pragma unroll
+    for (int o = 0; o < M; ++o) lo[o] = lc[o];
+
+    // contributions: b = W u_S gives W^2 A lambda; the weights give
+    // 2 w (A lambda) (u_S - A v) through d w / d u
+    double to_c = 0.0, to_nb = 0.0;
+    double slotv[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * G + g;
+        const bool valid = jrow[s] >= 0;
+        const int64_t j = valid ? (int64_t)jrow[s] : c;
+        double dl[DIM];
+        centroid_offset<DIM>(a.geo + j * GS, xc, a.period, dl);
+        double row[M];
+        taylor_row<DIM, P>(dl, a.geo + j * GS + DIM, row);
+        const double uj = a.u[j];
+        double al = 0.0, av = 0.0;
+#pragma unroll
+        for (int o = 0; o < M; ++o) {
+            al = fma(row[o], lo[o], al);
+            av = fma(row[o], coef[o], av);
+        }
+        const double w = wt[s];
+        const double bbar = w * w * al;
+        const double wbar = 2.0 * w * al * (uj - av);
+        double own = bbar;
+        if (a.weight_mode == 0 && valid) {
+            if (r == 0) {
+                // w_0 = alpha_w / beta_min, beta_min = (u_nb - u_i)^2 + eps h^2
+                const double d = lfmin >= 0 ? 2.0 * (unbmin - uc) : 0.0;
+                const double dw = -w * w / a.alpha_w;   // d w_0 / d beta
+                to_nb += wbar * dw * d;
+                to_c -= wbar * dw * d;
+            } else {
+                // w_r = 1 / beta_r, beta_r = (u_j - u_i)^2 + eps h^2
+                const double d = 2.0 * (uj - uc);
+                own += wbar * (-w * w) * d;
+                to_c += wbar * (w * w) * d;
+            }
+        }
+        slotv[s] = valid ? own : 0.0;
+    }
+    to_c = group_sum<G>(to_c);
+    to_nb = group_sum<G>(to_nb);
+    if (live) {
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const int r = s * G + g;
+            if (r < stride) a.cpad[pad_off + (c - cell_begin) * stride + r] = slotv[s] + (r == 0 ? to_c : 0.0);
+        }
+        if (g == 0) {
+#pragma unroll
+            for (int lf = 0; lf < F; ++lf) a.cfn[lf * N + c] = lf == lfmin ? to_nb : 0.0;
+        }
+    }
+}
+
+template <int DIM, int P, int G, int R0, int R1, int R2>
+__global__ void __launch_bounds__(256) k_adjoint(AArgs a)
+{
+    constexpr int CPB = 256 / G;
+    __shared__ double lds[2 * CPB * Basis<DIM, P>::M];
+    const int L = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int g = (int)(threadIdx.x % G);
+    const int slot = (int)(threadIdx.x / G);
+    if (L < a.blk0[1]) {
+        const int64_t cell = a.cell0[0] + (int64_t)(L - a.blk0[0]) * CPB + slot;
+        adjoint_cell<DIM, P, G, R0>(a, cell, a.cell0[0], a.cell0[1], a.spad_off[0], a.stride[0], g, lds, slot);
+    } else if (L < a.blk0[2]) {
+        const int64_t cell = a.cell0[1] + (int64_t)(L - a.blk0[1]) * CPB + slot;
+        adjoint_cell<DIM, P, G, R1>(a, cell, a.cell0[1], a.cell0[2], a.spad_off[1], a.stride[1], g, lds, slot);
+    } else {
+        const int64_t cell = a.cell0[2] + (int64_t)(L - a.blk0[2]) * CPB + slot;
+        adjoint_cell<DIM, P, G, R2>(a, cell, a.cell0[2], a.cell0[3], a.spad_off[2], a.stride[2], g, lds, slot);
+    }
+}
+
+// out = A x + B y + C z + D sum_{t in T(j)} contrib[t], per cell j (device order);
+// null vectors count as zero.
+__global__ void __launch_bounds__(256) k_adjoint_gather(int64_t nc, const int64_t *tptr, const int32_t *tidx,
+                                                        const double *contrib, const double *x, const double *y,
+                                                        const double *z, double *out, double A, double B,
+                                                        double C, double D)
+{
+    const int64_t j = (int64_t)xcd_block((int)blockIdx.x, (int)gridDim.x) * 256 + threadIdx.x;
+    if (j >= nc) return;
+    double s = 0.0;
+    for (int64_t t = tptr[j]; t < tptr[j + 1]; ++t) s += contrib[tidx[t]];
+    double o = D * s;
+    if (x) o += A * x[j];
+    if (y) o += B * y[j];
+    if (z) o += C * z[j];
+    out[j] = o;
+}
+
 // --------------------------------------------------------------- K2/K3
 struct UArgs {
     int nc;
@@ -784,6 +1138,7 @@ struct UArgs {
     double vel[3];
     double gamma;
     int mode;
+    int bc;
 };
 
 // Euler normal flux F(U).m for the area-scaled normal m (linear in m).
@@ -884,13 +1239,16 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
 #pragma unroll
         for (int v = 0; v < V; ++v) facc[v] = 0.0;
         if (s < 0) {
-            // transmissive boundary: outside state equals inside state
+            // boundary: outside state = inside state (transmissive) or zero
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                double uo[V], fl[V];
+                double uo[V], ux[V], fl[V];
 #pragma unroll
-                for (int v = 0; v < V; ++v) uo[v] = a.fv[((v * F + lf) * N + c) * Q + q];
-                lf_flux<DIM, FLUX, V>(uo, uo, m, alpha, vel, a.gamma, fl);
+                for (int v = 0; v < V; ++v) {
+                    uo[v] = a.fv[((v * F + lf) * N + c) * Q + q];
+                    ux[v] = a.bc ? 0.0 : uo[v];
+                }
+                lf_flux<DIM, FLUX, V>(uo, ux, m, alpha, vel, a.gamma, fl);
 #pragma unroll
                 for (int v = 0; v < V; ++v) facc[v] += quad_weight<DIM, Q>(q) * fl[v];
             }
@@ -1004,6 +1362,20 @@ int launch_k23(const DevMesh &dm, const UArgs &args, hipStream_t st)
 }
 
 }  // namespace
+
+template <int DIM, int P, int G, int R0, int R1, int R2>
+int launch_adj(AArgs args, hipStream_t st)
+{
+    int nb = 0;
+    for (int b = 0; b < kMaxBuckets; ++b) {
+        args.blk0[b] = nb;
+        nb += blocks_for(args.cell0[b + 1] - args.cell0[b], 256 / G);
+    }
+    args.blk0[kMaxBuckets] = nb;
+    if (nb == 0) return 0;
+    hipLaunchKernelGGL((k_adjoint<DIM, P, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
+    return (int)hipGetLastError();
+}
 
 std::vector<int> stencil_capacities(int dim, int p)
 {
@@ -1121,6 +1493,7 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
     a.vel[2] = dm.vel[2];
     a.gamma = dm.gamma;
     a.mode = mode;
+    a.bc = dm.bc;
     hipStream_t st = (hipStream_t)stream;
     if (dm.dim == 1) return launch_k23<1, 1>(dm, a, st);
     if (dm.dim == 2) {
@@ -1129,6 +1502,65 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
     }
     if (dm.dim == 3 && dm.nq == 3) return launch_k23<3, 3>(dm, a, st);
     return (int)hipErrorInvalidValue;
+}
+
+bool adjoint_supported(const DevMesh &dm)
+{
+    return dm.flux == WLSENO_FLUX_ADVECTION && dm.nvars == 1 && dm.nmesh == 1 && reconstruct_supported(dm);
+}
+
+int launch_adjoint(const DevMesh &dm, const double *u, const double *v, double *cpad, double *cfn, void *stream)
+{
+    AArgs a;
+    a.nc = dm.nc;
+    a.u = u;
+    a.v = v;
+    a.geo = dm.geo;
+    a.vrel = dm.vrel;
+    a.normal = dm.normal;
+    a.rvol = dm.rvol;
+    a.spad = dm.spad;
+    a.sib = dm.sib;
+    a.cpad = cpad;
+    a.cfn = cfn;
+    a.eh2 = dm.eh2;
+    a.alpha_w = dm.alpha_w;
+    a.rank_tol = dm.rank_tol;
+    a.period = dm.period;
+    a.weight_mode = dm.weight_mode;
+    a.bc = dm.bc;
+    for (int d = 0; d < 3; ++d) a.vel[d] = dm.vel[d];
+    for (int b = 0; b <= kMaxBuckets; ++b) {
+        a.cell0[b] = dm.bucket_cell0[b < dm.nbuckets ? b : dm.nbuckets];
+        a.spad_off[b] = dm.spad_off[b];
+        if (b < kMaxBuckets) a.stride[b] = b < dm.nbuckets ? dm.bucket_cap[b] : 0;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (dm.dim == 1) {
+        switch (dm.p) {
+        case 2: return launch_adj<1, 2, 4, 2, 2, 2>(a, st);
+        case 3: return launch_adj<1, 3, 4, 2, 2, 2>(a, st);
+        case 4: return launch_adj<1, 4, 4, 2, 2, 2>(a, st);
+        case 5: return launch_adj<1, 5, 4, 2, 2, 2>(a, st);
+        }
+    } else if (dm.dim == 2) {
+        if (dm.p == 2) return launch_adj<2, 2, 4, 2, 2, 2>(a, st);
+        if (dm.p == 3) return launch_adj<2, 3, 4, 3, 4, 5>(a, st);
+        if (dm.p == 4) return launch_adj<2, 4, 8, 3, 4, 5>(a, st);
+    } else if (dm.dim == 3) {
+        if (dm.p == 2) return launch_adj<3, 2, 4, 4, 4, 4>(a, st);
+        if (dm.p == 3) return launch_adj<3, 3, 8, 4, 5, 7>(a, st);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_adjoint_gather(const DevMesh &dm, const int64_t *tptr, const int32_t *tidx, const double *contrib,
+                          const double *x, const double *y, const double *z, double *out, double A, double B,
+                          double C, double D, void *stream)
+{
+    hipLaunchKernelGGL(k_adjoint_gather, dim3(blocks_for(dm.nc, 256)), dim3(256), 0, (hipStream_t)stream, dm.nc,
+                       tptr, tidx, contrib, x, y, z, out, A, B, C, D);
+    return (int)hipGetLastError();
 }
 
 int launch_permute(const DevMesh &dm, const double *in, double *out, bool to_device_order, void *stream)

@@ -441,6 +441,8 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
         throw Error{WLSENO_EUNSUPPORTED, "the Euler system is compiled for 2-D meshes"};
     if (prm.flux == WLSENO_FLUX_EULER && !(prm.gamma > 1.0)) throw inval("gamma > 1 required");
     if (prm.weight_mode != 0 && prm.weight_mode != 1) throw inval("weight_mode must be 0 or 1");
+    if (prm.bc != 0 && prm.bc != 1) throw inval("bc must be 0 or 1");
+    if (prm.bc == 1 && prm.flux == WLSENO_FLUX_EULER) throw inval("bc = 1 (zero outside state) is not valid for Euler");
     if (prm.lanes != 0 && prm.lanes != 2 && prm.lanes != 4 && prm.lanes != 8 && prm.lanes != 16)
         throw inval("lanes must be 0, 2, 4, 8 or 16");
     if (!(prm.eps >= 0.0) || !(prm.alpha_w > 0.0) || !(prm.rank_tol >= 0.0))
@@ -700,6 +702,24 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     }
     b.min_insphere = min_ins;
     out = std::move(b);
+}
+
+void transpose_tables(const Build &b, int64_t nc, int nf, std::vector<int64_t> &tptr, std::vector<int32_t> &tidx)
+{
+    const int64_t npad = b.spad_off[kMaxBuckets];
+    if (npad + (int64_t)nf * nc > (int64_t)INT32_MAX) throw inval("mesh too large for the adjoint tables");
+    tptr.assign(nc + 1, 0);
+    for (int64_t t = 0; t < npad; ++t)
+        if (b.spad[t] >= 0) ++tptr[b.spad[t] + 1];
+    for (int64_t t = 0; t < (int64_t)nf * nc; ++t)
+        if (b.dsib[t] >= 0) ++tptr[(b.dsib[t] >> 2) + 1];
+    for (int64_t j = 0; j < nc; ++j) tptr[j + 1] += tptr[j];
+    tidx.assign(tptr[nc], 0);
+    std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int64_t t = 0; t < npad; ++t)
+        if (b.spad[t] >= 0) tidx[fill[b.spad[t]]++] = (int32_t)t;
+    for (int64_t t = 0; t < (int64_t)nf * nc; ++t)
+        if (b.dsib[t] >= 0) tidx[fill[b.dsib[t] >> 2]++] = (int32_t)(npad + t);
 }
 
 }  // namespace wlseno

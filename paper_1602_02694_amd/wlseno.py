@@ -83,13 +83,14 @@ class WLSENO:
         return mid.value
 
     def stencil_build(self, p=3, n_lo=12, n_hi=20, flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2,
-                      alpha_w=1.5, rank_tol=1e-12, weight_mode=0, gamma=1.4, lanes=0):
+                      alpha_w=1.5, rank_tol=1e-12, weight_mode=0, gamma=1.4, lanes=0, bc=0):
         prm = N.Params()
         self._lib.wlseno_params_default(C.byref(prm))
         prm.p, prm.n_lo, prm.n_hi = int(p), int(n_lo), int(n_hi)
         prm.flux = N.FLUX[flux] if isinstance(flux, str) else int(flux)
         prm.weight_mode = int(weight_mode)
         prm.lanes = int(lanes)
+        prm.bc = int(bc)
         prm.eps, prm.alpha_w, prm.rank_tol, prm.gamma = float(eps), float(alpha_w), float(rank_tol), float(gamma)
         for d in range(3):
             prm.velocity[d] = float(velocity[d]) if d < len(velocity) else 0.0
@@ -173,6 +174,32 @@ class WLSENO:
         self._sync_stream()
         self._check(self._lib.wlseno_batch_last_alpha(self._h, a.ctypes.data_as(C.POINTER(C.c_double))))
         return a
+
+    # ----------------------------------------------------------- adjoint
+    def rhs_vjp(self, u, v, out=None):
+        """J(u)^T v for the advection right-hand side L."""
+        import torch
+
+        u = self._field(u)
+        v = self._field(v)
+        if out is None:
+            out = torch.empty_like(u)
+        self._sync_stream()
+        self._check(self._lib.wlseno_rhs_vjp(self._h, _ptr(u), _ptr(v), _ptr(out)))
+        return out
+
+    def step_adjoint(self, u0, dt, n_steps, gT, ckpt_every=10, out=None):
+        """(d u(T)/d u0)^T gT for n_steps TVD RK3 steps of size dt from u0."""
+        import torch
+
+        u0 = self._field(u0)
+        gT = self._field(gT)
+        if out is None:
+            out = torch.empty_like(u0)
+        self._sync_stream()
+        self._check(self._lib.wlseno_step_adjoint(self._h, _ptr(u0), float(dt), int(n_steps), int(ckpt_every),
+                                                  _ptr(gT), _ptr(out)))
+        return out
 
     def last_alpha(self) -> float:
         a = C.c_double(0.0)

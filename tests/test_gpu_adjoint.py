@@ -1,0 +1,166 @@
+"""GPU checks of the hand-written adjoint (marked gpu).
+
+* exact transpose: with unit weights the scheme is linear, so <w, L v> equals
+  <J^T w, v> to rounding (the equal-weight limit of the method);
+* the transposed Jacobian of L against central differences of L on the GPU;
+* the gradient of 1/2 ||u(T) - u_target||^2 with respect to u0 against a
+  reference derived from the oracle alone: Richardson-extrapolated central
+  differences of the extended-precision oracle's trajectory;
+* independence of the checkpoint interval, and the torch.autograd binding.
+"""
+
+import numpy as np
+import pytest
+
+from workloads import fields, jittered_square
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _setup(n=12, seed=5101, weight_mode=0, p=3, bc=0):
+    from paper_1602_02694_amd import WLSENO
+
+    mesh = jittered_square(n, 0.3, seed)
+    w = WLSENO(device=0)
+    w.mesh_upload(2, mesh.verts, mesh.cells)
+    kw = dict(p=p, n_lo=12 if p == 3 else 20, n_hi=20 if p == 3 else 36, flux="advection", velocity=(1.0, 0.5, 0.0),
+              weight_mode=weight_mode, bc=bc)
+    w.stencil_build(**kw)
+    u0 = fields.cell_averages(mesh, fields.gaussian_sum(seed, 8, 2))
+    target = fields.cell_averages(mesh, fields.gaussian_sum(seed + 1, 8, 2))
+    return mesh, w, kw, u0, target
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("p,bc", [(3, 0), (4, 0), (3, 1)])
+def test_vjp_is_exact_transpose_with_unit_weights(p, bc):
+    torch = _torch()
+    mesh, w, kw, u0, _ = _setup(weight_mode=1, p=p, bc=bc)
+    _say(f"[case] transpose p={p} bc={bc} n_cell={mesh.n_cell}")
+    rng = np.random.default_rng(7)
+    v = torch.tensor(rng.standard_normal(mesh.n_cell), device="cuda")
+    x = torch.tensor(rng.standard_normal(mesh.n_cell), device="cuda")
+    Lv = w.rhs(v)                       # linear scheme: J = L
+    JTx = w.rhs_vjp(v, x)
+    a = float(torch.dot(x, Lv))
+    b = float(torch.dot(JTx, v))
+    scale = float(torch.linalg.norm(x) * torch.linalg.norm(Lv))
+    assert abs(a - b) <= 1e-12 * scale, (a, b)
+
+
+def test_vjp_against_central_differences():
+    torch = _torch()
+    mesh, w, kw, u0, _ = _setup()
+    _say(f"[case] vjp-fd n_cell={mesh.n_cell}")
+    rng = np.random.default_rng(8)
+    u = torch.tensor(u0, device="cuda")
+    for trial in range(4):
+        d = torch.tensor(rng.standard_normal(mesh.n_cell), device="cuda")
+        x = torch.tensor(rng.standard_normal(mesh.n_cell), device="cuda")
+        h = 1e-6 * float(u.abs().max()) / float(d.abs().max())
+        fd = (w.rhs(u + h * d) - w.rhs(u - h * d)) / (2 * h)
+        a = float(torch.dot(x, fd))
+        b = float(torch.dot(w.rhs_vjp(u, x), d))
+        assert abs(a - b) <= 1e-6 * abs(b), (trial, a, b)
+
+
+def _oracle_directional(o, u0, d, dt, n, target, h):
+    """d/de of 1/2 ||u_T(u0 + e d) - target||^2 at e = 0: central differences
+    at h and h/2 combined by Richardson extrapolation (error O(h^4))."""
+    uT = o.step(u0, dt, n).reshape(-1)
+    g = uT - target
+
+    def D(hh):
+        up = o.step(u0 + hh * d, dt, n).reshape(-1)
+        um = o.step(u0 - hh * d, dt, n).reshape(-1)
+        return (up - um) / (2 * hh)
+
+    Jd = (4.0 * D(h / 2) - D(h)) / 3.0
+    return float(np.dot(g, Jd))
+
+
+@pytest.mark.parametrize("n,h_rel,tol,bc", [(2, 1e-5, 1e-8, 0), (8, 2e-7, 1e-6, 0), (2, 1e-6, 1e-6, 1)])
+def test_step_adjoint_against_oracle_reference(n, h_rel, tol, bc):
+    """The map from u0 has kinks near u0 (a facet neighbour that switches as
+    the smallest indicator, a pivot tie); differences that straddle one
+    depart from the active-branch derivative.  Over more steps, and with a
+    zero outside state (near-equal indicators where the solution is nearly
+    zero), the extended-precision differences level off near 1e-7 however
+    small the step, while a single right-hand side matches at 1e-8; those
+    cases use the 1e-6 bar of the finite-difference check."""
+    torch = _torch()
+    import oracle
+
+    mesh, w, kw, u0, target = _setup(bc=bc)
+    ck = 3
+    dt = 0.5 * w.info()["min_insphere"] / np.hypot(1.0, 0.5)
+    _say(f"[case] adjoint-oracle n_cell={mesh.n_cell} steps={n} ckpt={ck}")
+    u = torch.tensor(u0, device="cuda")
+    uT = u.clone()
+    w.step(uT, dt, n)
+    gT = uT - torch.tensor(target, device="cuda")
+    g0 = w.step_adjoint(u, dt, n, gT, ckpt_every=ck).cpu().numpy()
+    kwo = {k: v for k, v in kw.items() if k != "weight_mode"}
+    ox = oracle.Oracle(2, mesh.verts, mesh.cells, extended=True, weight_mode=kw["weight_mode"], **kwo)
+    rng = np.random.default_rng(9)
+    for trial in range(4):
+        d = rng.standard_normal(mesh.n_cell)
+        # the trajectory is strongly nonlinear in u0 (the weights), so the
+        # step must be small; the extended-precision oracle keeps the
+        # differences accurate (double outputs: ~1e-16 / h_rel relative)
+        h = h_rel * np.max(np.abs(u0)) / np.max(np.abs(d))
+        ref = _oracle_directional(ox, u0, d, dt, n, target, h)
+        got = float(np.dot(g0, d))
+        assert abs(got - ref) <= tol * abs(ref), (trial, got, ref)
+
+
+def test_step_adjoint_checkpoints_and_autograd():
+    torch = _torch()
+    from paper_1602_02694_amd.autograd import trajectory
+
+    mesh, w, kw, u0, target = _setup(n=10, seed=5102)
+    n = 7
+    dt = 0.5 * w.info()["min_insphere"] / np.hypot(1.0, 0.5)
+    _say(f"[case] adjoint-ckpt n_cell={mesh.n_cell} steps={n}")
+    u = torch.tensor(u0, device="cuda")
+    tg = torch.tensor(target, device="cuda")
+    uT = u.clone()
+    w.step(uT, dt, n)
+    gT = uT - tg
+    grads = [w.step_adjoint(u, dt, n, gT, ckpt_every=k).clone() for k in (1, 2, 3, 7, 50)]
+    for gk in grads[1:]:
+        assert torch.equal(gk, grads[0])
+    x = u.clone().requires_grad_(True)
+    loss = 0.5 * ((trajectory(x, w, dt, n, 3) - tg) ** 2).sum()
+    loss.backward()
+    assert torch.equal(x.grad, grads[0])
+    # zero steps: the identity
+    assert torch.equal(w.step_adjoint(u, dt, 0, gT), gT)
+
+
+def test_adjoint_errors():
+    torch = _torch()
+    from paper_1602_02694_amd import WLSENO, WLSENOError
+
+    mesh, w, kw, u0, _ = _setup(n=8)
+    u = torch.tensor(u0, device="cuda")
+    with pytest.raises(WLSENOError) as e:
+        w.step_adjoint(u, 1e-3, 2, u, ckpt_every=0)
+    assert e.value.status == 1
+    wb = WLSENO(device=0)
+    wb.mesh_upload(2, mesh.verts, mesh.cells)
+    wb.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers")
+    with pytest.raises(WLSENOError) as e:
+        wb.rhs_vjp(u, u)
+    assert e.value.status == 5

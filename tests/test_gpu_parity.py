@@ -126,6 +126,14 @@ def test_square_small_advection_ragged(lanes):
                  velocity=(1.0, 0.5, 0), lanes=lanes)
 
 
+def test_square_zero_outside_state():
+    """Advection with a zero outside state at boundary facets (no inflow)."""
+    mesh = jittered_square(13, 0.3, 95)
+    u0 = fields.cell_averages(mesh, fields.gaussian_sum(95, 8, 2))
+    _compare_all(mesh, u0, 10, 0.002, "square13-adv-bc1", p=3, n_lo=12, n_hi=20, flux="advection",
+                 velocity=(1.0, 0.5, 0), bc=1)
+
+
 def test_square_unit_weights():
     mesh = jittered_square(11, 0.3, 92)
     u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)

@@ -368,6 +368,48 @@ def test_conservation_2d_burgers():
     assert abs(total + bnd) < 1e-12 * np.sum(np.abs(o.mesh.vol * L[0]))
 
 
+@pytest.mark.parametrize("bc,net", [(0, 0.0), (1, -1.5)])
+def test_boundary_states_net_flux_of_a_constant(bc, net):
+    """Unit square, a = (1, 0.5), u = c: interior facets cancel, so
+    sum_i |tau_i| L_i = -c sum over boundary facets of |f| (a.n) F-weight.
+    Transmissive outside states (bc 0) let every facet carry a.n c: the net
+    outflow of a constant through a closed square is 0.  A zero outside state
+    (bc 1) keeps the outflow (x = 1: a.n = 1; y = 1: a.n = 0.5) and removes
+    the inflow: -1.5 c."""
+    import oracle
+
+    mesh = jittered_square(9, 0.3, 47)
+    o = oracle.Oracle(2, mesh.verts, mesh.cells, p=3, n_lo=12, n_hi=20, flux="advection",
+                      velocity=(1.0, 0.5, 0.0), bc=bc)
+    c = 0.7
+    L, _ = o.rhs(np.full(o.nc, c))
+    assert abs(np.dot(o.mesh.vol, L[0]) - net * c) < 1e-12
+
+
+@pytest.mark.slow
+def test_zero_outside_state_keeps_inflow_boundary_stable():
+    """Gaussians advected through the unit square (100x100 lattice, CFL 0.5
+    on the smallest insphere): with the inside state at inflow facets the
+    semi-discrete operator grows without bound within 100 steps (the growth
+    does not depend on the time step); a zero outside state stays bounded."""
+    import oracle
+    from workloads import configs
+
+    wl = configs.square_advection_adjoint(100, 5001)
+    m = wl.mesh
+    v = m.verts[m.cells]
+    e = [v[:, 1] - v[:, 0], v[:, 2] - v[:, 1], v[:, 0] - v[:, 2]]
+    area = 0.5 * np.abs(e[0][:, 0] * (-e[2][:, 1]) - e[0][:, 1] * (-e[2][:, 0]))
+    dt = 0.5 * np.min(4 * area / sum(np.linalg.norm(x, axis=1) for x in e)) / np.hypot(1.0, 0.5)
+    top = np.max(np.abs(wl.u0))
+    grown = {}
+    for bc in (0, 1):
+        o = oracle.from_workload(wl, bc=bc)
+        grown[bc] = np.max(np.abs(o.step(wl.u0, dt, 100)[0])) / top
+    assert grown[0] > 10.0
+    assert grown[1] < 1.01
+
+
 def test_conservation_1d_periodic():
     import oracle
     from workloads import configs

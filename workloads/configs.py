@@ -46,9 +46,11 @@ def square_advection_adjoint(n_per_side: int = 317, seed: int = 5001) -> Workloa
     mesh = jittered_square(n_per_side, 0.3, seed)
     u0 = fields.cell_averages(mesh, fields.gaussian_sum(seed, 8, 2))
     target = fields.cell_averages(mesh, fields.gaussian_sum(seed + 1, 8, 2))
+    # zero outside state at boundary facets (no inflow): with the inside
+    # state there, inflow facets make the operator grow without bound
     return Workload(f"tri{mesh.n_cell}-advection-p3", mesh, u0,
                     dict(p=3, n_lo=12, n_hi=20, flux="advection", velocity=(1.0, 0.5, 0.0),
-                         steps=100, cfl=0.5, target=target, ckpt_every=10))
+                         steps=100, cfl=0.5, target=target, ckpt_every=10, bc=1))
 
 
 def cube_advection(n_per_side: int = 74, seed: int = 4001) -> Workload:
