@@ -318,6 +318,8 @@ def main():
                     help="target CPU time of the oracle sample (0 disables the CPU leg)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward measurement of the default workload")
+    ap.add_argument("--adjoint-fd", type=int, default=32,
+                    help="random directions of the adjoint's finite-difference check")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design is "
@@ -470,7 +472,7 @@ def main():
         out["parity"] = {"steps": S, "max_rel_err_vs_oracle": err, "tolerance": 1e-12, "pass": err <= 1e-12}
         log(f"[bench] oracle {nc * S / cpu_t:.4g} cell-updates/s; GPU vs oracle after {S} steps: {err:.3e}")
     if args.workload == "square" and not args.no_adjoint:
-        out["adjoint"] = run_adjoint(torch, WLSENO)
+        out["adjoint"] = run_adjoint(torch, WLSENO, directions=args.adjoint_fd)
     print(json.dumps(out), flush=True)
 
 

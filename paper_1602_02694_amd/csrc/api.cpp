@@ -44,7 +44,7 @@ struct wlseno_ctx {
     // adjoint: transposed stencil, contributions, cotangents, checkpoints
     bool adj_ready = false;
     int64_t *tptr = nullptr;
-    int32_t *tidx = nullptr;
+    int32_t *tpos = nullptr;
     double *contrib = nullptr, *ga = nullptr, *gb = nullptr, *gc = nullptr;
     double *ck = nullptr, *seg = nullptr;
     size_t ck_cap = 0, seg_cap = 0;   // doubles
@@ -85,7 +85,7 @@ void free_device(wlseno_ctx *c)
     c->ubuf = c->kbuf = c->tbuf = nullptr;
     c->adj_ready = false;
     c->tptr = nullptr;
-    c->tidx = nullptr;
+    c->tpos = nullptr;
     c->contrib = c->ga = c->gb = c->gc = c->ck = c->seg = nullptr;
     c->ck_cap = c->seg_cap = 0;
 }
@@ -488,12 +488,11 @@ void adjoint_setup(wlseno_ctx *c)
     if (!adjoint_supported(c->dm))
         throw Error{WLSENO_EUNSUPPORTED, "the adjoint covers scalar linear advection on a single mesh"};
     std::vector<int64_t> tptr;
-    std::vector<int32_t> tidx;
-    transpose_tables(c->build, c->dm.nc, c->dm.nf, tptr, tidx);
+    std::vector<int32_t> tpos;
+    transpose_tables(c->build, c->dm.nc, c->dm.nf, tptr, tpos);
     c->tptr = upload(c, tptr);
-    c->tidx = upload(c, tidx);
-    const size_t nct = (size_t)c->build.spad_off[kMaxBuckets] + (size_t)c->dm.nf * c->dm.nc;
-    c->contrib = (double *)dev_alloc(c, nct * sizeof(double));
+    c->tpos = upload(c, tpos);
+    c->contrib = (double *)dev_alloc(c, (size_t)tptr.back() * sizeof(double));
     c->ga = (double *)dev_alloc(c, c->dm.nc * sizeof(double));
     c->gb = (double *)dev_alloc(c, c->dm.nc * sizeof(double));
     c->gc = (double *)dev_alloc(c, c->dm.nc * sizeof(double));
@@ -504,9 +503,8 @@ void adjoint_setup(wlseno_ctx *c)
 void vjp(wlseno_ctx *c, const double *u, const double *v, const double *x, const double *y, const double *z,
          double *out, double A, double B, double C, double D)
 {
-    double *cfn = c->contrib + c->build.spad_off[kMaxBuckets];
-    check_launch(launch_adjoint(c->dm, u, v, c->contrib, cfn, c->stream), "adjoint");
-    check_launch(launch_adjoint_gather(c->dm, c->tptr, c->tidx, c->contrib, x, y, z, out, A, B, C, D, c->stream),
+    check_launch(launch_adjoint(c->dm, u, v, c->tpos, c->contrib, c->stream), "adjoint");
+    check_launch(launch_adjoint_gather(c->dm, c->tptr, c->contrib, x, y, z, out, A, B, C, D, c->stream),
                  "adjoint gather");
 }
 

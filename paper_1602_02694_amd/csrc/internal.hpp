@@ -125,18 +125,20 @@ constexpr int kAlphaSlotsBatch = 8;   // slots per mesh of a batch
 bool reconstruct_supported(const DevMesh &dm);
 int launch_permute(const DevMesh &dm, const double *in, double *out, bool to_device_order, void *stream);
 // Transposed Jacobian of the advection right-hand side: per-cell
-// contributions (padded stencil slots cpad, facet slots cfn [F][nc]), then
-// their sums over the transposed stencil, combined as
+// contributions written into each receiving cell's segment of contrib
+// (positions tpos), then each segment summed and combined as
 // out = A x + B y + C z + D (J^T v) (null vectors count as zero).
 bool adjoint_supported(const DevMesh &dm);
-int launch_adjoint(const DevMesh &dm, const double *u, const double *v, double *cpad, double *cfn, void *stream);
-int launch_adjoint_gather(const DevMesh &dm, const int64_t *tptr, const int32_t *tidx, const double *contrib,
-                          const double *x, const double *y, const double *z, double *out, double A, double B,
-                          double C, double D, void *stream);
-// Transposed stencil: for each device cell j, the contribution indices t
-// (padded slots first, then npad + lf nc + i for facet slots) that read j,
-// in increasing t.
-void transpose_tables(const Build &b, int64_t nc, int nf, std::vector<int64_t> &tptr, std::vector<int32_t> &tidx);
+int launch_adjoint(const DevMesh &dm, const double *u, const double *v, const int32_t *tpos, double *contrib,
+                   void *stream);
+int launch_adjoint_gather(const DevMesh &dm, const int64_t *tptr, const double *contrib, const double *x,
+                          const double *y, const double *z, double *out, double A, double B, double C, double D,
+                          void *stream);
+// Transposed stencil: segment tptr[j]..tptr[j+1] of cell j lists, in
+// increasing source index, the contribution slots that read j (padded stencil
+// slots first, then npad + lf nc + i for facet slots); tpos maps each slot to
+// its place (-1: padding or a boundary facet).
+void transpose_tables(const Build &b, int64_t nc, int nf, std::vector<int64_t> &tptr, std::vector<int32_t> &tpos);
 int launch_clear_alpha(const DevMesh &dm, void *stream);
 int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *coef_user,
                        double *fv_user, int32_t *rank_user, void *stream);

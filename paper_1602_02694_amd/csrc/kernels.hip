@@ -822,16 +822,17 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
 // Transposed Jacobian of the advection right-hand side, v -> J(u)^T v, in two
 // kernels: k_adjoint writes, per cell i, the contribution of (dL/du)^T v
 // through cell i's reconstruction to every cell its stencil reads (one value
-// per padded stencil slot, one per facet slot for the centre weight's
-// smallest-indicator neighbour); k_adjoint_gather sums them per cell over the
-// transposed stencil in a fixed order.
+// per stencil slot, one per facet slot for the centre weight's
+// smallest-indicator neighbour), each into the receiving cell's contiguous
+// segment; k_adjoint_gather sums every segment in a fixed order.
 
 struct AArgs {
-    int64_t nc;
+    int64_t nc, npad;
     const double *u, *v;               // state and cotangent of L(u), device order
     const double *geo, *vrel, *normal, *rvol;
     const int32_t *spad, *sib;
-    double *cpad, *cfn;                // contributions: padded stencil slots; facet slots [F][nc]
+    double *contrib;                   // contributions, in transposed-stencil order
+    const int32_t *tpos;               // position in contrib of each padded slot, then of each facet slot
     double eh2, alpha_w, rank_tol, period;
     int weight_mode, bc;
     double vel[3];
@@ -1072,14 +1073,22 @@ __device__ __forceinline__ void adjoint_cell(const AArgs &a, int64_t cell, int64
     to_c = group_sum<G>(to_c);
     to_nb = group_sum<G>(to_nb);
     if (live) {
+        // each slot that reads a cell has a place in that cell's contiguous
+        // segment of contrib (tpos < 0: padding, or a boundary facet)
 #pragma unroll
         for (int s = 0; s < RPL; ++s) {
             const int r = s * G + g;
-            if (r < stride) a.cpad[pad_off + (c - cell_begin) * stride + r] = slotv[s] + (r == 0 ? to_c : 0.0);
+            if (r < stride) {
+                const int32_t t = a.tpos[pad_off + (c - cell_begin) * stride + r];
+                if (t >= 0) a.contrib[t] = slotv[s] + (r == 0 ? to_c : 0.0);
+            }
         }
         if (g == 0) {
 #pragma unroll
-            for (int lf = 0; lf < F; ++lf) a.cfn[lf * N + c] = lf == lfmin ? to_nb : 0.0;
+            for (int lf = 0; lf < F; ++lf) {
+                const int32_t t = a.tpos[a.npad + lf * N + c];
+                if (t >= 0) a.contrib[t] = lf == lfmin ? to_nb : 0.0;
+            }
         }
     }
 }
@@ -1104,17 +1113,16 @@ __global__ void __launch_bounds__(256) k_adjoint(AArgs a)
     }
 }
 
-// out = A x + B y + C z + D sum_{t in T(j)} contrib[t], per cell j (device order);
-// null vectors count as zero.
-__global__ void __launch_bounds__(256) k_adjoint_gather(int64_t nc, const int64_t *tptr, const int32_t *tidx,
-                                                        const double *contrib, const double *x, const double *y,
-                                                        const double *z, double *out, double A, double B,
-                                                        double C, double D)
+// out = A x + B y + C z + D sum of cell j's segment of contrib, per cell j
+// (device order, segments in increasing source order); null vectors count as zero.
+__global__ void __launch_bounds__(256) k_adjoint_gather(int64_t nc, const int64_t *tptr, const double *contrib,
+                                                        const double *x, const double *y, const double *z,
+                                                        double *out, double A, double B, double C, double D)
 {
     const int64_t j = (int64_t)xcd_block((int)blockIdx.x, (int)gridDim.x) * 256 + threadIdx.x;
     if (j >= nc) return;
     double s = 0.0;
-    for (int64_t t = tptr[j]; t < tptr[j + 1]; ++t) s += contrib[tidx[t]];
+    for (int64_t t = tptr[j]; t < tptr[j + 1]; ++t) s += contrib[t];
     double o = D * s;
     if (x) o += A * x[j];
     if (y) o += B * y[j];
@@ -1509,10 +1517,12 @@ bool adjoint_supported(const DevMesh &dm)
     return dm.flux == WLSENO_FLUX_ADVECTION && dm.nvars == 1 && dm.nmesh == 1 && reconstruct_supported(dm);
 }
 
-int launch_adjoint(const DevMesh &dm, const double *u, const double *v, double *cpad, double *cfn, void *stream)
+int launch_adjoint(const DevMesh &dm, const double *u, const double *v, const int32_t *tpos, double *contrib,
+                   void *stream)
 {
     AArgs a;
     a.nc = dm.nc;
+    a.npad = dm.spad_off[kMaxBuckets];
     a.u = u;
     a.v = v;
     a.geo = dm.geo;
@@ -1521,8 +1531,8 @@ int launch_adjoint(const DevMesh &dm, const double *u, const double *v, double *
     a.rvol = dm.rvol;
     a.spad = dm.spad;
     a.sib = dm.sib;
-    a.cpad = cpad;
-    a.cfn = cfn;
+    a.tpos = tpos;
+    a.contrib = contrib;
     a.eh2 = dm.eh2;
     a.alpha_w = dm.alpha_w;
     a.rank_tol = dm.rank_tol;
@@ -1554,12 +1564,12 @@ int launch_adjoint(const DevMesh &dm, const double *u, const double *v, double *
     return (int)hipErrorInvalidValue;
 }
 
-int launch_adjoint_gather(const DevMesh &dm, const int64_t *tptr, const int32_t *tidx, const double *contrib,
-                          const double *x, const double *y, const double *z, double *out, double A, double B,
-                          double C, double D, void *stream)
+int launch_adjoint_gather(const DevMesh &dm, const int64_t *tptr, const double *contrib, const double *x,
+                          const double *y, const double *z, double *out, double A, double B, double C, double D,
+                          void *stream)
 {
     hipLaunchKernelGGL(k_adjoint_gather, dim3(blocks_for(dm.nc, 256)), dim3(256), 0, (hipStream_t)stream, dm.nc,
-                       tptr, tidx, contrib, x, y, z, out, A, B, C, D);
+                       tptr, contrib, x, y, z, out, A, B, C, D);
     return (int)hipGetLastError();
 }
 

@@ -704,22 +704,23 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     out = std::move(b);
 }
 
-void transpose_tables(const Build &b, int64_t nc, int nf, std::vector<int64_t> &tptr, std::vector<int32_t> &tidx)
+void transpose_tables(const Build &b, int64_t nc, int nf, std::vector<int64_t> &tptr, std::vector<int32_t> &tpos)
 {
     const int64_t npad = b.spad_off[kMaxBuckets];
-    if (npad + (int64_t)nf * nc > (int64_t)INT32_MAX) throw inval("mesh too large for the adjoint tables");
+    const int64_t nslot = npad + (int64_t)nf * nc;
+    if (nslot > (int64_t)INT32_MAX) throw inval("mesh too large for the adjoint tables");
     tptr.assign(nc + 1, 0);
     for (int64_t t = 0; t < npad; ++t)
         if (b.spad[t] >= 0) ++tptr[b.spad[t] + 1];
     for (int64_t t = 0; t < (int64_t)nf * nc; ++t)
         if (b.dsib[t] >= 0) ++tptr[(b.dsib[t] >> 2) + 1];
     for (int64_t j = 0; j < nc; ++j) tptr[j + 1] += tptr[j];
-    tidx.assign(tptr[nc], 0);
+    tpos.assign(nslot, -1);
     std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
     for (int64_t t = 0; t < npad; ++t)
-        if (b.spad[t] >= 0) tidx[fill[b.spad[t]]++] = (int32_t)t;
+        if (b.spad[t] >= 0) tpos[t] = (int32_t)fill[b.spad[t]]++;
     for (int64_t t = 0; t < (int64_t)nf * nc; ++t)
-        if (b.dsib[t] >= 0) tidx[fill[b.dsib[t] >> 2]++] = (int32_t)(npad + t);
+        if (b.dsib[t] >= 0) tpos[npad + t] = (int32_t)fill[b.dsib[t] >> 2]++;
 }
 
 }  // namespace wlseno
