@@ -1208,21 +1208,25 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
     constexpr int F = DIM + 1;
     constexpr int V = FLUX == kFluxEuler ? DIM + 2 : 1;
     const unsigned N = (unsigned)a.nc;
-    const unsigned c = (unsigned)xcd_block((int)blockIdx.x, (int)gridDim.x) * (unsigned)BS + threadIdx.x;
-    double alpha = 0.0;
+    const unsigned c0 = (unsigned)xcd_block((int)blockIdx.x, (int)gridDim.x) * (unsigned)BS + threadIdx.x;
+    const bool live = c0 < N;
+    const unsigned c = live ? c0 : N - 1;   // lanes past the end work on the last cell, store nothing
     if constexpr (FLUX != kFluxAdv) {
         if (blockIdx.x == 0)
             for (int t = (int)threadIdx.x; t < a.nslot; t += BS) a.alpha_clr[t * 16] = 0ull;
-        if (!a.mid) {
-            // one mesh: its 64 slots, one per lane, reduced over the wave
-            const int lane = (int)(threadIdx.x & 63);
-            double v = __longlong_as_double((long long)a.alpha_rd[lane * 16]);
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-            alpha = v;
-        }
     }
-    if (c >= N) return;
+    // every load is issued up front (indices clamped into this cell's own
+    // records for boundary facets), then the fluxes are formed
+    int32_t sb[F];
+    double m[F][DIM];
+#pragma unroll
+    for (int lf = 0; lf < F; ++lf) {
+        sb[lf] = a.sib[lf * N + c];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) m[lf][d] = a.snormal[(lf * N + c) * DIM + d];
+    }
+    const double rv = a.rvol[c];
+    double alpha = 0.0;
     double cdt = a.Cdt;
     if (a.mid) {
         const int32_t mesh = a.mid[c];
@@ -1231,6 +1235,31 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
             for (int t = 0; t < a.spm; ++t)
                 alpha = fmax(alpha, __longlong_as_double((long long)a.alpha_rd[((int64_t)mesh * a.spm + t) * 16]));
         }
+    } else if constexpr (FLUX != kFluxAdv) {
+        // one mesh: its 64 slots, one per lane, reduced over the wave
+        const double v = __longlong_as_double((long long)a.alpha_rd[(threadIdx.x & 63) * 16]);
+        const double w = wave_max(v);
+        alpha = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(w)),
+                                 __builtin_amdgcn_readfirstlane(__double2loint(w)));
+    }
+    double own[V][F][Q], oth[V][F][Q];
+    bool owner[F];
+    int32_t qp[F];
+#pragma unroll
+    for (int lf = 0; lf < F; ++lf) {
+        const bool inner = sb[lf] >= 0;
+        const unsigned j = inner ? (unsigned)sb[lf] >> 2 : c;
+        const unsigned l2 = inner ? (unsigned)sb[lf] & 3u : (unsigned)lf;
+        owner[lf] = c < j;
+        qp[lf] = 0;
+        if constexpr (DIM == 3) qp[lf] = inner ? (owner[lf] ? a.qperm[lf * N + c] : a.qperm[l2 * N + j]) : 0;
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                own[v][lf][q] = a.fv[((v * F + lf) * N + c) * Q + q];
+                oth[v][lf][q] = a.fv[((v * F + l2) * N + j) * Q + q];
+            }
     }
     double vel[3] = {a.vel[0], a.vel[1], a.vel[2]};
     double tot[V];
@@ -1238,64 +1267,61 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
     for (int v = 0; v < V; ++v) tot[v] = 0.0;
 #pragma unroll
     for (int lf = 0; lf < F; ++lf) {
-        const unsigned fc = lf * N + c;
-        const int32_t s = a.sib[fc];
-        double m[DIM];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) m[d] = a.snormal[fc * DIM + d];
         double facc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) facc[v] = 0.0;
-        if (s < 0) {
+        if (sb[lf] < 0) {
             // boundary: outside state = inside state (transmissive) or zero
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 double uo[V], ux[V], fl[V];
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    uo[v] = a.fv[((v * F + lf) * N + c) * Q + q];
+                    uo[v] = own[v][lf][q];
                     ux[v] = a.bc ? 0.0 : uo[v];
                 }
-                lf_flux<DIM, FLUX, V>(uo, ux, m, alpha, vel, a.gamma, fl);
+                lf_flux<DIM, FLUX, V>(uo, ux, m[lf], alpha, vel, a.gamma, fl);
 #pragma unroll
                 for (int v = 0; v < V; ++v) facc[v] += quad_weight<DIM, Q>(q) * fl[v];
             }
         } else {
             // both cells evaluate the facet from identical operands in the
             // orientation of the lower-numbered cell; the other one negates
-            const unsigned j = (unsigned)s >> 2;
-            const unsigned l2 = (unsigned)s & 3u;
-            const bool owner = c < j;
-            int32_t qp = 0;
-            if constexpr (DIM == 3) qp = owner ? a.qperm[fc] : a.qperm[l2 * N + j];
+            const bool ow = owner[lf];
             double mm[DIM];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) mm[d] = owner ? m[d] : -m[d];
+            for (int d = 0; d < DIM; ++d) mm[d] = ow ? m[lf][d] : -m[lf][d];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 // the sibling's point matching point q: reversed along an edge in 2-D
-                const int qo = DIM == 3 ? ((qp >> (2 * q)) & 3) : (Q - 1 - q);
+                const int qo = DIM == 3 ? ((qp[lf] >> (2 * q)) & 3) : (Q - 1 - q);
                 double ua[V], ub[V], fl[V];
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    const double own_q = a.fv[((v * F + lf) * N + c) * Q + q];
-                    const double own_qo = a.fv[((v * F + lf) * N + c) * Q + qo];
-                    const double oth_q = a.fv[((v * F + l2) * N + j) * Q + q];
-                    const double oth_qo = a.fv[((v * F + l2) * N + j) * Q + qo];
-                    ua[v] = owner ? own_q : oth_q;
-                    ub[v] = owner ? oth_qo : own_qo;
+                    // 3-D: qo is data, so select among the three points
+                    double own_qo = own[v][lf][0], oth_q = oth[v][lf][0];
+#pragma unroll
+                    for (int t = 1; t < Q; ++t) {
+                        own_qo = qo == t ? own[v][lf][t] : own_qo;
+                    }
+                    oth_q = oth[v][lf][q];
+                    double oth_qo = oth[v][lf][0];
+#pragma unroll
+                    for (int t = 1; t < Q; ++t) oth_qo = qo == t ? oth[v][lf][t] : oth_qo;
+                    ua[v] = ow ? own[v][lf][q] : oth_q;
+                    ub[v] = ow ? oth_qo : own_qo;
                 }
                 lf_flux<DIM, FLUX, V>(ua, ub, mm, alpha, vel, a.gamma, fl);
 #pragma unroll
                 for (int v = 0; v < V; ++v) facc[v] += quad_weight<DIM, Q>(q) * fl[v];
             }
 #pragma unroll
-            for (int v = 0; v < V; ++v) facc[v] = owner ? facc[v] : -facc[v];
+            for (int v = 0; v < V; ++v) facc[v] = ow ? facc[v] : -facc[v];
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) tot[v] += facc[v];
     }
-    const double rv = a.rvol[c];
+    if (!live) return;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const unsigned vc = v * N + c;
