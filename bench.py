@@ -288,9 +288,21 @@ def run_adjoint(torch, WLSENO, steps=100, ckpt=10, directions=32):
             for _ in range(reps):
                 g0 = w.step_adjoint(u0, dt, steps, gT, ckpt)
             torch.cuda.synchronize()
-            t_adj = (time.perf_counter() - ts) / reps
-            log(f"[bench] forward {t_fwd * 1e3:.2f} ms, adjoint {t_adj * 1e3:.2f} ms for {steps} steps")
-            out.update({"forward_ms": t_fwd * 1e3, "adjoint_ms": t_adj * 1e3, "adjoint_over_forward": t_adj / t_fwd})
+            t_full = (time.perf_counter() - ts) / reps
+            # forward with checkpoints, then the reverse sweep alone
+            ur = u0.clone()
+            w.step_record(ur, dt, steps, ckpt)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for _ in range(reps):
+                g0r = w.step_adjoint_recorded(gT)
+            torch.cuda.synchronize()
+            t_rev = (time.perf_counter() - ts) / reps
+            assert torch.equal(g0r, g0)
+            log(f"[bench] forward {t_fwd * 1e3:.2f} ms; adjoint {t_full * 1e3:.2f} ms from u0, "
+                f"{t_rev * 1e3:.2f} ms over a recorded forward ({steps} steps)")
+            out.update({"forward_ms": t_fwd * 1e3, "adjoint_ms": t_rev * 1e3, "adjoint_over_forward": t_rev / t_fwd,
+                        "adjoint_from_u0_ms": t_full * 1e3, "adjoint_from_u0_over_forward": t_full / t_fwd})
 
         rng = np.random.default_rng(5003)
         worst = 0.0

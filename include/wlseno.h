@@ -235,6 +235,16 @@ wlseno_status wlseno_rhs_vjp(wlseno_t ctx, const double *u_dev, const double *v_
 wlseno_status wlseno_step_adjoint(wlseno_t ctx, const double *u0_dev, double dt, int n_steps, int ckpt_every,
                                   const double *gT_dev, double *g0_dev);
 
+/* The same gradient in two calls, for callers that run the forward anyway
+ * (training loops, torch.autograd): wlseno_step_record advances u_dev in
+ * place by n_steps RK3 steps (as wlseno_step) and keeps the state every
+ * ckpt_every steps; wlseno_step_adjoint_recorded then writes
+ * g0_dev = (d u(T) / d u0)^T gT_dev for that trajectory without running the
+ * forward again.  A rebuild, another record or wlseno_step_adjoint drops the
+ * record (ESTATE until the next record).  Arguments as wlseno_step_adjoint. */
+wlseno_status wlseno_step_record(wlseno_t ctx, double *u_dev, double dt, int n_steps, int ckpt_every);
+wlseno_status wlseno_step_adjoint_recorded(wlseno_t ctx, const double *gT_dev, double *g0_dev);
+
 /* Kernel timing for measurement.  Reconstructs u_dev (user order, n_cell
  * doubles on the device, not modified) once, then records a HIP event on the
  * context's stream, launches one kernel of a right-hand-side stage `launches`

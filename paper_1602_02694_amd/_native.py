@@ -18,7 +18,7 @@ EXPORTS = [
     "wlseno_mesh_upload", "wlseno_stencil_build", "wlseno_get_info", "wlseno_get_stencil",
     "wlseno_reconstruct", "wlseno_rhs", "wlseno_step", "wlseno_last_alpha", "wlseno_time_kernel",
     "wlseno_batch_add_mesh", "wlseno_batch_step", "wlseno_batch_last_alpha", "wlseno_set_graphs",
-    "wlseno_rhs_vjp", "wlseno_step_adjoint",
+    "wlseno_rhs_vjp", "wlseno_step_adjoint", "wlseno_step_record", "wlseno_step_adjoint_recorded",
 ]
 
 
@@ -82,6 +82,8 @@ def load():
     lib.wlseno_set_graphs.argtypes = [vp, C.c_int]
     lib.wlseno_rhs_vjp.argtypes = [vp, vp, vp, vp]
     lib.wlseno_step_adjoint.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, vp, vp]
+    lib.wlseno_step_record.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int]
+    lib.wlseno_step_adjoint_recorded.argtypes = [vp, vp, vp]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name not in ("wlseno_params_default", "wlseno_last_error"):

@@ -48,6 +48,9 @@ struct wlseno_ctx {
     double *contrib = nullptr, *ga = nullptr, *gb = nullptr, *gc = nullptr;
     double *ck = nullptr, *seg = nullptr;
     size_t ck_cap = 0, seg_cap = 0;   // doubles
+    bool rec_valid = false;           // ck holds the checkpoints of a recorded trajectory
+    double rec_dt = 0.0;
+    int rec_n = 0, rec_ckpt = 1;
 };
 
 namespace {
@@ -88,6 +91,7 @@ void free_device(wlseno_ctx *c)
     c->tpos = nullptr;
     c->contrib = c->ga = c->gb = c->gc = c->ck = c->seg = nullptr;
     c->ck_cap = c->seg_cap = 0;
+    c->rec_valid = false;
 }
 
 void *dev_alloc(wlseno_ctx *c, size_t bytes)
@@ -524,35 +528,40 @@ wlseno_status wlseno_rhs_vjp(wlseno_t ctx, const double *u_dev, const double *v_
     API_END(ctx)
 }
 
-wlseno_status wlseno_step_adjoint(wlseno_t ctx, const double *u0_dev, double dt, int n_steps, int ckpt_every,
-                                  const double *gT_dev, double *g0_dev)
+namespace {
+
+// Forward sweep from the device-order state in ubuf: store the state at the
+// start of every segment of ckpt_every steps, and advance to step n_steps
+// (advance_last) or only to the start of the last segment.
+void forward_checkpoints(wlseno_ctx *ctx, double dt, int n_steps, int ckpt_every, bool advance_last)
 {
-    API_BEGIN(ctx)
-    if (!u0_dev || !gT_dev || !g0_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
-    if (!std::isfinite(dt) || n_steps < 0 || ckpt_every < 1)
-        throw Error{WLSENO_EINVAL, "dt finite, n_steps >= 0 and ckpt_every >= 1 required"};
-    need_device(ctx);
-    adjoint_setup(ctx);
     const int64_t nc = ctx->dm.nc;
     const int nseg = n_steps == 0 ? 0 : (n_steps + ckpt_every - 1) / ckpt_every;
     const int E = n_steps < ckpt_every ? n_steps : ckpt_every;
     dev_grow(ctx, &ctx->ck, &ctx->ck_cap, (size_t)(nseg > 0 ? nseg : 1) * nc);
     dev_grow(ctx, &ctx->seg, &ctx->seg_cap, (size_t)(E > 0 ? E : 1) * 3 * nc);
-    double *u = ctx->ubuf;
+    ctx->rec_valid = false;
     const size_t bytes = (size_t)nc * sizeof(double);
-    // forward sweep: the state at the start of every segment
-    check_launch(launch_permute(ctx->dm, u0_dev, u, true, ctx->stream), "permute");
     for (int sg = 0; sg < nseg; ++sg) {
-        check_hip(hipMemcpyAsync(ctx->ck + (size_t)sg * nc, u, bytes, hipMemcpyDeviceToDevice, ctx->stream),
+        check_hip(hipMemcpyAsync(ctx->ck + (size_t)sg * nc, ctx->ubuf, bytes, hipMemcpyDeviceToDevice, ctx->stream),
                   "hipMemcpyAsync");
         const int s_end = (sg + 1) * ckpt_every < n_steps ? (sg + 1) * ckpt_every : n_steps;
-        if (sg + 1 < nseg)
+        if (sg + 1 < nseg || advance_last)
             for (int s = sg * ckpt_every; s < s_end; ++s) rk3_step(ctx, dt, 0, ctx->stream);
     }
-    // reverse sweep, segment by segment: recompute its stage states, then
-    // transpose each RK3 step (g = cotangent of the step's output):
-    //   g2 = 2/3 g + 2/3 dt J(U2)^T g;  g1 = 1/4 g2 + 1/4 dt J(U1)^T g2;
-    //   g  = 1/3 g + 3/4 g2 + g1 + dt J(U)^T g1
+}
+
+// Reverse sweep over the stored checkpoints, segment by segment: recompute
+// the segment's stage states, then transpose each RK3 step (g = cotangent of
+// the step's output):
+//   g2 = 2/3 g + 2/3 dt J(U2)^T g;  g1 = 1/4 g2 + 1/4 dt J(U1)^T g2;
+//   g  = 1/3 g + 3/4 g2 + g1 + dt J(U)^T g1
+void reverse_sweep(wlseno_ctx *ctx, double dt, int n_steps, int ckpt_every, const double *gT_dev, double *g0_dev)
+{
+    const int64_t nc = ctx->dm.nc;
+    const int nseg = n_steps == 0 ? 0 : (n_steps + ckpt_every - 1) / ckpt_every;
+    const size_t bytes = (size_t)nc * sizeof(double);
+    double *u = ctx->ubuf;
     double *g = ctx->ga, *g2 = ctx->gb, *g1 = ctx->gc;
     check_launch(launch_permute(ctx->dm, gT_dev, g, true, ctx->stream), "permute");
     for (int sg = nseg - 1; sg >= 0; --sg) {
@@ -575,6 +584,55 @@ wlseno_status wlseno_step_adjoint(wlseno_t ctx, const double *u0_dev, double dt,
         }
     }
     check_launch(launch_permute(ctx->dm, g, g0_dev, false, ctx->stream), "permute");
+}
+
+void check_adjoint_args(double dt, int n_steps, int ckpt_every)
+{
+    if (!std::isfinite(dt) || n_steps < 0 || ckpt_every < 1)
+        throw Error{WLSENO_EINVAL, "dt finite, n_steps >= 0 and ckpt_every >= 1 required"};
+}
+
+}  // namespace
+
+wlseno_status wlseno_step_adjoint(wlseno_t ctx, const double *u0_dev, double dt, int n_steps, int ckpt_every,
+                                  const double *gT_dev, double *g0_dev)
+{
+    API_BEGIN(ctx)
+    if (!u0_dev || !gT_dev || !g0_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
+    check_adjoint_args(dt, n_steps, ckpt_every);
+    need_device(ctx);
+    adjoint_setup(ctx);
+    check_launch(launch_permute(ctx->dm, u0_dev, ctx->ubuf, true, ctx->stream), "permute");
+    // the last segment's states are recomputed by the reverse sweep anyway
+    forward_checkpoints(ctx, dt, n_steps, ckpt_every, false);
+    reverse_sweep(ctx, dt, n_steps, ckpt_every, gT_dev, g0_dev);
+    API_END(ctx)
+}
+
+wlseno_status wlseno_step_record(wlseno_t ctx, double *u_dev, double dt, int n_steps, int ckpt_every)
+{
+    API_BEGIN(ctx)
+    if (!u_dev) throw Error{WLSENO_EINVAL, "u_dev is NULL"};
+    check_adjoint_args(dt, n_steps, ckpt_every);
+    need_device(ctx);
+    adjoint_setup(ctx);
+    check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
+    forward_checkpoints(ctx, dt, n_steps, ckpt_every, true);
+    check_launch(launch_permute(ctx->dm, ctx->ubuf, u_dev, false, ctx->stream), "permute");
+    ctx->rec_valid = true;
+    ctx->rec_dt = dt;
+    ctx->rec_n = n_steps;
+    ctx->rec_ckpt = ckpt_every;
+    API_END(ctx)
+}
+
+wlseno_status wlseno_step_adjoint_recorded(wlseno_t ctx, const double *gT_dev, double *g0_dev)
+{
+    API_BEGIN(ctx)
+    if (!gT_dev || !g0_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
+    need_device(ctx);
+    if (!ctx->rec_valid) throw Error{WLSENO_ESTATE, "no recorded trajectory (wlseno_step_record first)"};
+    reverse_sweep(ctx, ctx->rec_dt, ctx->rec_n, ctx->rec_ckpt, gT_dev, g0_dev);
     API_END(ctx)
 }
 

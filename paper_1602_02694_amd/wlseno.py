@@ -96,6 +96,7 @@ class WLSENO:
             prm.velocity[d] = float(velocity[d]) if d < len(velocity) else 0.0
         self._check(self._lib.wlseno_stencil_build(self._h, C.byref(prm)))
         self.flux = flux
+        self._record_tag = None
 
     def info(self) -> dict:
         inf = N.Info()
@@ -199,6 +200,25 @@ class WLSENO:
         self._sync_stream()
         self._check(self._lib.wlseno_step_adjoint(self._h, _ptr(u0), float(dt), int(n_steps), int(ckpt_every),
                                                   _ptr(gT), _ptr(out)))
+        self._record_tag = None      # the library dropped any recorded trajectory
+        return out
+
+    def step_record(self, u, dt, n_steps, ckpt_every=10):
+        """step() that keeps checkpoints for step_adjoint_recorded()."""
+        u = self._field(u)
+        self._sync_stream()
+        self._check(self._lib.wlseno_step_record(self._h, _ptr(u), float(dt), int(n_steps), int(ckpt_every)))
+        return u
+
+    def step_adjoint_recorded(self, gT, out=None):
+        """(d u(T)/d u0)^T gT for the trajectory of the last step_record()."""
+        import torch
+
+        gT = self._field(gT)
+        if out is None:
+            out = torch.empty_like(gT)
+        self._sync_stream()
+        self._check(self._lib.wlseno_step_adjoint_recorded(self._h, _ptr(gT), _ptr(out)))
         return out
 
     def last_alpha(self) -> float:

@@ -141,8 +141,19 @@ def test_step_adjoint_checkpoints_and_autograd():
     grads = [w.step_adjoint(u, dt, n, gT, ckpt_every=k).clone() for k in (1, 2, 3, 7, 50)]
     for gk in grads[1:]:
         assert torch.equal(gk, grads[0])
+    # record the forward, then the reverse sweep alone: the same gradient
+    ur = u.clone()
+    w.step_record(ur, dt, n, 3)
+    assert torch.equal(ur, uT)
+    assert torch.equal(w.step_adjoint_recorded(gT), grads[0])
     x = u.clone().requires_grad_(True)
     loss = 0.5 * ((trajectory(x, w, dt, n, 3) - tg) ** 2).sum()
+    loss.backward()
+    assert torch.equal(x.grad, grads[0])
+    # a full adjoint in between drops the record; autograd then recomputes
+    x = u.clone().requires_grad_(True)
+    loss = 0.5 * ((trajectory(x, w, dt, n, 2) - tg) ** 2).sum()
+    w.step_adjoint(u, dt, n, gT, ckpt_every=5)
     loss.backward()
     assert torch.equal(x.grad, grads[0])
     # zero steps: the identity
@@ -158,6 +169,9 @@ def test_adjoint_errors():
     with pytest.raises(WLSENOError) as e:
         w.step_adjoint(u, 1e-3, 2, u, ckpt_every=0)
     assert e.value.status == 1
+    with pytest.raises(WLSENOError) as e:
+        w.step_adjoint_recorded(u)          # nothing recorded
+    assert e.value.status == 4
     wb = WLSENO(device=0)
     wb.mesh_upload(2, mesh.verts, mesh.cells)
     wb.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers")
