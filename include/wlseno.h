@@ -74,15 +74,16 @@ enum {
  * rank_tol = 1e-12 relative to |R_11| (Sec. 3.3.2 leaves it open), unit
  * weights off, automatic lane count. */
 typedef struct {
-    int32_t p;           /* order: reconstruct polynomials of degree p-1 (1-D: 2..5, 2-D: 2..4, 3-D: 2..3) */
+    int32_t p;           /* order: reconstruct polynomials of degree p-1 (1-D: 2..5, 2-D: 2..5, 3-D: 2..3) */
     int32_t n_lo, n_hi;  /* stencil size rule: grow rings until >= n_lo cells, keep the n_hi nearest */
     int32_t flux;        /* WLSENO_FLUX_* */
     int32_t weight_mode; /* 0: WLS-ENO weights (eq. weight); 1: unit weights (plain least squares) */
     int32_t lanes;       /* lanes per cell in the reconstruction kernel: 0 = automatic (2 for
-                            2-D p = 3, 8 in 3-D, 4 otherwise); 2, 4, 8 and 16 are compiled for
-                            2-D p = 3, 4, 8 and 16 for 2-D p = 4, 8 and 16 for 3-D p = 3.
-                            Other values are EINVAL; a value not compiled for (dim, p) uses
-                            the automatic choice.  Results agree to rounding either way. */
+                            2-D p = 3, 16 for 2-D p = 5, 8 in 3-D, 4 otherwise); 2, 4, 8 and 16
+                            are compiled for 2-D p = 3, 4, 8 and 16 for 2-D p = 4, 8 and 16
+                            for 2-D p = 5 and 3-D p = 3.  Other values are EINVAL; a value not
+                            compiled for (dim, p) uses the automatic choice.  Results agree to
+                            rounding either way. */
     double eps;          /* epsilon in beta_j = (u_j - u_i)^2 + eps h^2 */
     double alpha_w;      /* centre weight factor alpha > 1 in eq. (weight) */
     double rank_tol;     /* numerical rank: |R_kk| > rank_tol |R_11| */

@@ -189,10 +189,14 @@ __device__ __forceinline__ void edge_point(const double (&a)[DIM], const double 
         double t;
         if constexpr (Q == 1) {
             t = 0.5;
-        } else {
+        } else if constexpr (Q == 2) {
             // Gauss-Legendre nodes on [0,1], ascending
             const double h = 0.5 / 1.7320508075688772;   // 1/(2 sqrt 3)
             t = q == 0 ? 0.5 - h : 0.5 + h;
+        } else {
+            static_assert(Q == 3, "up to three points per edge");
+            const double h = 0.38729833462074170;        // sqrt(3/5) / 2
+            t = q == 0 ? 0.5 - h : (q == 1 ? 0.5 : 0.5 + h);
         }
 #pragma unroll
         for (int d = 0; d < DIM; ++d) x[d] = a[d] + t * (b[d] - a[d]);
@@ -221,7 +225,7 @@ template <int DIM, int Q>
 __device__ __forceinline__ double quad_weight(int q)
 {
     if constexpr (DIM == 1) return 1.0;
-    else if constexpr (DIM == 2) return Q == 1 ? 1.0 : 0.5;
+    else if constexpr (DIM == 2) return Q == 1 ? 1.0 : (Q == 2 ? 0.5 : (q == 1 ? 8.0 / 18.0 : 5.0 / 18.0));
     else return 1.0 / 3.0;
 }
 
@@ -1417,6 +1421,7 @@ std::vector<int> stencil_capacities(int dim, int p)
     if (dim == 2 && p == 2) return {8};
     if (dim == 2 && p == 3) return {12, 16, 20};
     if (dim == 2 && p == 4) return {20, 28, 36};
+    if (dim == 2 && p == 5) return {24, 32, 40};
     if (dim == 3 && p == 2) return {16};
     if (dim == 3 && p == 3) return {32, 40, 56};
     return {};
@@ -1467,9 +1472,11 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     hipStream_t st = (hipStream_t)stream;
     // rows per lane = ceil(capacity / lanes).  Measured fastest: 2 lanes per
     // cell for 2-D p=3 (6 coefficients), 8 in 3-D (10 coefficients, stencils
-    // up to 56 rows), 4 otherwise.  Fewer lanes replicate less of the
+    // up to 56 rows), 16 for 2-D p=5 (15 coefficients: fewer lanes spill
+    // registers), 4 otherwise.  Fewer lanes replicate less of the
     // per-column work (pivot search, exchanges, broadcasts) across a cell.
-    const int lanes = dm.lanes ? dm.lanes : (dm.dim == 3 ? 8 : (dm.dim == 2 && dm.p == 3 ? 2 : 4));
+    const int lanes = dm.lanes ? dm.lanes
+                               : (dm.dim == 3 ? 8 : (dm.dim == 2 && dm.p == 3 ? 2 : (dm.dim == 2 && dm.p == 5 ? 16 : 4)));
     if (dm.dim == 1) {
         switch (dm.p) {
         case 2: return launch_k1<1, 2, 4, 2, 2, 2>(dm, a, st);
@@ -1489,6 +1496,10 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
             if (lanes == 16) return launch_k1<2, 4, 16, 2, 2, 3>(dm, a, st);
             if (lanes == 8) return launch_k1<2, 4, 8, 3, 4, 5>(dm, a, st);
             return launch_k1<2, 4, 4, 5, 7, 9>(dm, a, st);
+        }
+        if (dm.p == 5) {
+            if (lanes == 8) return launch_k1<2, 5, 8, 3, 4, 5>(dm, a, st);
+            return launch_k1<2, 5, 16, 2, 2, 3>(dm, a, st);
         }
     } else if (dm.dim == 3) {
         if (dm.p == 2) return launch_k1<3, 2, 4, 4, 4, 4>(dm, a, st);
@@ -1533,6 +1544,7 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
     if (dm.dim == 2) {
         if (dm.nq == 1) return launch_k23<2, 1>(dm, a, st);
         if (dm.nq == 2) return launch_k23<2, 2>(dm, a, st);
+        if (dm.nq == 3) return launch_k23<2, 3>(dm, a, st);
     }
     if (dm.dim == 3 && dm.nq == 3) return launch_k23<3, 3>(dm, a, st);
     return (int)hipErrorInvalidValue;
@@ -1583,6 +1595,7 @@ int launch_adjoint(const DevMesh &dm, const double *u, const double *v, const in
         if (dm.p == 2) return launch_adj<2, 2, 4, 2, 2, 2>(a, st);
         if (dm.p == 3) return launch_adj<2, 3, 4, 3, 4, 5>(a, st);
         if (dm.p == 4) return launch_adj<2, 4, 8, 3, 4, 5>(a, st);
+        if (dm.p == 5) return launch_adj<2, 5, 16, 2, 2, 3>(a, st);
     } else if (dm.dim == 3) {
         if (dm.p == 2) return launch_adj<3, 2, 4, 4, 4, 4>(a, st);
         if (dm.p == 3) return launch_adj<3, 3, 8, 4, 5, 7>(a, st);

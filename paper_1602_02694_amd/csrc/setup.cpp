@@ -434,7 +434,7 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     const int64_t nc = m.nc;
     if (prm.p < 2 || prm.p > 5) throw inval("p must be in 2..5");
     if (dim == 3 && prm.p > 3) throw Error{WLSENO_EUNSUPPORTED, "3-D supports p <= 3"};
-    if (dim == 2 && prm.p > 4) throw Error{WLSENO_EUNSUPPORTED, "2-D supports p <= 4"};
+    if (dim == 2 && prm.p > 5) throw Error{WLSENO_EUNSUPPORTED, "2-D supports p <= 5"};
     if (prm.flux != WLSENO_FLUX_ADVECTION && prm.flux != WLSENO_FLUX_BURGERS && prm.flux != WLSENO_FLUX_EULER)
         throw inval("flux must be advection, Burgers or Euler");
     if (prm.flux == WLSENO_FLUX_EULER && dim != 2)
@@ -558,8 +558,6 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     b.vrel.assign(nc * nvc * dim, 0.0);
     b.rvol.resize(nc);
     const double fact[5] = {1, 1, 2, 6, 24};
-    double dfact = 1.0;
-    for (int k = 2; k <= dim; ++k) dfact *= k;
     for (int64_t d = 0; d < nc; ++d) {
         int64_t u = b.perm[d];
         double e[4][3] = {{0}};
@@ -598,7 +596,7 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
                 int p02[2] = {idx[0], idx[2]}, p13[2] = {idx[1], idx[3]};
                 int p03[2] = {idx[0], idx[3]}, p12[2] = {idx[1], idx[2]};
                 double pairs = S(p01, 2) * S(p23, 2) + S(p02, 2) * S(p13, 2) + S(p03, 2) * S(p12, 2);
-                double df4 = dfact;
+                double df4 = 1.0;
                 for (int k = dim + 1; k <= dim + 4; ++k) df4 /= k;   // d!/(d+4)!
                 mu = (6.0 * S(idx, 4) + pairs) * df4;
             }

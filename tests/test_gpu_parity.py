@@ -148,6 +148,15 @@ def test_square_p4(lanes):
                  lanes=lanes)
 
 
+@pytest.mark.parametrize("lanes", [0, 8])
+def test_square_p5(lanes):
+    """Degree-4 polynomials (15 coefficients), 24-30 cell stencils, 3-point edges."""
+    mesh = jittered_square(15, 0.3, 96)
+    u0 = fields.cell_averages(mesh, lambda x: np.sin(3 * x[:, 0]) * np.cos(2 * x[:, 1]) + (x[:, 0] > 0.5))
+    _compare_all(mesh, u0, 4, 0.001, f"square15-p5-lanes{lanes}", p=5, n_lo=24, n_hi=30, flux="burgers",
+                 lanes=lanes)
+
+
 def test_square_p2():
     mesh = jittered_square(12, 0.3, 94)
     u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
@@ -162,13 +171,15 @@ def test_tiny_mesh_whole_domain_stencils():
     _compare_all(mesh, u0, 3, 0.01, "square3", p=3, n_lo=12, n_hi=20, flux="burgers")
 
 
-def test_polynomial_reproduction_gpu():
-    """Degree-2 data are reconstructed exactly by the GPU path too."""
+@pytest.mark.parametrize("p,n_lo,n_hi", [(3, 12, 20), (4, 18, 24), (5, 24, 30)])
+def test_polynomial_reproduction_gpu(p, n_lo, n_hi):
+    """Degree p-1 data are reconstructed exactly by the GPU path too (every
+    centred moment of the geometry records enters)."""
     torch = _torch()
     mesh = jittered_square(17, 0.3, 95)
-    fn = fields.polynomial_field(5, 2, 2)
-    w = _gpu(mesh, p=3, n_lo=12, n_hi=20)
-    o = _oracle(mesh, p=3, n_lo=12, n_hi=20)
+    fn = fields.polynomial_field(5, 2, p - 1)
+    w = _gpu(mesh, p=p, n_lo=n_lo, n_hi=n_hi)
+    o = _oracle(mesh, p=p, n_lo=n_lo, n_hi=n_hi)
     u = torch.tensor(fields.cell_averages(mesh, fn), device="cuda")
     fv = w.reconstruct(u)["fval"][0].cpu().numpy()
     exact = fn(o.mesh.qx.reshape(-1, 2)).reshape(fv.shape)

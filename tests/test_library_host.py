@@ -49,7 +49,7 @@ def _host_ctx(mesh, **kw):
     return w
 
 
-@pytest.mark.parametrize("case", ["line", "square", "square_p4", "cube"])
+@pytest.mark.parametrize("case", ["line", "square", "square_p4", "square_p5", "cube"])
 def test_stencils_equal_oracle(lib, case):
     from oracle.mesh import OracleMesh
 
@@ -59,6 +59,8 @@ def test_stencils_equal_oracle(lib, case):
         mesh, kw = jittered_square(24, 0.3, 2001), dict(p=3, n_lo=12, n_hi=20)
     elif case == "square_p4":
         mesh, kw = jittered_square(16, 0.3, 3001), dict(p=4, n_lo=20, n_hi=36)
+    elif case == "square_p5":
+        mesh, kw = jittered_square(16, 0.3, 3002), dict(p=5, n_lo=24, n_hi=30)
     else:
         mesh, kw = jittered_cube(6, 0.15, 4001), dict(p=3, n_lo=30, n_hi=50)
     w = _host_ctx(mesh, **kw)

@@ -60,6 +60,26 @@ def test_reconstruction_order_2d_p3():
 
 
 @pytest.mark.slow
+def test_reconstruction_order_2d_p5():
+    """Degree-4 reconstruction on 24-30 cell stencils: fifth order at the
+    facet points (3-point Gauss-Legendre edges), interior cells."""
+    import oracle
+
+    fn = lambda x: np.sin(2 * x[:, 0] + 1.0) * np.cos(3 * x[:, 1])
+    hs, errs = [], []
+    for P in (12, 24, 48):
+        mesh = jittered_square(P, 0.3, 210 + P)
+        ubar = fields.cell_averages(mesh, fn)
+        o = oracle.Oracle(2, mesh.verts, mesh.cells, p=5, n_lo=24, n_hi=30)
+        fv = o.reconstruct(ubar)["fval"][0]
+        exact = fn(o.mesh.qx.reshape(-1, 2)).reshape(fv.shape)
+        inner = np.all((o.mesh.cv > 0.2) & (o.mesh.cv < 0.8), axis=(1, 2))
+        errs.append(np.max(np.abs(fv - exact)[inner]))
+        hs.append(o.mesh.h)
+    assert _fit_slope(hs, errs) >= 5 - 0.5, (errs, _slopes(hs, errs))
+
+
+@pytest.mark.slow
 def test_reconstruction_order_3d_p3():
     import oracle
 

@@ -279,7 +279,8 @@ def test_rank_truncation_drops_dependent_column():
 
 # ------------------------------------------------- reproduction / invariants
 
-@pytest.mark.parametrize("dim,p,n_lo,n_hi", [(1, 3, 5, 5), (1, 5, 7, 7), (2, 3, 12, 20), (2, 4, 20, 36), (3, 3, 30, 50)])
+@pytest.mark.parametrize("dim,p,n_lo,n_hi", [(1, 3, 5, 5), (1, 5, 7, 7), (2, 3, 12, 20), (2, 4, 20, 36), (2, 5, 24, 30),
+                                          (3, 3, 30, 50)])
 def test_polynomial_reproduction(dim, p, n_lo, n_hi):
     """Sec. 3.1.1/3.2: cell averages of a degree p-1 polynomial are fitted exactly
     (zero residual), whatever the weights, so facet values are exact."""
