@@ -25,7 +25,8 @@ numerical rank is truncated, and cells where the Euler positivity fallback
 fires.
 """
 
-from .core import Oracle, build, basis, num_coeffs, wls_qrcp_solve, simplex_avg_monomial, eval_taylor, from_workload
+from .core import (Oracle, build, basis, num_coeffs, wls_qrcp_solve, simplex_avg_monomial, eval_taylor, from_workload,
+                   char_basis, euler_normal_flux)
 from .mesh import OracleMesh
 
 __all__ = ["Oracle", "OracleMesh", "build", "basis", "num_coeffs", "wls_qrcp_solve",

@@ -54,6 +54,8 @@ def lib(extended: bool = False):
         _lib.or_wls_qrcp_solve.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_double, dp, dp, ip]
         _lib.or_eval_taylor.argtypes = [C.c_int, C.c_int, ip, dp, dp]
         _lib.or_eval_taylor.restype = C.c_double
+        _lib.or_char_basis.argtypes = [C.c_int, C.c_double, dp, dp, dp, dp]
+        _lib.or_euler_normal_flux.argtypes = [C.c_int, C.c_double, dp, dp, dp]
         pp = C.POINTER(_Problem)
         _lib.or_cell_matrix.argtypes = [pp, C.c_int, dp]
         _lib.or_cell_weights.argtypes = [pp, C.c_int, dp, dp]
@@ -73,7 +75,7 @@ class _Problem(C.Structure):
     _fields_ = [
         ("dim", C.c_int), ("p", C.c_int), ("m", C.c_int), ("nvars", C.c_int),
         ("flux", C.c_int), ("weight_mode", C.c_int),
-        ("nc", C.c_int), ("nq", C.c_int), ("periodic", C.c_int), ("bc", C.c_int),
+        ("nc", C.c_int), ("nq", C.c_int), ("periodic", C.c_int), ("bc", C.c_int), ("characteristic", C.c_int),
         ("period", C.c_double), ("eps", C.c_double), ("alpha_w", C.c_double),
         ("rank_tol", C.c_double), ("h", C.c_double), ("gamma", C.c_double),
         ("adv", C.c_double * 3),
@@ -118,6 +120,26 @@ def simplex_avg_monomial(verts, center, a) -> float:
     return float(lib().or_simplex_avg_monomial(dim, _dp(verts), _dp(c), _ip(a)))
 
 
+def char_basis(dim, gamma, U, n):
+    """(L, R) of the Euler normal-flux Jacobian at state U along unit normal n."""
+    V = dim + 2
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    L = np.zeros((V, V))
+    R = np.zeros((V, V))
+    if lib().or_char_basis(int(dim), float(gamma), _dp(U), _dp(n), _dp(L), _dp(R)):
+        raise ValueError("characteristic basis: 1-D and 2-D only")
+    return L, R
+
+
+def euler_normal_flux(dim, gamma, U, n):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    F = np.zeros(dim + 2)
+    lib().or_euler_normal_flux(int(dim), float(gamma), _dp(U), _dp(n), _dp(F))
+    return F
+
+
 def wls_qrcp_solve(A, w, b, rank_tol: float = 1e-12):
     """Column-scaled weighted LS by Householder QRCP; returns (v, rank, rdiag, perm)."""
     A = np.ascontiguousarray(A, dtype=np.float64)
@@ -143,7 +165,8 @@ class Oracle:
 
     def __init__(self, dim, verts, cells, periodic=False, *, p=3, n_lo=None, n_hi=None,
                  flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2, alpha_w=1.5,
-                 rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None, extended=False, bc=0):
+                 rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None, extended=False, bc=0,
+                 characteristic=False):
         self.extended = bool(extended)
         self.mesh = OracleMesh(dim, verts, cells, periodic, p=p)
         om = self.mesh
@@ -178,6 +201,9 @@ class Oracle:
         P.flux, P.weight_mode = FLUX[flux], int(weight_mode)
         P.nc, P.nq, P.periodic = om.nc, om.nq, int(om.periodic)
         P.bc = int(bc)
+        if characteristic and (flux != "euler" or dim > 2):
+            raise ValueError("characteristic fields: the 1-D and 2-D Euler system only")
+        P.characteristic = int(bool(characteristic))
         P.period, P.eps, P.alpha_w, P.rank_tol = om.period, eps, alpha_w, rank_tol
         P.h, P.gamma = self.h, gamma
         for d in range(3):
@@ -249,6 +275,7 @@ class Oracle:
 def from_workload(wl, **kw) -> Oracle:
     s = dict(wl.settings)
     args = dict(p=s["p"], n_lo=s["n_lo"], n_hi=s["n_hi"], flux=s["flux"],
-                velocity=s.get("velocity", (1.0, 0.0, 0.0)), gamma=s.get("gamma", 1.4), bc=s.get("bc", 0))
+                velocity=s.get("velocity", (1.0, 0.0, 0.0)), gamma=s.get("gamma", 1.4), bc=s.get("bc", 0),
+                characteristic=s.get("characteristic", False))
     args.update(kw)
     return Oracle(wl.mesh.dim, wl.mesh.verts, wl.mesh.cells, wl.mesh.periodic, **args)

@@ -53,6 +53,7 @@ typedef struct {
     int dim, p, m, nvars, flux, weight_mode;
     int nc, nq, periodic;
     int bc;               /* boundary facets: 0 outside state = inside state; 1 outside state = 0 */
+    int characteristic;   /* Euler: 0 reconstruct conserved components; 1 characteristic fields per facet */
     double period, eps, alpha_w, rank_tol, h, gamma;
     double adv[3];
     const int *exps;      /* m x 3 exponents of the Taylor basis */
@@ -215,8 +216,10 @@ void or_cell_matrix(const or_problem *P, int i, double *A)
     for (int t = 0; t < stencil_size(P, i) * P->m; ++t) A[t] = (double)Ar[t];
 }
 
-/* Row weights omega for cell i from one scalar field u (length nc). */
-static void cell_weights(const or_problem *P, int i, const real *u, real *w)
+/* Row weights omega for cell i from the values of one scalar field: ui at the
+ * centre, us[r] at stencil row r, unb[lf] at the facet neighbour across lf
+ * (read only where that neighbour exists). */
+static void weights_from_values(const or_problem *P, int i, real ui, const real *us, const real *unb, real *w)
 {
     int n = stencil_size(P, i);
     const int *rows = P->col + P->row_ptr[i];
@@ -226,25 +229,37 @@ static void cell_weights(const or_problem *P, int i, const real *u, real *w)
     }
     real h = P->h;
     real eh2 = (real)P->eps * h * h;
-    real ui = u[i];
     /* beta of the centre: the smallest indicator among its facet neighbours */
     real beta_i = -1.0;
     for (int lf = 0; lf <= P->dim; ++lf) {
         int j = P->nbr[(size_t)i * (P->dim + 1) + lf];
         if (j < 0) continue;
-        real b = (u[j] - ui) * (u[j] - ui) + eh2;
+        real b = (unb[lf] - ui) * (unb[lf] - ui) + eh2;
         if (beta_i < 0.0 || b < beta_i) beta_i = b;
     }
     if (beta_i < 0.0) beta_i = eh2;
     for (int r = 0; r < n; ++r) {
-        int j = rows[r];
-        if (j == i) {
+        if (rows[r] == i) {
             w[r] = (real)P->alpha_w / beta_i;
         } else {
-            real b = (u[j] - ui) * (u[j] - ui) + eh2;
+            real b = (us[r] - ui) * (us[r] - ui) + eh2;
             w[r] = 1.0 / b;
         }
     }
+}
+
+/* Row weights omega for cell i from one scalar field u (length nc). */
+static void cell_weights(const or_problem *P, int i, const real *u, real *w)
+{
+    int n = stencil_size(P, i);
+    const int *rows = P->col + P->row_ptr[i];
+    real us[OR_MAXN], unb[OR_MAXF];
+    for (int r = 0; r < n; ++r) us[r] = u[rows[r]];
+    for (int lf = 0; lf <= P->dim; ++lf) {
+        int j = P->nbr[(size_t)i * (P->dim + 1) + lf];
+        unb[lf] = j >= 0 ? u[j] : 0.0;
+    }
+    weights_from_values(P, i, u[i], us, unb, w);
 }
 
 void or_cell_weights(const or_problem *P, int i, const double *u, double *w)
@@ -433,6 +448,97 @@ static real spectral_radius(const or_problem *P, const real *U, const real *n)
     }
 }
 
+/* Characteristic decomposition of the Euler system along the unit normal n
+ * (Sec. 5.2: the eigen-decomposition of the flux Jacobian, R^{-1} f' R =
+ * Lambda).  Fields, in order: q_n - c, q_n (entropy), in 2-D q_n (shear,
+ * along the tangent t = (-n_y, n_x)), q_n + c, with q_n = v.n, c the speed of
+ * sound and H the enthalpy at the state U.  R (V x V, row-major) holds the
+ * right eigenvectors as columns -- in 1-D exactly the paper's R(u) -- and L
+ * its inverse, the left eigenvectors as rows (b1 = (gamma-1)/c^2,
+ * b2 = |v|^2 b1 / 2). */
+static void char_basis(const or_problem *P, const real *U, const real *n, real *L, real *R)
+{
+    int D = P->dim, V = D + 2, kc = V - 1;
+    real g = (real)P->gamma, rho = U[0], vel[OR_MAXDIM], q2 = 0.0, qn = 0.0;
+    for (int d = 0; d < D; ++d) {
+        vel[d] = U[1 + d] / rho;
+        q2 += vel[d] * vel[d];
+        qn += vel[d] * n[d];
+    }
+    real pr = euler_pressure(P, U);
+    real c = sqrt(g * pr / rho), H = (U[D + 1] + pr) / rho;
+    real b1 = (g - 1.0) / (c * c), b2 = 0.5 * q2 * b1;
+    for (int t = 0; t < V * V; ++t) L[t] = R[t] = 0.0;
+    /* q_n - c */
+    R[0 * V + 0] = 1.0;
+    for (int d = 0; d < D; ++d) R[(1 + d) * V + 0] = vel[d] - c * n[d];
+    R[(D + 1) * V + 0] = H - c * qn;
+    L[0 * V + 0] = 0.5 * (b2 + qn / c);
+    for (int d = 0; d < D; ++d) L[0 * V + 1 + d] = 0.5 * (-b1 * vel[d] - n[d] / c);
+    L[0 * V + D + 1] = 0.5 * b1;
+    /* q_n, entropy */
+    R[0 * V + 1] = 1.0;
+    for (int d = 0; d < D; ++d) R[(1 + d) * V + 1] = vel[d];
+    R[(D + 1) * V + 1] = 0.5 * q2;
+    L[1 * V + 0] = 1.0 - b2;
+    for (int d = 0; d < D; ++d) L[1 * V + 1 + d] = b1 * vel[d];
+    L[1 * V + D + 1] = -b1;
+    /* q_n, shear (2-D) */
+    if (D == 2) {
+        real t[2] = {-n[1], n[0]};
+        real qt = vel[0] * t[0] + vel[1] * t[1];
+        R[1 * V + 2] = t[0];
+        R[2 * V + 2] = t[1];
+        R[3 * V + 2] = qt;
+        L[2 * V + 0] = -qt;
+        L[2 * V + 1] = t[0];
+        L[2 * V + 2] = t[1];
+    }
+    /* q_n + c */
+    R[0 * V + kc] = 1.0;
+    for (int d = 0; d < D; ++d) R[(1 + d) * V + kc] = vel[d] + c * n[d];
+    R[(D + 1) * V + kc] = H + c * qn;
+    L[kc * V + 0] = 0.5 * (b2 - qn / c);
+    for (int d = 0; d < D; ++d) L[kc * V + 1 + d] = 0.5 * (-b1 * vel[d] + n[d] / c);
+    L[kc * V + D + 1] = 0.5 * b1;
+}
+
+int or_char_basis(int dim, double gamma, const double *U, const double *n, double *L, double *R)
+{
+    if (dim < 1 || dim > 2) return -1;
+    or_problem P;
+    memset(&P, 0, sizeof P);
+    P.dim = dim;
+    P.gamma = gamma;
+    int V = dim + 2;
+    real Ur[OR_MAXV], nr[OR_MAXDIM], Lr[OR_MAXV * OR_MAXV], Rr[OR_MAXV * OR_MAXV];
+    for (int t = 0; t < V; ++t) Ur[t] = U[t];
+    for (int d = 0; d < dim; ++d) nr[d] = n[d];
+    char_basis(&P, Ur, nr, Lr, Rr);
+    for (int t = 0; t < V * V; ++t) {
+        L[t] = (double)Lr[t];
+        R[t] = (double)Rr[t];
+    }
+    return 0;
+}
+
+/* Euler normal flux F(U).n of one state (pins). */
+int or_euler_normal_flux(int dim, double gamma, const double *U, const double *n, double *F)
+{
+    if (dim < 1 || dim > 3) return -1;
+    or_problem P;
+    memset(&P, 0, sizeof P);
+    P.dim = dim;
+    P.gamma = gamma;
+    P.flux = OR_EULER;
+    real Ur[OR_MAXV], nr[OR_MAXDIM], Fr[OR_MAXV];
+    for (int t = 0; t < dim + 2; ++t) Ur[t] = U[t];
+    for (int d = 0; d < dim; ++d) nr[d] = n[d];
+    normal_flux(&P, Ur, nr, Fr);
+    for (int t = 0; t < dim + 2; ++t) F[t] = (double)Fr[t];
+    return 0;
+}
+
 /* --------------------------------------------------------- reconstruction */
 
 static int faces_per_cell(const or_problem *P) { return P->dim + 1; }
@@ -456,23 +562,79 @@ static void reconstruct_cell(const or_problem *P, int i, const real *u, real *co
     const int *rows = P->col + P->row_ptr[i];
     real A[OR_MAXN * OR_MAXM], w[OR_MAXN], b[OR_MAXN];
     real v[OR_MAXV][OR_MAXM];
-    cell_matrix(P, i, A);
-    for (int var = 0; var < V; ++var) {
-        const real *uv = u + (size_t)var * P->nc;
-        cell_weights(P, i, uv, w);
-        for (int r = 0; r < n; ++r) b[r] = uv[rows[r]];
-        int rk = qrcp_solve(n, m, A, w, b, P->rank_tol, v[var], NULL, NULL);
-        if (rank) rank[(size_t)var * P->nc + i] = rk;
-    }
-    /* facet values of the reconstruction */
     real vals[OR_MAXV][OR_MAXF][OR_MAXQ];
-    for (int lf = 0; lf < F; ++lf)
-        for (int q = 0; q < P->nq; ++q) {
-            const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
-            real dx[OR_MAXDIM];
-            for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)i * D + d];
-            for (int var = 0; var < V; ++var) vals[var][lf][q] = eval_taylor(D, m, P->exps, v[var], dx);
+    cell_matrix(P, i, A);
+    if (P->flux == OR_EULER && P->characteristic) {
+        /* characteristic-wise (Sec. 5.2): for each facet, decompose along its
+         * normal at the facet state (mean of the two cells' averages; the
+         * cell's own average on the boundary), reconstruct every field with its
+         * own weights, evaluate at the facet's points and map back with R.
+         * There is no single polynomial per component: coefficients are NaN,
+         * the rank is the smallest over the facets. */
+        for (int var = 0; var < V; ++var) {
+            for (int k = 0; k < m; ++k) v[var][k] = NAN;
+            if (rank) rank[(size_t)var * P->nc + i] = m + 1;
         }
+        for (int lf = 0; lf < F; ++lf) {
+            int jn = P->nbr[(size_t)i * F + lf];
+            real Ub[OR_MAXV], nn[OR_MAXDIM], Lc[OR_MAXV * OR_MAXV], Rc[OR_MAXV * OR_MAXV];
+            for (int c = 0; c < V; ++c) {
+                real ui = u[(size_t)c * P->nc + i];
+                Ub[c] = jn >= 0 ? 0.5 * (ui + u[(size_t)c * P->nc + jn]) : ui;
+            }
+            load_normal(P, i, lf, nn);
+            char_basis(P, Ub, nn, Lc, Rc);
+            real wq[OR_MAXV][OR_MAXQ];
+            for (int k = 0; k < V; ++k) {
+                /* field k of every stencil cell and facet neighbour */
+                real unb[OR_MAXF], ui = 0.0, vk[OR_MAXM];
+                for (int r = 0; r < n; ++r) {
+                    real t = 0.0;
+                    for (int c = 0; c < V; ++c) t += Lc[k * V + c] * u[(size_t)c * P->nc + rows[r]];
+                    b[r] = t;
+                }
+                for (int c = 0; c < V; ++c) ui += Lc[k * V + c] * u[(size_t)c * P->nc + i];
+                for (int f2 = 0; f2 < F; ++f2) {
+                    int j = P->nbr[(size_t)i * F + f2];
+                    real t = 0.0;
+                    if (j >= 0)
+                        for (int c = 0; c < V; ++c) t += Lc[k * V + c] * u[(size_t)c * P->nc + j];
+                    unb[f2] = t;
+                }
+                weights_from_values(P, i, ui, b, unb, w);
+                int rk = qrcp_solve(n, m, A, w, b, P->rank_tol, vk, NULL, NULL);
+                if (rank && rk < rank[(size_t)k * P->nc + i]) rank[(size_t)k * P->nc + i] = rk;
+                for (int q = 0; q < P->nq; ++q) {
+                    const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
+                    real dx[OR_MAXDIM];
+                    for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)i * D + d];
+                    wq[k][q] = eval_taylor(D, m, P->exps, vk, dx);
+                }
+            }
+            for (int q = 0; q < P->nq; ++q)
+                for (int c = 0; c < V; ++c) {
+                    real t = 0.0;
+                    for (int k = 0; k < V; ++k) t += Rc[c * V + k] * wq[k][q];
+                    vals[c][lf][q] = t;
+                }
+        }
+    } else {
+        for (int var = 0; var < V; ++var) {
+            const real *uv = u + (size_t)var * P->nc;
+            cell_weights(P, i, uv, w);
+            for (int r = 0; r < n; ++r) b[r] = uv[rows[r]];
+            int rk = qrcp_solve(n, m, A, w, b, P->rank_tol, v[var], NULL, NULL);
+            if (rank) rank[(size_t)var * P->nc + i] = rk;
+        }
+        /* facet values of the reconstruction */
+        for (int lf = 0; lf < F; ++lf)
+            for (int q = 0; q < P->nq; ++q) {
+                const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
+                real dx[OR_MAXDIM];
+                for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)i * D + d];
+                for (int var = 0; var < V; ++var) vals[var][lf][q] = eval_taylor(D, m, P->exps, v[var], dx);
+            }
+    }
     /* Euler: keep the cell averages if any facet state is not physical */
     int fb = 0;
     if (P->flux == OR_EULER) {
@@ -597,6 +759,27 @@ static void divergence_cell(const or_problem *P, int i, const real *u, const rea
                 /* transmissive (u+ = u-), or a zero far field (u+ = 0): with the
                  * upwind flux of linear advection, outflow unchanged and no inflow */
                 for (int var = 0; var < V; ++var) up[var] = P->bc == 1 ? 0.0 : um[var];
+            } else if (P->flux == OR_EULER && P->characteristic) {
+                /* per-facet reconstructions: the neighbour's own value at the
+                 * same point, found as its nearest facet point on a facet it
+                 * shares with cell i */
+                const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
+                int bf = -1, bq = -1;
+                real bd = 0.0;
+                for (int f2 = 0; f2 < F; ++f2) {
+                    if (P->nbr[(size_t)j * F + f2] != i) continue;
+                    for (int q2 = 0; q2 < P->nq; ++q2) {
+                        const double *y = P->qx + (((size_t)j * F + f2) * P->nq + q2) * D;
+                        real dd = 0.0;
+                        for (int d = 0; d < D; ++d) {
+                            real e = (real)y[d] - (real)x[d];
+                            if (d == 0) e = wrap(P, e);
+                            dd += e * e;
+                        }
+                        if (bf < 0 || dd < bd) { bf = f2; bq = q2; bd = dd; }
+                    }
+                }
+                for (int var = 0; var < V; ++var) up[var] = fval[fval_index(P, var, j, bf, bq)];
             } else {
                 const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
                 real dx[OR_MAXDIM];
