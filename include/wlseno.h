@@ -93,6 +93,15 @@ typedef struct {
                             (transmissive); 1 = zero (a zero far field: with the upwind flux
                             of linear advection, outflow as before and no inflow); 1 is
                             EINVAL for the Euler system */
+    int32_t characteristic; /* Euler only (else EINVAL for 1): 0 = reconstruct the conserved
+                            components; 1 = reconstruct characteristic fields per facet
+                            (Sec. 5.1.4, 5.2.4): for each facet, the eigenvectors of the
+                            normal-flux Jacobian at the mean of the two cells' averages (the
+                            cell's own on the boundary) project the stencil averages, each
+                            field gets its own weights and fit, and R maps the facet-point
+                            values back; 4 x (dim+1) solves per cell.  Coefficients are then
+                            per facet: wlseno_reconstruct rejects a coefficient output
+                            (EINVAL); its rank output is the smallest over the facets. */
 } wlseno_params;
 
 typedef struct {

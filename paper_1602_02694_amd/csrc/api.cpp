@@ -177,6 +177,7 @@ void upload_build(wlseno_ctx *c)
     dm.period = m.periodic ? m.period : 0.0;
     dm.gamma = b.prm.gamma;
     dm.bc = b.prm.bc;
+    dm.characteristic = b.prm.characteristic;
     for (int d = 0; d < 3; ++d) dm.vel[d] = b.prm.velocity[d];
     dm.geo = upload(c, b.geo);
     dm.vrel = upload(c, b.vrel);
@@ -293,6 +294,7 @@ void wlseno_params_default(wlseno_params *out)
     out->velocity[0] = 1.0;
     out->gamma = 1.4;
     out->bc = 0;
+    out->characteristic = 0;
 }
 
 wlseno_status wlseno_create(int device, wlseno_t *out)
@@ -461,6 +463,8 @@ wlseno_status wlseno_reconstruct(wlseno_t ctx, const double *u_dev, double *coef
 {
     API_BEGIN(ctx)
     if (!u_dev) throw Error{WLSENO_EINVAL, "u_dev is NULL"};
+    if (coef_dev && ctx->have_build && ctx->dm.characteristic)
+        throw Error{WLSENO_EINVAL, "no coefficient output with characteristic fields (one fit per facet)"};
     need_device(ctx);
     check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
     check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");

@@ -94,6 +94,7 @@ struct DevMesh {
     int dim = 0, p = 0, m = 0, nq = 0, nf = 0, nvars = 1, gs = 0;
     int flux = 0, weight_mode = 0, max_stencil = 0;
     int bc = 0;   // boundary facets: 0 outside state = inside state, 1 outside state = 0
+    int characteristic = 0;   // Euler: reconstruct characteristic fields per facet
     int lanes = 0;   // lanes per cell in the reconstruction: 0 = automatic, 4 or 8
     int64_t nc = 0;
     int nbuckets = 0;

@@ -34,6 +34,9 @@ constexpr int kFluxAdv = WLSENO_FLUX_ADVECTION;
 constexpr double kPivotTie = 1e-10;
 constexpr int kFluxBurgers = WLSENO_FLUX_BURGERS;
 constexpr int kFluxEuler = WLSENO_FLUX_EULER;
+// Euler reconstructed in characteristic fields per facet (a kernel variant,
+// not a flux of the interface: the flux itself is the Euler one)
+constexpr int kFluxEulerChar = 16;
 
 constexpr int binom(int n, int k)
 {
@@ -282,6 +285,51 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 
 // ------------------------------------------------------ per-cell solve
 
+// Characteristic decomposition of the 2-D Euler system along the unit normal
+// of facet fl of cell c (Sec. 5.1.4 gives R(u) in 1-D; Sec. 5.2.4 applies it
+// along facet normals): row v of L = R^{-1} and column v of R at the facet
+// state, the mean of the averages of c and of its neighbour across fl (c's own
+// average on the boundary).  Fields: q_n - c, q_n (entropy), q_n (shear, along
+// (-n_y, n_x)), q_n + c.
+__device__ __forceinline__ void char_vectors(const double *u, const double *normal, const int32_t *sib, int64_t N,
+                                             int64_t c, int fl, int v, double gamma, double (&Lr)[4],
+                                             double (&Rc)[4])
+{
+    const int32_t sbf = sib[(int64_t)fl * N + c];
+    const int64_t nb = sbf >= 0 ? (int64_t)(sbf >> 2) : c;
+    double U[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double ui = u[(int64_t)k * N + c], uj = u[(int64_t)k * N + nb];
+        U[k] = sbf >= 0 ? 0.5 * (ui + uj) : ui;
+    }
+    double nx = normal[((int64_t)fl * N + c) * 2 + 0], ny = normal[((int64_t)fl * N + c) * 2 + 1];
+    const double il = 1.0 / sqrt(nx * nx + ny * ny);
+    nx *= il;
+    ny *= il;
+    const double rho = U[0], ux = U[1] / rho, uy = U[2] / rho;
+    const double q2 = ux * ux + uy * uy, qn = ux * nx + uy * ny;
+    const double pr = (gamma - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) / rho);
+    const double cs = sqrt(gamma * pr / rho), H = (U[3] + pr) / rho;
+    const double b1 = (gamma - 1.0) / (cs * cs), b2 = 0.5 * q2 * b1;
+    if (v == 0) {
+        Rc[0] = 1.0; Rc[1] = ux - cs * nx; Rc[2] = uy - cs * ny; Rc[3] = H - cs * qn;
+        Lr[0] = 0.5 * (b2 + qn / cs); Lr[1] = 0.5 * (-b1 * ux - nx / cs); Lr[2] = 0.5 * (-b1 * uy - ny / cs);
+        Lr[3] = 0.5 * b1;
+    } else if (v == 1) {
+        Rc[0] = 1.0; Rc[1] = ux; Rc[2] = uy; Rc[3] = 0.5 * q2;
+        Lr[0] = 1.0 - b2; Lr[1] = b1 * ux; Lr[2] = b1 * uy; Lr[3] = -b1;
+    } else if (v == 2) {
+        const double qt = -ux * ny + uy * nx;
+        Rc[0] = 0.0; Rc[1] = -ny; Rc[2] = nx; Rc[3] = qt;
+        Lr[0] = -qt; Lr[1] = -ny; Lr[2] = nx; Lr[3] = 0.0;
+    } else {
+        Rc[0] = 1.0; Rc[1] = ux + cs * nx; Rc[2] = uy + cs * ny; Rc[3] = H + cs * qn;
+        Lr[0] = 0.5 * (b2 - qn / cs); Lr[1] = 0.5 * (-b1 * ux + nx / cs); Lr[2] = 0.5 * (-b1 * uy + ny / cs);
+        Lr[3] = 0.5 * b1;
+    }
+}
+
 // Centroid offset of a stencil cell (record gxs: centroid, then moments) from
 // x_c, wrapped into the period on a periodic line.
 template <int DIM>
@@ -513,7 +561,12 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     constexpr int NMOM = M - 1 - DIM;
     constexpr int GS = geo_stride<DIM, P>();
     constexpr int RS = (M + G - 1) / G;
-    constexpr int V = FLUX == kFluxEuler ? DIM + 2 : 1;
+    constexpr bool CHAR = FLUX == kFluxEulerChar;
+    constexpr bool EULER = FLUX == kFluxEuler || CHAR;
+    static_assert(!CHAR || DIM == 2, "characteristic fields: 2-D only");
+    constexpr int V = EULER ? DIM + 2 : 1;
+    // solves per cell: one per component, or (characteristic) one per field and facet
+    constexpr int NIT = CHAR ? V * F : V;
     constexpr int CPB = 256 / G;
 
     const bool live = cell < cell_end;
@@ -566,12 +619,12 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     // Burgers: sum of the unit normal's components; Euler: the area-scaled
     // normal, on this lane's facets (for the Lax-Friedrichs alpha bound)
     double nsm[FPL];
-    double nrm[FLUX == kFluxEuler ? FPL : 1][DIM];
+    double nrm[EULER ? FPL : 1][DIM];
 #pragma unroll
     for (int t = 0; t < FPL; ++t) {
         const int lf = g + t * G < F ? g + t * G : F - 1;
         if constexpr (FLUX == kFluxBurgers) nsm[t] = a.nsum[lf * N + c];
-        if constexpr (FLUX == kFluxEuler) {
+        if constexpr (EULER) {
 #pragma unroll
             for (int d = 0; d < DIM; ++d) nrm[t][d] = a.normal[(lf * N + c) * DIM + d];
         }
@@ -581,18 +634,33 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     const bool user = live && (a.fv_user || a.rank_user || a.coef_user);
     const int64_t uid = user ? (int64_t)a.perm[c] : 0;
 
+    int rkm = 0;   // characteristic: smallest rank of a field over the facets
 #pragma unroll 1
-    for (int v = 0; v < V; ++v) {
-    const double *uv = a.u + (int64_t)v * N;
-    const double uc = uv[c];
+    for (int it = 0; it < NIT; ++it) {
+    // component v, or (characteristic) field v of facet fl
+    const int v = CHAR ? it / F : it;
+    const int fl = CHAR ? it - v * F : 0;
+    double Lr[4], Rc[4];
+    if constexpr (CHAR) char_vectors(a.u, a.normal, a.sib, N, c, fl, v, a.gamma, Lr, Rc);
+    auto field = [&](int64_t j) -> double {
+        if constexpr (CHAR) {
+            double t = Lr[0] * a.u[j];
+#pragma unroll
+            for (int k = 1; k < V; ++k) t = fma(Lr[k], a.u[(int64_t)k * N + j], t);
+            return t;
+        } else {
+            return a.u[(int64_t)v * N + j];
+        }
+    };
+    const double uc = field(c);
     double unb[F];
 #pragma unroll
-    for (int lf = 0; lf < F; ++lf) unb[lf] = uv[sb[lf] >= 0 ? (sb[lf] >> 2) : c];
+    for (int lf = 0; lf < F; ++lf) unb[lf] = field(sb[lf] >= 0 ? (sb[lf] >> 2) : c);
     double ug[RPL], gx[RPL][DIM + NMOM];
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         const int64_t j = jrow[s] >= 0 ? (int64_t)jrow[s] : c;
-        ug[s] = uv[j];
+        ug[s] = field(j);
 #pragma unroll
         for (int t = 0; t < DIM + NMOM; ++t) gx[s][t] = a.geo[j * GS + t];
     }
@@ -657,6 +725,41 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     double coef[M];
 #pragma unroll
     for (int o = 0; o < M; ++o) coef[o] = lc[o];
+    if constexpr (CHAR) {
+        rkm = fl == 0 ? rank : min(rkm, rank);
+        if (live && a.rank_user && g == 0 && fl == F - 1) a.rank_user[(int64_t)v * N + uid] = rkm;
+        // facet fl only, by the lane that holds its values: field v at its
+        // points, mapped back with column v of R and summed over the fields
+        if (g == fl % G) {
+            const int ia = fl == 2 ? 0 : fl + 1, ib = fl == 0 ? 2 : fl - 1;
+            double pa[DIM], pb[DIM];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                pa[d] = a.vrel[(c * F + ia) * DIM + d];
+                pb[d] = a.vrel[(c * F + ib) * DIM + d];
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                double x[DIM];
+                edge_point<DIM, Q>(pa, pb, q, x);
+                double pw[DIM][P];
+                scaled_powers<DIM, P>(x, pw);
+                double val = 0.0;
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    double ph = coef[k];
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d) ph *= pw[d][B.e[k][d]];
+                    val += ph;
+                }
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    double *dst = lfv + (k * F + fl) * Q + q;
+                    *dst = v == 0 ? Rc[k] * val : fma(Rc[k], val, *dst);
+                }
+            }
+        }
+    } else {
     if (live && a.rank_user && g == 0) a.rank_user[(int64_t)v * N + uid] = rank;
 
     // evaluate at the facet points: lane g handles facets g, g+G, ...
@@ -702,7 +805,8 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
         for (int o = 0; o < M; ++o)
             if ((o % G) == g) a.coef_user[((int64_t)v * N + uid) * M + o] = coef[o];
     }
-    }   // components
+    }   // component-wise evaluation
+    }   // solves
 
     if constexpr (V > 1) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -752,7 +856,7 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
 #pragma unroll
                     for (int v = 0; v < V; ++v) a.fv_user[(((int64_t)v * N + uid) * F + lf) * Q + q] = U[v];
                 }
-                if constexpr (FLUX == kFluxEuler) {
+                if constexpr (EULER) {
                     // |v.n| + c with the unit normal n = m / |m|
                     double mn = 0.0, mm = 0.0;
 #pragma unroll
@@ -771,7 +875,7 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
             }
         }
     }
-    if (live && a.coef_user && fallback) {
+    if (!CHAR && live && a.coef_user && fallback) {
 #pragma unroll
         for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -803,7 +907,8 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
 {
     constexpr int CPB = 256 / G;   // cells per workgroup
     // per cell: M coefficients; for the Euler system also its facet values [V][F][Q]
-    __shared__ double lds[CPB * (Basis<DIM, P>::M + (FLUX == kFluxEuler ? (DIM + 2) * (DIM + 1) * num_q<DIM, P>() : 0))];
+    __shared__ double lds[CPB * (Basis<DIM, P>::M +
+                                 (FLUX == kFluxEuler || FLUX == kFluxEulerChar ? (DIM + 2) * (DIM + 1) * num_q<DIM, P>() : 0))];
     const int L = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int g = (int)(threadIdx.x % G);
     const int slot = (int)(threadIdx.x / G);
@@ -1357,6 +1462,10 @@ __global__ void k_clear_alpha(unsigned long long *alpha, int nslot)
 // ------------------------------------------------------------ dispatch
 inline int blocks_for(int64_t work, int per_block) { return (int)((work + per_block - 1) / per_block); }
 
+// Lanes per cell of the characteristic-field variant (2-D Euler): 4 x 3 solves
+// per cell; enough lanes that the rows of a solve stay in registers.
+constexpr int char_lanes(int p) { return p == 2 ? 4 : (p == 5 ? 16 : 8); }
+
 template <int DIM, int P, int G, int R0, int R1, int R2>
 int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
 {
@@ -1371,10 +1480,20 @@ int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
     if (dm.flux == kFluxBurgers) {
         hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
     } else if (dm.flux == kFluxEuler) {
-        if constexpr (DIM == 2)
-            hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxEuler, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
-        else
+        if constexpr (DIM == 2) {
+            if (dm.characteristic) {
+                // one lane count per order (launch_reconstruct picks it)
+                if constexpr (G == char_lanes(P))
+                    hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxEulerChar, G, R0, R1, R2>), dim3(nb), dim3(256), 0,
+                                       st, args);
+                else
+                    return (int)hipErrorInvalidValue;
+            } else {
+                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxEuler, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
+            }
+        } else {
             return (int)hipErrorInvalidValue;
+        }
     } else {
         hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxAdv, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
     }
@@ -1485,6 +1604,15 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
         case 5: return launch_k1<1, 5, 4, 2, 2, 2>(dm, a, st);
         }
     } else if (dm.dim == 2) {
+        if (dm.flux == kFluxEuler && dm.characteristic) {
+            switch (dm.p) {
+            case 2: return launch_k1<2, 2, char_lanes(2), 2, 2, 2>(dm, a, st);
+            case 3: return launch_k1<2, 3, char_lanes(3), 2, 2, 3>(dm, a, st);
+            case 4: return launch_k1<2, 4, char_lanes(4), 3, 4, 5>(dm, a, st);
+            case 5: return launch_k1<2, 5, char_lanes(5), 2, 2, 3>(dm, a, st);
+            }
+            return (int)hipErrorInvalidValue;
+        }
         if (dm.p == 2) return launch_k1<2, 2, 4, 2, 2, 2>(dm, a, st);
         if (dm.p == 3) {
             if (lanes == 2) return launch_k1<2, 3, 2, 6, 8, 10>(dm, a, st);

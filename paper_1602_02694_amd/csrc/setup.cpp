@@ -443,6 +443,9 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     if (prm.weight_mode != 0 && prm.weight_mode != 1) throw inval("weight_mode must be 0 or 1");
     if (prm.bc != 0 && prm.bc != 1) throw inval("bc must be 0 or 1");
     if (prm.bc == 1 && prm.flux == WLSENO_FLUX_EULER) throw inval("bc = 1 (zero outside state) is not valid for Euler");
+    if (prm.characteristic != 0 && prm.characteristic != 1) throw inval("characteristic must be 0 or 1");
+    if (prm.characteristic && prm.flux != WLSENO_FLUX_EULER)
+        throw inval("characteristic = 1 applies to the Euler system only");
     if (prm.lanes != 0 && prm.lanes != 2 && prm.lanes != 4 && prm.lanes != 8 && prm.lanes != 16)
         throw inval("lanes must be 0, 2, 4, 8 or 16");
     if (!(prm.eps >= 0.0) || !(prm.alpha_w > 0.0) || !(prm.rank_tol >= 0.0))

@@ -83,7 +83,7 @@ class WLSENO:
         return mid.value
 
     def stencil_build(self, p=3, n_lo=12, n_hi=20, flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2,
-                      alpha_w=1.5, rank_tol=1e-12, weight_mode=0, gamma=1.4, lanes=0, bc=0):
+                      alpha_w=1.5, rank_tol=1e-12, weight_mode=0, gamma=1.4, lanes=0, bc=0, characteristic=False):
         prm = N.Params()
         self._lib.wlseno_params_default(C.byref(prm))
         prm.p, prm.n_lo, prm.n_hi = int(p), int(n_lo), int(n_hi)
@@ -91,11 +91,13 @@ class WLSENO:
         prm.weight_mode = int(weight_mode)
         prm.lanes = int(lanes)
         prm.bc = int(bc)
+        prm.characteristic = int(bool(characteristic))
         prm.eps, prm.alpha_w, prm.rank_tol, prm.gamma = float(eps), float(alpha_w), float(rank_tol), float(gamma)
         for d in range(3):
             prm.velocity[d] = float(velocity[d]) if d < len(velocity) else 0.0
         self._check(self._lib.wlseno_stencil_build(self._h, C.byref(prm)))
         self.flux = flux
+        self.characteristic = bool(characteristic)
         self._record_tag = None
 
     def info(self) -> dict:
@@ -128,6 +130,8 @@ class WLSENO:
         inf = self.info()
         V, nc = inf["n_vars"], inf["n_cell"]
         out = {}
+        if coef and getattr(self, "characteristic", False):
+            coef = False        # one fit per facet: no per-cell coefficients
         if coef:
             out["coef"] = torch.empty((V, nc, inf["m"]), dtype=torch.float64, device=u.device)
         if facevals:

@@ -180,6 +180,30 @@ def cell_conditions(o, u):
     return out
 
 
+def char_cell_conditions(o, u):
+    """kappa per (field, cell) for characteristic-wise reconstruction: the
+    largest cond_2(W A S) over the cell's facets, with the weights of each
+    field projected at that facet's state (2-D Euler)."""
+    import oracle
+
+    u = np.asarray(u, dtype=np.float64).reshape(o.nvars, o.nc)
+    out = np.zeros((o.nvars, o.nc))
+    normal = o.mesh.normal
+    for i in range(o.nc):
+        A = o.cell_matrix(i)
+        for lf in range(o.nf):
+            j = o.mesh.nbr[i, lf]
+            Ub = 0.5 * (u[:, i] + u[:, j]) if j >= 0 else u[:, i]
+            L, _ = oracle.char_basis(o.dim, o._P.gamma, Ub, normal[i, lf])
+            wf = L @ u
+            for v in range(o.nvars):
+                WA = o.cell_weights(i, wf[v])[:, None] * A
+                nr = np.linalg.norm(WA, axis=0)
+                sv = np.linalg.svd(WA / np.where(nr > 0, nr, 1.0), compute_uv=False)
+                out[v, i] = max(out[v, i], sv[0] / max(sv[-1], 1e-300))
+    return out
+
+
 def neighbourhood_max(o, x):
     """max of a per-cell array over each cell and its facet neighbours."""
     x = np.asarray(x)

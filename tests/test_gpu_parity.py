@@ -8,8 +8,8 @@ field's magnitude).  Stencils are integers and must be identical.
 import numpy as np
 import pytest
 
-from parity import (assert_parity, assert_poly_parity, cell_conditions, cell_noise, flux_scale, floor_tol,
-                    neighbourhood_max)
+from parity import (assert_parity, assert_poly_parity, cell_conditions, cell_noise, char_cell_conditions, flux_scale,
+                    floor_tol, neighbourhood_max)
 from workloads import configs, periodic_line, uniform_periodic_line, jittered_square, fields
 
 pytestmark = pytest.mark.gpu
@@ -63,7 +63,12 @@ def _compare_all(mesh, u0, steps, dt, name, **kw):
     ox = _oracle(mesh, extended=True, stencil=(o.row_ptr, o.col), **kw)
     rp, col = w.stencil()
     assert np.array_equal(rp, o.row_ptr) and np.array_equal(col, o.col), "stencils differ"
-    kappa = cell_conditions(o, u0)                       # (V, nc)
+    if kw.get("characteristic"):
+        # every component of a facet value mixes all fields of that facet
+        kc = char_cell_conditions(o, u0)
+        kappa = np.broadcast_to(kc.max(axis=0, keepdims=True), kc.shape)
+    else:
+        kappa = cell_conditions(o, u0)                   # (V, nc)
     # the flux couples a cell to its facet neighbours and, for a system, all
     # components to each other
     kappa_nb = np.broadcast_to(neighbourhood_max(o, kappa.max(axis=0, keepdims=True)), kappa.shape)
@@ -75,9 +80,10 @@ def _compare_all(mesh, u0, steps, dt, name, **kw):
     assert np.array_equal(rec["rank"].cpu().numpy(), ref["rank"]), "numerical ranks differ"
     fv_floor = floor_tol(kappa[:, :, None, None], cell_noise(ref["fval"], refx["fval"], cell_axes=2))
     assert_parity(rec["fval"].cpu().numpy(), ref["fval"], f"{name} facet values", tol_floor=fv_floor)
-    # Taylor coefficients, compared through the polynomials they define on each cell
-    assert_poly_parity(rec["coef"].cpu().numpy(), ref["coef"], o, u0, f"{name} polynomials",
-                       xcoef=refx["coef"], tol_floor=floor_tol(kappa))
+    if not kw.get("characteristic"):
+        # Taylor coefficients, compared through the polynomials they define on each cell
+        assert_poly_parity(rec["coef"].cpu().numpy(), ref["coef"], o, u0, f"{name} polynomials",
+                           xcoef=refx["coef"], tol_floor=floor_tol(kappa))
     L = w.rhs(u)
     torch.cuda.synchronize()
     Lo, alpha_o = o.rhs(u0)
@@ -314,6 +320,29 @@ def test_euler_quadrants(p, n_lo, n_hi, lanes):
     u0 = fields.cell_averages(mesh, fields.euler_quadrants(4101))
     _compare_all(mesh, u0, 4, None, f"euler14-p{p}-lanes{lanes}", p=p, n_lo=n_lo, n_hi=n_hi, flux="euler",
                  lanes=lanes)
+
+
+@pytest.mark.parametrize("p,n_lo,n_hi", [(3, 12, 20), (4, 20, 36), (5, 24, 30)])
+def test_euler_characteristic(p, n_lo, n_hi):
+    """2-D Euler reconstructed in characteristic fields per facet (4 x 3
+    fits per cell): facet values, ranks, rhs and steps against the oracle."""
+    mesh = jittered_square(14, 0.3, 3103)
+    u0 = fields.cell_averages(mesh, fields.euler_quadrants(4102))
+    _compare_all(mesh, u0, 4, None, f"euler14-char-p{p}", p=p, n_lo=n_lo, n_hi=n_hi, flux="euler",
+                 characteristic=True)
+
+
+def test_euler_characteristic_unit_weights_equal_components():
+    """With unit weights the fit is linear in the data, so the characteristic
+    path gives the component-wise facet values (GPU against GPU)."""
+    torch = _torch()
+    mesh = jittered_square(12, 0.3, 3104)
+    u0 = fields.cell_averages(mesh, fields.euler_quadrants(4103))
+    u = torch.tensor(u0.reshape(-1), device="cuda")
+    kw = dict(p=4, n_lo=20, n_hi=36, flux="euler", weight_mode=1)
+    fc = _gpu(mesh, **kw).reconstruct(u)["fval"].cpu().numpy()
+    fx = _gpu(mesh, characteristic=True, **kw).reconstruct(u)["fval"].cpu().numpy()
+    assert np.max(np.abs(fc - fx)) < 1e-11 * np.max(np.abs(fc))
 
 
 def _near_vacuum(x, gamma=1.4):
