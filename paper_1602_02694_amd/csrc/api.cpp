@@ -463,7 +463,7 @@ wlseno_status wlseno_reconstruct(wlseno_t ctx, const double *u_dev, double *coef
 {
     API_BEGIN(ctx)
     if (!u_dev) throw Error{WLSENO_EINVAL, "u_dev is NULL"};
-    if (coef_dev && ctx->have_build && ctx->dm.characteristic)
+    if (coef_dev && ctx->have_build && ctx->build.prm.characteristic)
         throw Error{WLSENO_EINVAL, "no coefficient output with characteristic fields (one fit per facet)"};
     need_device(ctx);
     check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");

@@ -1462,9 +1462,11 @@ __global__ void k_clear_alpha(unsigned long long *alpha, int nslot)
 // ------------------------------------------------------------ dispatch
 inline int blocks_for(int64_t work, int per_block) { return (int)((work + per_block - 1) / per_block); }
 
-// Lanes per cell of the characteristic-field variant (2-D Euler): 4 x 3 solves
-// per cell; enough lanes that the rows of a solve stay in registers.
-constexpr int char_lanes(int p) { return p == 2 ? 4 : (p == 5 ? 16 : 8); }
+// Lanes per cell of the characteristic-field variant (2-D Euler, 4 x 3 solves
+// per cell).  Measured on 179k cells: 4 lanes beat 8 and 16 by 1.5x and 2.8x
+// at p = 3 and 4 (less per-column work replicated across a cell's lanes);
+// p = 5 keeps 16, below which its rows spill.
+constexpr int char_lanes(int p) { return p == 5 ? 16 : 4; }
 
 template <int DIM, int P, int G, int R0, int R1, int R2>
 int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
@@ -1607,8 +1609,8 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
         if (dm.flux == kFluxEuler && dm.characteristic) {
             switch (dm.p) {
             case 2: return launch_k1<2, 2, char_lanes(2), 2, 2, 2>(dm, a, st);
-            case 3: return launch_k1<2, 3, char_lanes(3), 2, 2, 3>(dm, a, st);
-            case 4: return launch_k1<2, 4, char_lanes(4), 3, 4, 5>(dm, a, st);
+            case 3: return launch_k1<2, 3, char_lanes(3), 3, 4, 5>(dm, a, st);
+            case 4: return launch_k1<2, 4, char_lanes(4), 5, 7, 9>(dm, a, st);
             case 5: return launch_k1<2, 5, char_lanes(5), 2, 2, 3>(dm, a, st);
             }
             return (int)hipErrorInvalidValue;

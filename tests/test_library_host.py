@@ -121,6 +121,14 @@ def test_error_paths(lib):
     with pytest.raises(WLSENOError) as e:
         w3.stencil_build(p=3, n_lo=6, n_hi=10)
     assert e.value.status == 1 and "fewer than" in str(e.value)
+    # characteristic fields belong to the Euler system
+    with pytest.raises(WLSENOError) as e:
+        w.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers", characteristic=True)
+    assert e.value.status == 1 and "Euler" in str(e.value)
+    w.stencil_build(p=3, n_lo=12, n_hi=20, flux="euler", characteristic=True)
+    # and have no per-cell coefficients
+    rc = lib.wlseno_reconstruct(w._h, C.c_void_p(16), C.c_void_p(32), None, None)
+    assert rc == 1 and b"characteristic" in lib.wlseno_last_error(w._h)
     # device call on a host-only context
     w.stencil_build(p=3, n_lo=12, n_hi=20)
     rc = lib.wlseno_rhs(w._h, C.c_void_p(16), C.c_void_p(32))
