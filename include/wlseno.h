@@ -91,8 +91,11 @@ typedef struct {
     double gamma;        /* ratio of specific heats (Euler) */
     int32_t bc;          /* outside state at boundary facet points: 0 = the inside state
                             (transmissive); 1 = zero (a zero far field: with the upwind flux
-                            of linear advection, outflow as before and no inflow); 1 is
-                            EINVAL for the Euler system */
+                            of linear advection, outflow as before and no inflow; EINVAL for
+                            the Euler system); 2 = the constant far_state (inflow from a
+                            given free stream); 3 = Euler only: a slip wall, the inside state
+                            with the normal momentum reversed.  The Lax-Friedrichs alpha
+                            bound is taken over inside states only. */
     int32_t characteristic; /* Euler only (else EINVAL for 1): 0 = reconstruct the conserved
                             components; 1 = reconstruct characteristic fields per facet
                             (Sec. 5.1.4, 5.2.4): for each facet, the eigenvectors of the
@@ -102,6 +105,7 @@ typedef struct {
                             values back; 4 x (dim+1) solves per cell.  Coefficients are then
                             per facet: wlseno_reconstruct rejects a coefficient output
                             (EINVAL); its rank output is the smallest over the facets. */
+    double far_state[5]; /* bc = 2: outside state, n_vars components (Euler: rho, rho v, E) */
 } wlseno_params;
 
 typedef struct {

@@ -79,6 +79,7 @@ class _Problem(C.Structure):
         ("period", C.c_double), ("eps", C.c_double), ("alpha_w", C.c_double),
         ("rank_tol", C.c_double), ("h", C.c_double), ("gamma", C.c_double),
         ("adv", C.c_double * 3),
+        ("far", C.c_double * 5),
         ("exps", C.POINTER(C.c_int)),
         ("cv", C.POINTER(C.c_double)),
         ("cent", C.POINTER(C.c_double)),
@@ -166,7 +167,7 @@ class Oracle:
     def __init__(self, dim, verts, cells, periodic=False, *, p=3, n_lo=None, n_hi=None,
                  flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2, alpha_w=1.5,
                  rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None, extended=False, bc=0,
-                 characteristic=False):
+                 characteristic=False, far_state=None):
         self.extended = bool(extended)
         self.mesh = OracleMesh(dim, verts, cells, periodic, p=p)
         om = self.mesh
@@ -204,6 +205,10 @@ class Oracle:
         if characteristic and (flux != "euler" or dim > 2):
             raise ValueError("characteristic fields: the 1-D and 2-D Euler system only")
         P.characteristic = int(bool(characteristic))
+        if bc == 3 and flux != "euler":
+            raise ValueError("bc = 3 (slip wall): the Euler system only")
+        for v in range(5):
+            P.far[v] = float(far_state[v]) if far_state is not None and v < len(far_state) else 0.0
         P.period, P.eps, P.alpha_w, P.rank_tol = om.period, eps, alpha_w, rank_tol
         P.h, P.gamma = self.h, gamma
         for d in range(3):
@@ -276,6 +281,6 @@ def from_workload(wl, **kw) -> Oracle:
     s = dict(wl.settings)
     args = dict(p=s["p"], n_lo=s["n_lo"], n_hi=s["n_hi"], flux=s["flux"],
                 velocity=s.get("velocity", (1.0, 0.0, 0.0)), gamma=s.get("gamma", 1.4), bc=s.get("bc", 0),
-                characteristic=s.get("characteristic", False))
+                characteristic=s.get("characteristic", False), far_state=s.get("far_state"))
     args.update(kw)
     return Oracle(wl.mesh.dim, wl.mesh.verts, wl.mesh.cells, wl.mesh.periodic, **args)

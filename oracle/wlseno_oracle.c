@@ -52,10 +52,12 @@ enum { OR_ADVECTION = 0, OR_BURGERS = 1, OR_EULER = 2 };
 typedef struct {
     int dim, p, m, nvars, flux, weight_mode;
     int nc, nq, periodic;
-    int bc;               /* boundary facets: 0 outside state = inside state; 1 outside state = 0 */
+    int bc;               /* boundary facets: outside state 0 = inside state; 1 = zero; 2 = far[];
+                             3 = (Euler) inside state with the normal momentum reversed (slip wall) */
     int characteristic;   /* Euler: 0 reconstruct conserved components; 1 characteristic fields per facet */
     double period, eps, alpha_w, rank_tol, h, gamma;
     double adv[3];
+    double far[OR_MAXV];  /* bc = 2 outside state */
     const int *exps;      /* m x 3 exponents of the Taylor basis */
     const double *cv;     /* nc x (dim+1) x dim vertex coordinates of each cell */
     const double *cent;   /* nc x dim centroids */
@@ -758,7 +760,16 @@ static void divergence_cell(const or_problem *P, int i, const real *u, const rea
             if (j < 0) {
                 /* transmissive (u+ = u-), or a zero far field (u+ = 0): with the
                  * upwind flux of linear advection, outflow unchanged and no inflow */
-                for (int var = 0; var < V; ++var) up[var] = P->bc == 1 ? 0.0 : um[var];
+                for (int var = 0; var < V; ++var)
+                    up[var] = P->bc == 0 ? um[var] : (P->bc == 2 ? (real)P->far[var] : 0.0);
+                if (P->bc == 3) {
+                    /* slip wall: mirror image of the inside state */
+                    real mn = 0.0;
+                    for (int d = 0; d < D; ++d) mn += um[1 + d] * n[d];
+                    up[0] = um[0];
+                    for (int d = 0; d < D; ++d) up[1 + d] = um[1 + d] - 2.0 * mn * n[d];
+                    up[D + 1] = um[D + 1];
+                }
             } else if (P->flux == OR_EULER && P->characteristic) {
                 /* per-facet reconstructions: the neighbour's own value at the
                  * same point, found as its nearest facet point on a facet it

@@ -178,6 +178,7 @@ void upload_build(wlseno_ctx *c)
     dm.gamma = b.prm.gamma;
     dm.bc = b.prm.bc;
     dm.characteristic = b.prm.characteristic;
+    for (int v = 0; v < 5; ++v) dm.far[v] = b.prm.far_state[v];
     for (int d = 0; d < 3; ++d) dm.vel[d] = b.prm.velocity[d];
     dm.geo = upload(c, b.geo);
     dm.vrel = upload(c, b.vrel);
@@ -295,6 +296,7 @@ void wlseno_params_default(wlseno_params *out)
     out->gamma = 1.4;
     out->bc = 0;
     out->characteristic = 0;
+    for (int v = 0; v < 5; ++v) out->far_state[v] = 0.0;
 }
 
 wlseno_status wlseno_create(int device, wlseno_t *out)

@@ -95,6 +95,7 @@ struct DevMesh {
     int flux = 0, weight_mode = 0, max_stencil = 0;
     int bc = 0;   // boundary facets: 0 outside state = inside state, 1 outside state = 0
     int characteristic = 0;   // Euler: reconstruct characteristic fields per facet
+    double far[5] = {0, 0, 0, 0, 0};   // bc = 2: outside state
     int lanes = 0;   // lanes per cell in the reconstruction: 0 = automatic, 4 or 8
     int64_t nc = 0;
     int nbuckets = 0;

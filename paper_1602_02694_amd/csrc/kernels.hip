@@ -1256,6 +1256,7 @@ struct UArgs {
     double gamma;
     int mode;
     int bc;
+    double far[5];   // bc = 2: outside state
 };
 
 // Euler normal flux F(U).m for the area-scaled normal m (linear in m).
@@ -1380,14 +1381,31 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
 #pragma unroll
         for (int v = 0; v < V; ++v) facc[v] = 0.0;
         if (sb[lf] < 0) {
-            // boundary: outside state = inside state (transmissive) or zero
+            // boundary: outside state = inside state (transmissive), zero, a
+            // given far-field state, or (Euler) the inside state mirrored at a
+            // slip wall: normal momentum reversed
+            double mq = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) mq += m[lf][d] * m[lf][d];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 double uo[V], ux[V], fl[V];
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     uo[v] = own[v][lf][q];
-                    ux[v] = a.bc ? 0.0 : uo[v];
+                    ux[v] = a.bc == 0 ? uo[v] : (a.bc == 2 ? a.far[v] : 0.0);
+                }
+                if constexpr (V > 1) {
+                    if (a.bc == 3) {
+                        double mn = 0.0;
+#pragma unroll
+                        for (int d = 0; d < DIM; ++d) mn += uo[1 + d] * m[lf][d];
+                        const double s = 2.0 * mn / mq;
+                        ux[0] = uo[0];
+#pragma unroll
+                        for (int d = 0; d < DIM; ++d) ux[1 + d] = uo[1 + d] - s * m[lf][d];
+                        ux[DIM + 1] = uo[DIM + 1];
+                    }
                 }
                 lf_flux<DIM, FLUX, V>(uo, ux, m[lf], alpha, vel, a.gamma, fl);
 #pragma unroll
@@ -1669,6 +1687,7 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
     a.gamma = dm.gamma;
     a.mode = mode;
     a.bc = dm.bc;
+    for (int v = 0; v < 5; ++v) a.far[v] = dm.far[v];
     hipStream_t st = (hipStream_t)stream;
     if (dm.dim == 1) return launch_k23<1, 1>(dm, a, st);
     if (dm.dim == 2) {

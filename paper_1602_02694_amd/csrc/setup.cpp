@@ -441,7 +441,8 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
         throw Error{WLSENO_EUNSUPPORTED, "the Euler system is compiled for 2-D meshes"};
     if (prm.flux == WLSENO_FLUX_EULER && !(prm.gamma > 1.0)) throw inval("gamma > 1 required");
     if (prm.weight_mode != 0 && prm.weight_mode != 1) throw inval("weight_mode must be 0 or 1");
-    if (prm.bc != 0 && prm.bc != 1) throw inval("bc must be 0 or 1");
+    if (prm.bc < 0 || prm.bc > 3) throw inval("bc must be 0, 1, 2 or 3");
+    if (prm.bc == 3 && prm.flux != WLSENO_FLUX_EULER) throw inval("bc = 3 (slip wall) applies to the Euler system only");
     if (prm.bc == 1 && prm.flux == WLSENO_FLUX_EULER) throw inval("bc = 1 (zero outside state) is not valid for Euler");
     if (prm.characteristic != 0 && prm.characteristic != 1) throw inval("characteristic must be 0 or 1");
     if (prm.characteristic && prm.flux != WLSENO_FLUX_EULER)

@@ -345,6 +345,28 @@ def test_euler_characteristic_unit_weights_equal_components():
     assert np.max(np.abs(fc - fx)) < 1e-11 * np.max(np.abs(fc))
 
 
+FREE_STREAM = (1.0, 1.0, 1.0, 1.0 / 0.4 + 1.0)   # rho = p = 1, velocity (1, 1)
+
+
+@pytest.mark.parametrize("p,n_lo,n_hi,char", [(3, 12, 20, False), (5, 24, 30, True)])
+def test_far_field_vortex(p, n_lo, n_hi, char):
+    """Isentropic vortex on [0,10]^2 with the free stream as far-field state
+    at boundary facets (bc = 2)."""
+    mesh = jittered_square(13, 0.3, 3105, lo=0.0, hi=10.0)
+    u0 = fields.cell_averages(mesh, fields.isentropic_vortex(0.0))
+    _compare_all(mesh, u0, 4, None, f"vortex13-p{p}-char{int(char)}", p=p, n_lo=n_lo, n_hi=n_hi, flux="euler",
+                 characteristic=char, bc=2, far_state=FREE_STREAM)
+
+
+@pytest.mark.parametrize("char", [False, True])
+def test_slip_wall_sod(char):
+    """Sod's shock tube along x in the unit square with slip walls (bc = 3)."""
+    mesh = jittered_square(14, 0.3, 3106)
+    u0 = fields.cell_averages(mesh, fields.sod_x())
+    _compare_all(mesh, u0, 4, None, f"sod14-char{int(char)}", p=3, n_lo=12, n_hi=20, flux="euler",
+                 characteristic=char, bc=3)
+
+
 def _near_vacuum(x, gamma=1.4):
     """Dense disc in a near-vacuum, opposing jets, a pressure jump: the
     reconstruction undershoots density or pressure at some facet points."""

@@ -129,6 +129,14 @@ def test_error_paths(lib):
     # and have no per-cell coefficients
     rc = lib.wlseno_reconstruct(w._h, C.c_void_p(16), C.c_void_p(32), None, None)
     assert rc == 1 and b"characteristic" in lib.wlseno_last_error(w._h)
+    # boundary options: 0..3, the slip wall for the Euler system only
+    with pytest.raises(WLSENOError):
+        w.stencil_build(p=3, n_lo=12, n_hi=20, bc=4)
+    with pytest.raises(WLSENOError) as e:
+        w.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers", bc=3)
+    assert "slip wall" in str(e.value)
+    w.stencil_build(p=3, n_lo=12, n_hi=20, flux="euler", bc=3)
+    w.stencil_build(p=3, n_lo=12, n_hi=20, flux="euler", bc=2, far_state=(1.0, 0.0, 0.0, 2.5))
     # device call on a host-only context
     w.stencil_build(p=3, n_lo=12, n_hi=20)
     rc = lib.wlseno_rhs(w._h, C.c_void_p(16), C.c_void_p(32))

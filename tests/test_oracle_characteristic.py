@@ -179,3 +179,32 @@ def test_characteristic_uniform_state_is_steady():
     U = np.array([0.8, 0.8 * 0.3, 0.8 * -0.2, 1.0 / 0.4 + 0.5 * 0.8 * 0.13])
     L, _ = o.rhs(np.repeat(U[:, None], o.nc, axis=1))
     assert np.max(np.abs(L)) < 1e-10
+
+
+def test_exact_riemann_solver():
+    """The exact Riemann solution used to validate shock tubes: Rankine-
+    Hugoniot across its shock, isentropic fan, and a symmetric problem with
+    u* = 0."""
+    import riemann
+
+    g = GAMMA
+    L, R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    ps, us = riemann.star_state(L, R, g)
+    # right shock: mass and momentum flux continuous in the shock frame
+    w = riemann.sample(L, R, np.array([us + 1e-9, 5.0]), g)
+    r1, u1, p1 = w[:, 0]
+    r2, u2, p2 = w[:, 1]
+    s = (r1 * u1 - r2 * u2) / (r1 - r2)
+    assert (r1 * (u1 - s) - r2 * (u2 - s)) == pytest.approx(0.0, abs=1e-12)
+    assert (r1 * (u1 - s) ** 2 + p1) == pytest.approx(r2 * (u2 - s) ** 2 + p2, rel=1e-12)
+    E1 = p1 / (g - 1) + 0.5 * r1 * u1 ** 2
+    E2 = p2 / (g - 1) + 0.5 * r2 * u2 ** 2
+    assert ((E1 + p1) * u1 - s * E1) == pytest.approx((E2 + p2) * u2 - s * E2, rel=1e-10)
+    # left rarefaction: p / rho^gamma constant and u + 2c/(gamma-1) constant through the fan
+    xi = np.linspace(-1.18, -0.08, 7)
+    r, u, p = riemann.sample(L, R, xi, g)
+    assert np.allclose(p / r ** g, 1.0, rtol=1e-12)
+    assert np.allclose(u + 2 * np.sqrt(g * p / r) / (g - 1), 2 * np.sqrt(g) / (g - 1), rtol=1e-12)
+    # symmetric collision
+    ps2, us2 = riemann.star_state((1.0, 0.5, 1.0), (1.0, -0.5, 1.0), g)
+    assert us2 == pytest.approx(0.0, abs=1e-14) and ps2 > 1.0

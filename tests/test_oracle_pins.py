@@ -489,3 +489,31 @@ def test_weights_formula_values():
     for r, j in enumerate(rows):
         want = 1.5 / bi if j == i else 1.0 / beta[j]
         assert w[r] == pytest.approx(want, rel=1e-14)
+
+
+def test_far_field_and_slip_wall_boundaries():
+    """bc = 2 with the free stream as far field keeps a uniform state steady;
+    bc = 2 with a zero far field is bc = 1; a slip wall (bc = 3) passes no
+    mass or energy, so both totals are conserved for any state."""
+    import oracle
+
+    mesh = jittered_square(9, 0.3, 43)
+    kw = dict(p=3, n_lo=12, n_hi=20)
+    U = np.array([0.9, 0.9 * 0.4, 0.9 * -0.3, 1.2 / 0.4 + 0.5 * 0.9 * 0.25])
+    o = oracle.Oracle(2, mesh.verts, mesh.cells, flux="euler", bc=2, far_state=U, **kw)
+    L, _ = o.rhs(np.repeat(U[:, None], o.nc, axis=1))
+    assert np.max(np.abs(L)) < 1e-10
+    u = fields.cell_averages(mesh, fields.gaussian_sum(43, 8, 2))
+    a1 = oracle.Oracle(2, mesh.verts, mesh.cells, flux="advection", velocity=(1.0, 0.5, 0), bc=1, **kw).rhs(u)[0]
+    a2 = oracle.Oracle(2, mesh.verts, mesh.cells, flux="advection", velocity=(1.0, 0.5, 0), bc=2,
+                       far_state=(0.0,), **kw).rhs(u)[0]
+    assert np.array_equal(a1, a2)
+    w = oracle.Oracle(2, mesh.verts, mesh.cells, flux="euler", bc=3, **kw)
+    ue = fields.cell_averages(mesh, fields.euler_quadrants(44))
+    Lw, _ = w.rhs(ue)
+    vol = w.mesh.vol
+    scale = np.max(np.abs(Lw), axis=1) * vol.sum()
+    assert abs(np.sum(vol * Lw[0])) < 1e-12 * scale[0]
+    assert abs(np.sum(vol * Lw[3])) < 1e-12 * scale[3]
+    # momentum is not conserved: the walls push back with the pressure
+    assert abs(np.sum(vol * Lw[1])) > 1e-6 * scale[1]

@@ -194,3 +194,45 @@ def polynomial_field(seed: int, dim: int, degree: int, scale: float = 1.0):
     fn.exps = exps
     fn.coef = coef
     return fn
+
+
+def isentropic_vortex(t: float = 0.0, beta: float = 5.0, gamma: float = 1.4, centre=(5.0, 5.0), mean=(1.0, 1.0)):
+    """Isentropic vortex in a uniform stream (conserved variables), the exact
+    solution of the 2-D Euler equations at time ``t`` (Sec. 5.2.3 of the WLS-ENO
+    paper: rho, p = 1 at infinity, mean flow (1, 1), strength 5, centred in
+    [0,10]^2 at t = 0).  With x' = x - centre - mean t and r^2 = |x'|^2:
+    velocity perturbation beta/(2 pi) exp((1 - r^2)/2) (-y', x'), temperature
+    T = 1 - (gamma - 1) beta^2 / (8 gamma pi^2) exp(1 - r^2), and no entropy
+    perturbation: rho = T^(1/(gamma-1)), p = rho T."""
+    cx = centre[0] + mean[0] * t
+    cy = centre[1] + mean[1] * t
+
+    def fn(x):
+        xb = x[:, 0] - cx
+        yb = x[:, 1] - cy
+        r2 = xb * xb + yb * yb
+        amp = beta / (2.0 * np.pi) * np.exp(0.5 * (1.0 - r2))
+        u = mean[0] - amp * yb
+        v = mean[1] + amp * xb
+        T = 1.0 - (gamma - 1.0) * beta * beta / (8.0 * gamma * np.pi ** 2) * np.exp(1.0 - r2)
+        rho = T ** (1.0 / (gamma - 1.0))
+        p = rho * T
+        E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+        return np.stack([rho, rho * u, rho * v, E], axis=1)
+
+    return fn
+
+
+def sod_x(x0: float = 0.5, gamma: float = 1.4):
+    """Sod's shock-tube states (Sec. 5.1.4 of the WLS-ENO paper) along x, at
+    rest: (rho, p) = (1, 1) for x < x0 and (0.125, 0.1) beyond (conserved
+    variables of the 2-D system)."""
+
+    def fn(x):
+        left = x[:, 0] < x0
+        rho = np.where(left, 1.0, 0.125)
+        p = np.where(left, 1.0, 0.1)
+        z = np.zeros_like(rho)
+        return np.stack([rho, z, z, p / (gamma - 1.0)], axis=1)
+
+    return fn
