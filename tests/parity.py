@@ -50,6 +50,19 @@ def rel_errors(g, o, floor=FLOOR, scale=None):
     return np.abs(g - o) / sc
 
 
+def momentum_scale(o, dim, floor=FLOOR):
+    """Euler arrays (V, ...): a floor for the momentum components at 1% of the
+    momentum vector's largest component, the same for every component (a
+    rotation of the frame mixes them; a momentum component that vanishes in
+    the data, like the transverse momentum of a shock tube, is measured
+    against the flow's momentum, not against its own noise).  Zero for the
+    other components, which keep their own per-component floor."""
+    o = np.asarray(o, dtype=np.float64)
+    sc = np.zeros_like(o)
+    sc[1:1 + dim] = floor * np.max(np.abs(o[1:1 + dim]))
+    return sc
+
+
 def flux_scale(o, fval, alpha=0.0):
     """Per-cell magnitude of the flux sum that forms the right-hand side:
     S_i = (1/|tau_i|) sum_f |f| sum_q w_q |F(u_q).n_f| from the oracle's own

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from parity import (assert_parity, assert_poly_parity, cell_conditions, cell_noise, char_cell_conditions, flux_scale,
-                    floor_tol, neighbourhood_max)
+                    floor_tol, momentum_scale, neighbourhood_max)
 from workloads import configs, periodic_line, uniform_periodic_line, jittered_square, fields
 
 pytestmark = pytest.mark.gpu
@@ -78,8 +78,10 @@ def _compare_all(mesh, u0, steps, dt, name, **kw):
     ref = o.reconstruct(u0)
     refx = ox.reconstruct(u0)
     assert np.array_equal(rec["rank"].cpu().numpy(), ref["rank"]), "numerical ranks differ"
-    fv_floor = floor_tol(kappa[:, :, None, None], cell_noise(ref["fval"], refx["fval"], cell_axes=2))
-    assert_parity(rec["fval"].cpu().numpy(), ref["fval"], f"{name} facet values", tol_floor=fv_floor)
+    euler = kw.get("flux") == "euler"
+    fsc = momentum_scale(ref["fval"], mesh.dim) if euler else None
+    fv_floor = floor_tol(kappa[:, :, None, None], cell_noise(ref["fval"], refx["fval"], scale=fsc, cell_axes=2))
+    assert_parity(rec["fval"].cpu().numpy(), ref["fval"], f"{name} facet values", scale=fsc, tol_floor=fv_floor)
     if not kw.get("characteristic"):
         # Taylor coefficients, compared through the polynomials they define on each cell
         assert_poly_parity(rec["coef"].cpu().numpy(), ref["coef"], o, u0, f"{name} polynomials",
@@ -101,8 +103,9 @@ def _compare_all(mesh, u0, steps, dt, name, **kw):
         torch.cuda.synchronize()
         uo = o.step(u0, dt, steps).reshape(V, -1)
         ux = ox.step(u0, dt, steps).reshape(V, -1)
-        assert_parity(u.cpu().numpy().reshape(V, -1), uo, f"{name} {steps} steps",
-                      tol_floor=floor_tol(kappa_nb.reshape(V, -1), cell_noise(uo, ux)))
+        usc = momentum_scale(uo, mesh.dim) if euler else None
+        assert_parity(u.cpu().numpy().reshape(V, -1), uo, f"{name} {steps} steps", scale=usc,
+                      tol_floor=floor_tol(kappa_nb.reshape(V, -1), cell_noise(uo, ux, scale=usc)))
     return w, o
 
 
