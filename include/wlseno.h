@@ -106,6 +106,17 @@ typedef struct {
                             per facet: wlseno_reconstruct rejects a coefficient output
                             (EINVAL); its rank output is the smallest over the facets. */
     double far_state[5]; /* bc = 2: outside state, n_vars components (Euler: rho, rho v, E) */
+    int32_t balance;     /* 1: balanced-stencil refit (end of Sec. 3.2) for advection and
+                            Burgers at p = 3 in 2-D and 3-D (else EUNSUPPORTED; EINVAL for
+                            the Euler system).  A cell with a facet value outside the range
+                            of its stencil's averages (beyond a band of 1e-10 of that range)
+                            is fitted once more on a stencil balanced across the line/plane
+                            through its centroid orthogonal to the first fit's gradient:
+                            from its enlarged stencil (the same ring rule with 2 n_lo, 2 n_hi;
+                            2 n_hi <= 128), the centroid plus the nearest ceil((n-1)/2)
+                            cells on the gradient's side and floor((n-1)/2) on the other (a
+                            short side leaves its share to the other), n its own stencil
+                            size.  The lanes setting is then automatic. */
 } wlseno_params;
 
 typedef struct {

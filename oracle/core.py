@@ -57,10 +57,12 @@ def lib(extended: bool = False):
         _lib.or_char_basis.argtypes = [C.c_int, C.c_double, dp, dp, dp, dp]
         _lib.or_euler_normal_flux.argtypes = [C.c_int, C.c_double, dp, dp, dp]
         pp = C.POINTER(_Problem)
+        _lib.or_balanced_rows.argtypes = [pp, C.c_int, dp, C.c_int, ip]
         _lib.or_cell_matrix.argtypes = [pp, C.c_int, dp]
         _lib.or_cell_weights.argtypes = [pp, C.c_int, dp, dp]
-        _lib.or_reconstruct.argtypes = [pp, dp, dp, dp, ip, C.POINTER(C.c_ubyte)]
-        _lib.or_reconstruct_cells.argtypes = [pp, dp, C.c_int, ip, dp, dp, ip, C.POINTER(C.c_ubyte)]
+        ub = C.POINTER(C.c_ubyte)
+        _lib.or_reconstruct.argtypes = [pp, dp, dp, dp, ip, ub, ub]
+        _lib.or_reconstruct_cells.argtypes = [pp, dp, C.c_int, ip, dp, dp, ip, ub, ub]
         _lib.or_rhs.argtypes = [pp, dp, dp, dp]
         _lib.or_rk3.argtypes = [pp, dp, C.c_double, C.c_int]
         _lib.or_num_threads.argtypes = []
@@ -91,6 +93,9 @@ class _Problem(C.Structure):
         ("qw", C.POINTER(C.c_double)),
         ("normal", C.POINTER(C.c_double)),
         ("area", C.POINTER(C.c_double)),
+        ("pool_ptr", C.POINTER(C.c_int)),
+        ("pool_col", C.POINTER(C.c_int)),
+        ("balance", C.c_int),
     ]
 
 
@@ -167,7 +172,7 @@ class Oracle:
     def __init__(self, dim, verts, cells, periodic=False, *, p=3, n_lo=None, n_hi=None,
                  flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2, alpha_w=1.5,
                  rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None, extended=False, bc=0,
-                 characteristic=False, far_state=None):
+                 characteristic=False, far_state=None, balance=False):
         self.extended = bool(extended)
         self.mesh = OracleMesh(dim, verts, cells, periodic, p=p)
         om = self.mesh
@@ -219,6 +224,15 @@ class Oracle:
         P.row_ptr, P.col = _ip(self.row_ptr), _ip(self.col)
         P.qx, P.qw = _dp(k["qx"]), _dp(k["qw"])
         P.normal, P.area = _dp(k["normal"]), _dp(k["area"])
+        if balance:
+            if flux == "euler":
+                raise ValueError("balanced stencils: scalar fluxes only")
+            # enlarged stencils: the same rule with twice the sizes
+            pool = om.stencils(2 * self.n_lo, 2 * self.n_hi)
+            self.pool_ptr = np.ascontiguousarray(pool[0], dtype=np.int32)
+            self.pool_col = np.ascontiguousarray(pool[1], dtype=np.int32)
+            P.pool_ptr, P.pool_col = _ip(self.pool_ptr), _ip(self.pool_col)
+        P.balance = int(bool(balance))
         self._P = P
         self._lib = lib(self.extended)
         self.flux = flux
@@ -226,6 +240,13 @@ class Oracle:
         self.nf = dim + 1
 
     # -------------------------------------------------------------- pieces
+    def balanced_rows(self, i, grad, n):
+        """Balanced stencil of cell i for gradient grad and size n (needs balance=True)."""
+        out = np.zeros(2 * self.n_hi + 1, dtype=np.int32)
+        g = np.ascontiguousarray(grad, dtype=np.float64)
+        k = self._lib.or_balanced_rows(C.byref(self._P), int(i), _dp(g), int(n), _ip(out))
+        return out[:k].copy()
+
     def stencil_of(self, i):
         return self.col[self.row_ptr[i]:self.row_ptr[i + 1]]
 
@@ -253,14 +274,16 @@ class Oracle:
         fval = np.zeros((self.nvars, self.nc, self.nf, self.nq))
         rank = np.zeros((self.nvars, self.nc), dtype=np.int32)
         fb = np.zeros(self.nc, dtype=np.uint8)
+        rb = np.zeros(self.nc, dtype=np.uint8)
         fbp = fb.ctypes.data_as(C.POINTER(C.c_ubyte))
+        rbp = rb.ctypes.data_as(C.POINTER(C.c_ubyte))
         if cells is None:
-            self._lib.or_reconstruct(C.byref(self._P), _dp(u), _dp(coef), _dp(fval), _ip(rank), fbp)
+            self._lib.or_reconstruct(C.byref(self._P), _dp(u), _dp(coef), _dp(fval), _ip(rank), fbp, rbp)
         else:
             cells = np.ascontiguousarray(cells, dtype=np.int32)
             self._lib.or_reconstruct_cells(C.byref(self._P), _dp(u), len(cells), _ip(cells),
-                                       _dp(coef), _dp(fval), _ip(rank), fbp)
-        return dict(coef=coef, fval=fval, rank=rank, fallback=fb)
+                                       _dp(coef), _dp(fval), _ip(rank), fbp, rbp)
+        return dict(coef=coef, fval=fval, rank=rank, fallback=fb, rebalanced=rb)
 
     def rhs(self, u):
         u = self._u(u)
@@ -281,6 +304,7 @@ def from_workload(wl, **kw) -> Oracle:
     s = dict(wl.settings)
     args = dict(p=s["p"], n_lo=s["n_lo"], n_hi=s["n_hi"], flux=s["flux"],
                 velocity=s.get("velocity", (1.0, 0.0, 0.0)), gamma=s.get("gamma", 1.4), bc=s.get("bc", 0),
-                characteristic=s.get("characteristic", False), far_state=s.get("far_state"))
+                characteristic=s.get("characteristic", False), far_state=s.get("far_state"),
+                balance=s.get("balance", False))
     args.update(kw)
     return Oracle(wl.mesh.dim, wl.mesh.verts, wl.mesh.cells, wl.mesh.periodic, **args)

@@ -69,6 +69,9 @@ typedef struct {
     const double *qw;     /* nq weights, summing to 1 */
     const double *normal; /* nc x (dim+1) x dim unit outward normals */
     const double *area;   /* nc x (dim+1) facet measures */
+    const int *pool_ptr;  /* balance: enlarged stencils (CSR, centre first, canonical order) */
+    const int *pool_col;
+    int balance;          /* scalar fluxes: refit out-of-range cells on a balanced stencil */
 } or_problem;
 
 /* Threads the per-cell loops use (1 without OpenMP). */
@@ -199,16 +202,21 @@ static void image_vertices(const or_problem *P, int i, int j, real *out)
 }
 
 /* A (n x m): averages over each stencil cell of the Taylor monomials about x_i. */
-static void cell_matrix(const or_problem *P, int i, real *A)
+/* Rows of the cell-average system for stencil cells rows[0..n). */
+static void cell_matrix_rows(const or_problem *P, int i, const int *rows, int n, real *A)
 {
-    int n = stencil_size(P, i), m = P->m;
-    const int *rows = P->col + P->row_ptr[i];
+    int m = P->m;
     real verts[(OR_MAXDIM + 1) * OR_MAXDIM], ci[OR_MAXDIM];
     for (int d = 0; d < P->dim; ++d) ci[d] = P->cent[(size_t)i * P->dim + d];
     for (int r = 0; r < n; ++r) {
         image_vertices(P, i, rows[r], verts);
         for (int k = 0; k < m; ++k) A[r * m + k] = simplex_avg(P->dim, verts, ci, P->exps + 3 * k);
     }
+}
+
+static void cell_matrix(const or_problem *P, int i, real *A)
+{
+    cell_matrix_rows(P, i, P->col + P->row_ptr[i], stencil_size(P, i), A);
 }
 
 void or_cell_matrix(const or_problem *P, int i, double *A)
@@ -221,10 +229,9 @@ void or_cell_matrix(const or_problem *P, int i, double *A)
 /* Row weights omega for cell i from the values of one scalar field: ui at the
  * centre, us[r] at stencil row r, unb[lf] at the facet neighbour across lf
  * (read only where that neighbour exists). */
-static void weights_from_values(const or_problem *P, int i, real ui, const real *us, const real *unb, real *w)
+static void weights_from_values(const or_problem *P, int i, int n, const int *rows, real ui, const real *us,
+                                const real *unb, real *w)
 {
-    int n = stencil_size(P, i);
-    const int *rows = P->col + P->row_ptr[i];
     if (P->weight_mode == 1) {
         for (int r = 0; r < n; ++r) w[r] = 1.0;
         return;
@@ -261,7 +268,7 @@ static void cell_weights(const or_problem *P, int i, const real *u, real *w)
         int j = P->nbr[(size_t)i * (P->dim + 1) + lf];
         unb[lf] = j >= 0 ? u[j] : 0.0;
     }
-    weights_from_values(P, i, u[i], us, unb, w);
+    weights_from_values(P, i, n, rows, u[i], us, unb, w);
 }
 
 void or_cell_weights(const or_problem *P, int i, const double *u, double *w)
@@ -556,9 +563,54 @@ static void load_normal(const or_problem *P, int i, int lf, real *n)
     for (int d = 0; d < P->dim; ++d) n[d] = P->normal[((size_t)i * faces_per_cell(P) + lf) * P->dim + d];
 }
 
+/* Balanced stencil (end of Sec. 3.2): from the enlarged stencil of cell i
+ * (centre first, then by distance), keep the centre and the nearest cells
+ * on either side of the line/plane through the centroid orthogonal to the
+ * gradient g, ceil((n-1)/2) with g.(x_j - x_i) > 0 and floor((n-1)/2) with
+ * g.(x_j - x_i) <= 0; a side with too few cells leaves its share to the
+ * other.  Returns the number of rows written to out (centre first, then in
+ * the enlarged stencil's order). */
+static int balanced_rows(const or_problem *P, int i, const real *g, int n, int *out)
+{
+    const int *pool = P->pool_col + P->pool_ptr[i];
+    int np = P->pool_ptr[i + 1] - P->pool_ptr[i], D = P->dim;
+    unsigned char plus[2 * OR_MAXN];
+    int cp = 0, cm = 0;
+    for (int r = 1; r < np; ++r) {
+        int j = pool[r];
+        real s = 0.0;
+        for (int d = 0; d < D; ++d) {
+            real dd = (real)P->cent[(size_t)j * D + d] - (real)P->cent[(size_t)i * D + d];
+            if (d == 0) dd = wrap(P, dd);
+            s += g[d] * dd;
+        }
+        plus[r] = s > 0.0;
+        if (plus[r]) ++cp; else ++cm;
+    }
+    int qp = n / 2, qm = (n - 1) / 2;
+    if (cp < qp) { qm += qp - cp; qp = cp; }
+    if (cm < qm) { qp += qm - cm; qm = cm; }
+    int k = 0, tp = 0, tm = 0;
+    out[k++] = i;
+    for (int r = 1; r < np; ++r) {
+        if (plus[r] ? tp < qp : tm < qm) {
+            if (plus[r]) ++tp; else ++tm;
+            out[k++] = pool[r];
+        }
+    }
+    return k;
+}
+
+int or_balanced_rows(const or_problem *P, int i, const double *g, int n, int *out)
+{
+    real gr[OR_MAXDIM];
+    for (int d = 0; d < P->dim; ++d) gr[d] = g[d];
+    return balanced_rows(P, i, gr, n, out);
+}
+
 /* Reconstruct one cell for every variable: coefficients, own facet values. */
 static void reconstruct_cell(const or_problem *P, int i, const real *u, real *coef, real *fval,
-                             int *rank, unsigned char *fallback)
+                             int *rank, unsigned char *fallback, unsigned char *rebal)
 {
     int n = stencil_size(P, i), m = P->m, V = P->nvars, F = faces_per_cell(P), D = P->dim;
     const int *rows = P->col + P->row_ptr[i];
@@ -603,7 +655,7 @@ static void reconstruct_cell(const or_problem *P, int i, const real *u, real *co
                         for (int c = 0; c < V; ++c) t += Lc[k * V + c] * u[(size_t)c * P->nc + j];
                     unb[f2] = t;
                 }
-                weights_from_values(P, i, ui, b, unb, w);
+                weights_from_values(P, i, n, rows, ui, b, unb, w);
                 int rk = qrcp_solve(n, m, A, w, b, P->rank_tol, vk, NULL, NULL);
                 if (rank && rk < rank[(size_t)k * P->nc + i]) rank[(size_t)k * P->nc + i] = rk;
                 for (int q = 0; q < P->nq; ++q) {
@@ -636,6 +688,45 @@ static void reconstruct_cell(const or_problem *P, int i, const real *u, real *co
                 for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)i * D + d];
                 for (int var = 0; var < V; ++var) vals[var][lf][q] = eval_taylor(D, m, P->exps, v[var], dx);
             }
+        if (P->balance && V == 1) {
+            /* out of the stencil's range (beyond a rounding band)?  Then fit
+             * again on a balanced stencil (end of Sec. 3.2), once. */
+            real mn = u[rows[0]], mx = u[rows[0]];
+            for (int r = 1; r < n; ++r) {
+                real t = u[rows[r]];
+                if (t < mn) mn = t;
+                if (t > mx) mx = t;
+            }
+            real band = 1e-10 * (mx - mn) + 1e-14 * (fabs(mx) > fabs(mn) ? fabs(mx) : fabs(mn));
+            int out = 0;
+            for (int lf = 0; lf < F; ++lf)
+                for (int q = 0; q < P->nq; ++q)
+                    if (vals[0][lf][q] > mx + band || vals[0][lf][q] < mn - band) out = 1;
+            if (out) {
+                real g[OR_MAXDIM];
+                for (int d = 0; d < D; ++d) g[d] = v[0][1 + d];
+                int rows2[OR_MAXN];
+                int n2 = balanced_rows(P, i, g, n, rows2);
+                real A2[OR_MAXN * OR_MAXM], us[OR_MAXN], unb[OR_MAXF];
+                cell_matrix_rows(P, i, rows2, n2, A2);
+                for (int r = 0; r < n2; ++r) us[r] = u[rows2[r]];
+                for (int f2 = 0; f2 < F; ++f2) {
+                    int j = P->nbr[(size_t)i * F + f2];
+                    unb[f2] = j >= 0 ? u[j] : 0.0;
+                }
+                weights_from_values(P, i, n2, rows2, u[i], us, unb, w);
+                int rk = qrcp_solve(n2, m, A2, w, us, P->rank_tol, v[0], NULL, NULL);
+                if (rank) rank[i] = rk;
+                for (int lf = 0; lf < F; ++lf)
+                    for (int q = 0; q < P->nq; ++q) {
+                        const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
+                        real dx[OR_MAXDIM];
+                        for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)i * D + d];
+                        vals[0][lf][q] = eval_taylor(D, m, P->exps, v[0], dx);
+                    }
+                if (rebal) rebal[i] = 1;
+            }
+        }
     }
     /* Euler: keep the cell averages if any facet state is not physical */
     int fb = 0;
@@ -683,7 +774,7 @@ static void to_double(const real *x, double *out, size_t n)
  * indexed by cell id.  u: nvars x nc.  coef: nvars x nc x m.  fval: nvars x nc
  * x (dim+1) x nq. */
 static int reconstruct_api(const or_problem *P, const double *u, int ncells, const int *cells, double *coef,
-                           double *fval, int *rank, unsigned char *fallback)
+                           double *fval, int *rank, unsigned char *fallback, unsigned char *rebal)
 {
     size_t nu = (size_t)P->nvars * P->nc;
     size_t ncoef = nu * P->m, nfv = nu * faces_per_cell(P) * P->nq;
@@ -693,7 +784,7 @@ static int reconstruct_api(const or_problem *P, const double *u, int ncells, con
     if (!ur || !cr || !fr) { free(ur); free(cr); free(fr); return -1; }
     int count = cells ? ncells : P->nc;
 #pragma omp parallel for schedule(static)
-    for (int t = 0; t < count; ++t) reconstruct_cell(P, cells ? cells[t] : t, ur, cr, fr, rank, fallback);
+    for (int t = 0; t < count; ++t) reconstruct_cell(P, cells ? cells[t] : t, ur, cr, fr, rank, fallback, rebal);
     if (coef) to_double(cr, coef, ncoef);
     if (fval) to_double(fr, fval, nfv);
     free(ur); free(cr); free(fr);
@@ -701,15 +792,15 @@ static int reconstruct_api(const or_problem *P, const double *u, int ncells, con
 }
 
 int or_reconstruct(const or_problem *P, const double *u, double *coef, double *fval, int *rank,
-                   unsigned char *fallback)
+                   unsigned char *fallback, unsigned char *rebal)
 {
-    return reconstruct_api(P, u, 0, NULL, coef, fval, rank, fallback);
+    return reconstruct_api(P, u, 0, NULL, coef, fval, rank, fallback, rebal);
 }
 
 int or_reconstruct_cells(const or_problem *P, const double *u, int ncells, const int *cells,
-                         double *coef, double *fval, int *rank, unsigned char *fallback)
+                         double *coef, double *fval, int *rank, unsigned char *fallback, unsigned char *rebal)
 {
-    return reconstruct_api(P, u, ncells, cells, coef, fval, rank, fallback);
+    return reconstruct_api(P, u, ncells, cells, coef, fval, rank, fallback, rebal);
 }
 
 /* Lax-Friedrichs numerical flux for all components. */
@@ -823,7 +914,7 @@ static int rhs_real(const or_problem *P, const real *u, real *dudt, real *alpha_
     unsigned char *fb = (unsigned char *)calloc((size_t)P->nc, 1);
     if (!coef || !fval || !fb) { free(coef); free(fval); free(fb); return -1; }
 #pragma omp parallel for schedule(static)
-    for (int i = 0; i < P->nc; ++i) reconstruct_cell(P, i, u, coef, fval, NULL, fb);
+    for (int i = 0; i < P->nc; ++i) reconstruct_cell(P, i, u, coef, fval, NULL, fb, NULL);
     real alpha = 0.0;
     if (P->flux != OR_ADVECTION) alpha = global_alpha(P, fval);
 #pragma omp parallel for schedule(static)

@@ -180,6 +180,15 @@ void upload_build(wlseno_ctx *c)
     dm.characteristic = b.prm.characteristic;
     for (int v = 0; v < 5; ++v) dm.far[v] = b.prm.far_state[v];
     for (int d = 0; d < 3; ++d) dm.vel[d] = b.prm.velocity[d];
+    if (b.prm.balance) {
+        dm.balance = 1;
+        dm.pool_cap = b.pool_cap;
+        dm.pool = upload(c, b.pool);
+        dm.bal_list = (int32_t *)dev_alloc(c, m.nc * sizeof(int32_t));
+        dm.bal_grad = (double *)dev_alloc(c, m.nc * m.dim * sizeof(double));
+        dm.bal_count = (unsigned long long *)dev_alloc(c, 32 * sizeof(unsigned long long));
+        check_hip(hipMemset(dm.bal_count, 0, 32 * sizeof(unsigned long long)), "hipMemset");
+    }
     dm.geo = upload(c, b.geo);
     dm.vrel = upload(c, b.vrel);
     dm.normal = upload(c, b.normal);
@@ -296,6 +305,7 @@ void wlseno_params_default(wlseno_params *out)
     out->gamma = 1.4;
     out->bc = 0;
     out->characteristic = 0;
+    out->balance = 0;
     for (int v = 0; v < 5; ++v) out->far_state[v] = 0.0;
 }
 

@@ -83,6 +83,10 @@ struct Build {
     std::vector<double> area;       // [F][nc] facet measures (host only)
     std::vector<double> rvol;       // nc: 1/|tau|
     std::vector<int32_t> mid;       // batches: mesh of each device cell (empty for one mesh)
+    // balanced-stencil refit: enlarged stencils, device order and ids, centre
+    // first, pool_cap entries per cell (-1 padding)
+    std::vector<int32_t> pool;
+    int pool_cap = 0;
 };
 
 void mesh_setup(HostMesh &mesh, int dim, int64_t nv, const double *xyz, int64_t nc,
@@ -96,6 +100,13 @@ struct DevMesh {
     int bc = 0;   // boundary facets: 0 outside state = inside state, 1 outside state = 0
     int characteristic = 0;   // Euler: reconstruct characteristic fields per facet
     double far[5] = {0, 0, 0, 0, 0};   // bc = 2: outside state
+    // balanced-stencil refit: enlarged stencils, the refit list of each stage
+    // parity (count at bal_count[parity * 16]) and the listed cells' gradients
+    int balance = 0, pool_cap = 0;
+    const int32_t *pool = nullptr;
+    int32_t *bal_list = nullptr;
+    unsigned long long *bal_count = nullptr;
+    double *bal_grad = nullptr;
     int lanes = 0;   // lanes per cell in the reconstruction: 0 = automatic, 4 or 8
     int64_t nc = 0;
     int nbuckets = 0;

@@ -127,6 +127,48 @@ __device__ __forceinline__ double group_sum(double x)
     return x;
 }
 
+// Maximum / minimum over a group of G lanes (same exchange pattern as group_sum).
+template <int G>
+__device__ __forceinline__ double group_max(double x)
+{
+    x = fmax(x, dpp_d<0xB1>(x));
+    if constexpr (G >= 4) x = fmax(x, dpp_d<0x4E>(x));
+    if constexpr (G >= 8) x = fmax(x, dpp_d<0x141>(x));
+    if constexpr (G >= 16) x = fmax(x, dpp_d<0x140>(x));
+    return x;
+}
+
+template <int G>
+__device__ __forceinline__ double group_min(double x)
+{
+    x = fmin(x, dpp_d<0xB1>(x));
+    if constexpr (G >= 4) x = fmin(x, dpp_d<0x4E>(x));
+    if constexpr (G >= 8) x = fmin(x, dpp_d<0x141>(x));
+    if constexpr (G >= 16) x = fmin(x, dpp_d<0x140>(x));
+    return x;
+}
+
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long x)
+{
+    int lo = (int)(unsigned)(x & 0xffffffffull);
+    int hi = (int)(unsigned)(x >> 32);
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo;
+}
+
+// Bitwise OR over a group of G lanes.
+template <int G>
+__device__ __forceinline__ unsigned long long group_or(unsigned long long x)
+{
+    x |= dpp_u64<0xB1>(x);
+    if constexpr (G >= 4) x |= dpp_u64<0x4E>(x);
+    if constexpr (G >= 8) x |= dpp_u64<0x141>(x);
+    if constexpr (G >= 16) x |= dpp_u64<0x140>(x);
+    return x;
+}
+
 // Value of lane l (constant after unrolling) of the group, for lane g.
 template <int G>
 __device__ __forceinline__ double group_bcast(double x, int l, int g)
@@ -245,6 +287,12 @@ struct RArgs {
     int spm;                         // alpha slots per mesh
     double eh2, alpha_w, rank_tol, period, gamma;
     int weight_mode;
+    // balanced-stencil refit: list the cells whose facet values leave their
+    // stencil's range (count, ids, gradients of the first fit)
+    int balance;
+    unsigned long long *bal_count;
+    int32_t *bal_list;
+    double *bal_grad;
     // stencil-size buckets: cells [cell0[b], cell0[b+1]) run with rpl[b] rows
     // per lane, in workgroups [blk0[b], blk0[b+1])
     int64_t cell0[kMaxBuckets + 1];
@@ -635,6 +683,7 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     const int64_t uid = user ? (int64_t)a.perm[c] : 0;
 
     int rkm = 0;   // characteristic: smallest rank of a field over the facets
+    double vhi = -INFINITY, vlo = INFINITY;   // scalar: range of this lane's facet values
 #pragma unroll 1
     for (int it = 0; it < NIT; ++it) {
     // component v, or (characteristic) field v of facet fl
@@ -794,6 +843,8 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
                     a.fv[(lf * N + c) * Q + q] = val;
                     if (a.fv_user) a.fv_user[(uid * F + lf) * Q + q] = val;
                     if constexpr (FLUX == kFluxBurgers) am = fmax(am, fabs(val * nsm[t]));
+                    vhi = fmax(vhi, val);
+                    vlo = fmin(vlo, val);
                 }
             } else {
                 lfv[(v * F + lf) * Q + q] = val;
@@ -804,6 +855,35 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
 #pragma unroll
         for (int o = 0; o < M; ++o)
             if ((o % G) == g) a.coef_user[((int64_t)v * N + uid) * M + o] = coef[o];
+    }
+    if constexpr (V == 1) {
+        if (a.balance) {
+            // facet values beyond the range of the stencil's averages (outside
+            // a rounding band): list the cell for a refit on a balanced stencil
+            double rlo = uc, rhi = uc;
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) {
+                if (jrow[s] >= 0) {
+                    rlo = fmin(rlo, ug[s]);
+                    rhi = fmax(rhi, ug[s]);
+                }
+            }
+            rlo = group_min<G>(rlo);
+            rhi = group_max<G>(rhi);
+            const double band = 1e-10 * (rhi - rlo) + 1e-14 * fmax(fabs(rhi), fabs(rlo));
+            const double out = (vhi > rhi + band || vlo < rlo - band) ? 1.0 : 0.0;
+            if (group_sum<G>(out) > 0.0) {
+                am = 0.0;   // the refit posts this cell's alpha bound
+                if (live && g == 0) {
+                    const unsigned long long k = atomicAdd(a.bal_count, 1ull);
+                    if (k < (unsigned long long)N) {
+                        a.bal_list[k] = (int32_t)c;
+#pragma unroll
+                        for (int d = 0; d < DIM; ++d) a.bal_grad[c * DIM + d] = coef[1 + d];
+                    }
+                }
+            }
+        }
     }
     }   // component-wise evaluation
     }   // solves
@@ -925,6 +1005,110 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
         reconstruct_cell<DIM, P, G, R2, FLUX>(a, cell, a.cell0[2], a.cell0[3], a.spad + a.spad_off[2], a.stride[2], g,
                                               lds, slot);
     }
+}
+
+// Balanced-stencil refit (end of Sec. 3.2) of the cells listed by
+// k_reconstruct: from each cell's enlarged stencil (centre first, then by
+// distance) keep the centroid and the nearest cells on both sides of the
+// line/plane through it orthogonal to the first fit's gradient,
+// ceil((n-1)/2) with g.(x_j - x_i) > 0 and floor((n-1)/2) otherwise (a short
+// side leaves its share to the other), and fit again.  Lane g of a cell
+// classifies enlarged-stencil entries g, g+G, ...; the sides are 128-bit
+// masks in stencil order, OR-ed over the group, so the choice is a prefix
+// count.
+struct BArgs {
+    const unsigned long long *count;
+    const int32_t *list, *pool, *sptr;
+    const double *grad;
+    int pool_cap;
+};
+
+__device__ __forceinline__ unsigned long long lowest_bits(unsigned long long x, int k)
+{
+    unsigned long long y = 0ull;
+    for (int t = 0; t < k && x; ++t) {
+        const unsigned long long low = x & (~x + 1ull);
+        y |= low;
+        x ^= low;
+    }
+    return y;
+}
+
+template <int DIM, int P, int FLUX, int G, int RPL>
+__global__ void __launch_bounds__(256) k_rebalance(RArgs a, BArgs b)
+{
+    constexpr int CPB = 256 / G;
+    constexpr int GS = geo_stride<DIM, P>();
+    __shared__ double lds[CPB * Basis<DIM, P>::M];
+    __shared__ int32_t rows[CPB][RPL * G];
+    const int g = (int)(threadIdx.x % G);
+    const int slot = (int)(threadIdx.x / G);
+    const int64_t total = (int64_t)*b.count;
+    const int64_t cnt = total < a.nc ? total : a.nc;
+    // whole wavefronts past the end of the list leave at once
+    const int64_t first = (int64_t)blockIdx.x * CPB + (int64_t)(threadIdx.x / 64) * (64 / G);
+    if (first >= cnt) return;
+    const int64_t idx = (int64_t)blockIdx.x * CPB + slot;
+    const bool live = idx < cnt;
+    const int64_t c = b.list[live ? idx : cnt - 1];
+    double gr[DIM], xc[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        gr[d] = b.grad[c * DIM + d];
+        xc[d] = a.geo[c * GS + d];
+    }
+    const int32_t *pool = b.pool + c * b.pool_cap;
+    unsigned long long mp[2] = {0ull, 0ull}, mm[2] = {0ull, 0ull};
+    for (int r = g; r < b.pool_cap; r += G) {
+        const int32_t j = pool[r];
+        if (r == 0 || j < 0) continue;   // the centre; padding
+        double sd = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) sd += gr[d] * (a.geo[(int64_t)j * GS + d] - xc[d]);
+        const unsigned long long bit = 1ull << (r & 63);
+        if (sd > 0.0)
+            mp[r >> 6] |= bit;
+        else
+            mm[r >> 6] |= bit;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        mp[h] = group_or<G>(mp[h]);
+        mm[h] = group_or<G>(mm[h]);
+    }
+    const int cp = __popcll(mp[0]) + __popcll(mp[1]);
+    const int cm = __popcll(mm[0]) + __popcll(mm[1]);
+    const int n = b.sptr[c + 1] - b.sptr[c];
+    int qp = n / 2, qm = (n - 1) / 2;
+    if (cp < qp) {
+        qm += qp - cp;
+        qp = cp;
+    }
+    if (cm < qm) {
+        qp += qm - cm;
+        qm = cm;
+    }
+    unsigned long long acc[2];
+    {
+        const int p0 = __popcll(mp[0]) < qp ? __popcll(mp[0]) : qp;
+        const int m0 = __popcll(mm[0]) < qm ? __popcll(mm[0]) : qm;
+        acc[0] = lowest_bits(mp[0], p0) | lowest_bits(mm[0], m0);
+        acc[1] = lowest_bits(mp[1], qp - p0) | lowest_bits(mm[1], qm - m0);
+    }
+    const int n2 = 1 + __popcll(acc[0]) + __popcll(acc[1]);
+    int32_t *rw = rows[slot];
+    if (g == 0) rw[0] = (int32_t)c;
+    for (int r = g; r < b.pool_cap; r += G) {
+        const unsigned long long w = acc[r >> 6];
+        if ((w >> (r & 63)) & 1ull) {
+            const int below = (r >= 64 ? __popcll(acc[0]) : 0) + __popcll(w & ((1ull << (r & 63)) - 1ull));
+            rw[1 + below] = pool[r];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    reconstruct_cell<DIM, P, G, RPL, FLUX>(a, c, c, live ? c + 1 : c, rw, n2, g, lds, slot);
 }
 
 // ------------------------------------------------------------ adjoint
@@ -1497,6 +1681,33 @@ int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
     }
     args.blk0[kMaxBuckets] = nb;
     if (nb == 0) return 0;
+    if constexpr (DIM >= 2 && P == 3 && G == (DIM == 3 ? 8 : 2)) {
+        if (dm.balance) {
+            // first fit and listing, then the refit of the listed cells
+            BArgs b;
+            b.count = args.bal_count;
+            b.list = args.bal_list;
+            b.pool = dm.pool;
+            b.sptr = dm.sptr;
+            b.grad = args.bal_grad;
+            b.pool_cap = dm.pool_cap;
+            RArgs a2 = args;
+            a2.balance = 0;
+            const int nb2 = blocks_for(dm.nc, 256 / G);
+            if (dm.flux == kFluxBurgers) {
+                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st,
+                                   args);
+                hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxBurgers, G, R2>), dim3(nb2), dim3(256), 0, st, a2, b);
+            } else if (dm.flux == kFluxAdv) {
+                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxAdv, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
+                hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxAdv, G, R2>), dim3(nb2), dim3(256), 0, st, a2, b);
+            } else {
+                return (int)hipErrorInvalidValue;
+            }
+            return (int)hipGetLastError();
+        }
+    }
+    if (dm.balance) return (int)hipErrorInvalidValue;   // no refit variant for this shape
     if (dm.flux == kFluxBurgers) {
         hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
     } else if (dm.flux == kFluxEuler) {
@@ -1602,6 +1813,10 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     a.period = dm.period;
     a.gamma = dm.gamma;
     a.weight_mode = dm.weight_mode;
+    a.balance = dm.balance;
+    a.bal_count = dm.bal_count ? dm.bal_count + (size_t)parity * 16 : nullptr;
+    a.bal_list = dm.bal_list;
+    a.bal_grad = dm.bal_grad;
     // bucket b covers the variant's b-th rows-per-lane value; unused buckets are empty
     for (int b = 0; b <= kMaxBuckets; ++b) {
         a.cell0[b] = dm.bucket_cell0[b < dm.nbuckets ? b : dm.nbuckets];
@@ -1616,6 +1831,13 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     // per-column work (pivot search, exchanges, broadcasts) across a cell.
     const int lanes = dm.lanes ? dm.lanes
                                : (dm.dim == 3 ? 8 : (dm.dim == 2 && dm.p == 3 ? 2 : (dm.dim == 2 && dm.p == 5 ? 16 : 4)));
+    if (dm.balance) {
+        // the refit list of this stage starts empty
+        hipLaunchKernelGGL(k_clear_alpha, dim3(1), dim3(64), 0, st, a.bal_count, 1);
+        if (dm.dim == 2 && dm.p == 3) return launch_k1<2, 3, 2, 6, 8, 10>(dm, a, st);
+        if (dm.dim == 3 && dm.p == 3) return launch_k1<3, 3, 8, 4, 5, 7>(dm, a, st);
+        return (int)hipErrorInvalidValue;
+    }
     if (dm.dim == 1) {
         switch (dm.p) {
         case 2: return launch_k1<1, 2, 4, 2, 2, 2>(dm, a, st);
@@ -1701,7 +1923,7 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
 
 bool adjoint_supported(const DevMesh &dm)
 {
-    return dm.flux == WLSENO_FLUX_ADVECTION && dm.nvars == 1 && dm.nmesh == 1 && reconstruct_supported(dm);
+    return dm.flux == WLSENO_FLUX_ADVECTION && dm.nvars == 1 && dm.nmesh == 1 && !dm.balance && reconstruct_supported(dm);
 }
 
 int launch_adjoint(const DevMesh &dm, const double *u, const double *v, const int32_t *tpos, double *contrib,

@@ -447,6 +447,10 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     if (prm.characteristic != 0 && prm.characteristic != 1) throw inval("characteristic must be 0 or 1");
     if (prm.characteristic && prm.flux != WLSENO_FLUX_EULER)
         throw inval("characteristic = 1 applies to the Euler system only");
+    if (prm.balance != 0 && prm.balance != 1) throw inval("balance must be 0 or 1");
+    if (prm.balance && prm.flux == WLSENO_FLUX_EULER) throw inval("balance = 1 applies to scalar fluxes only");
+    if (prm.balance && !((dim == 2 || dim == 3) && prm.p == 3))
+        throw Error{WLSENO_EUNSUPPORTED, "balanced stencils are compiled for p = 3 in 2-D and 3-D"};
     if (prm.lanes != 0 && prm.lanes != 2 && prm.lanes != 4 && prm.lanes != 8 && prm.lanes != 16)
         throw inval("lanes must be 0, 2, 4, 8 or 16");
     if (!(prm.eps >= 0.0) || !(prm.alpha_w > 0.0) || !(prm.rank_tol >= 0.0))
@@ -534,6 +538,33 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
         int32_t u = b.perm[d];
         for (int32_t t = 0; t < cnt[u]; ++t) b.scol[b.sptr[d] + t] = b.iperm[b.col[b.row_ptr[u] + t]];
     }
+    // balanced-stencil refit: enlarged stencils (the same rule, twice the
+    // sizes), device order, padded
+    if (prm.balance) {
+        const int cap2 = 2 * prm.n_hi;
+        std::vector<int32_t> flat2(nc * cap2);
+        std::vector<int32_t> cnt2(nc);
+#pragma omp parallel
+        {
+            RingSet a(nc), bb(nc);
+            std::vector<std::pair<double, int32_t>> tmp;
+#pragma omp for schedule(dynamic, 256)
+            for (int64_t i = 0; i < nc; ++i) {
+                int k = 0;
+                one_stencil(m, i, 2 * prm.n_lo, 2 * prm.n_hi, a, bb, tmp, &flat2[i * cap2], &k);
+                cnt2[i] = k;
+            }
+        }
+        int pc = 0;
+        for (int64_t i = 0; i < nc; ++i) pc = std::max(pc, (int)cnt2[i]);
+        b.pool_cap = pc;
+        b.pool.assign(nc * pc, -1);
+        for (int64_t d = 0; d < nc; ++d) {
+            const int32_t u = b.perm[d];
+            for (int32_t t = 0; t < cnt2[u]; ++t) b.pool[d * pc + t] = b.iperm[flat2[u * cap2 + t]];
+        }
+    }
+
     // padded per-bucket stencil table (no row-pointer load in the kernel)
     {
         int64_t off = 0;

@@ -10,7 +10,7 @@ import pytest
 
 from parity import (assert_parity, assert_poly_parity, cell_conditions, cell_noise, char_cell_conditions, flux_scale,
                     floor_tol, momentum_scale, neighbourhood_max)
-from workloads import configs, periodic_line, uniform_periodic_line, jittered_square, fields
+from workloads import configs, periodic_line, uniform_periodic_line, jittered_cube, jittered_square, fields
 
 pytestmark = pytest.mark.gpu
 
@@ -346,6 +346,31 @@ def test_euler_characteristic_unit_weights_equal_components():
     fc = _gpu(mesh, **kw).reconstruct(u)["fval"].cpu().numpy()
     fx = _gpu(mesh, characteristic=True, **kw).reconstruct(u)["fval"].cpu().numpy()
     assert np.max(np.abs(fc - fx)) < 1e-11 * np.max(np.abs(fc))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_balanced_refit(dim):
+    """Balanced-stencil refit: the same cells are refitted on both sides
+    (GPU refits found by comparing with a run without it), and facet values,
+    coefficients, ranks, rhs and steps match the oracle."""
+    torch = _torch()
+    if dim == 2:
+        mesh = jittered_square(14, 0.3, 3107)
+        u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+        kw = dict(p=3, n_lo=12, n_hi=20, flux="burgers")
+    else:
+        mesh = jittered_cube(7, 0.15, 4107)
+        u0 = fields.cell_averages(mesh, fields.sine_with_sphere_3d)
+        kw = dict(p=3, n_lo=30, n_hi=50, flux="advection", velocity=(1.0, 0.5, 0.25))
+    u = torch.tensor(u0, device="cuda")
+    f0 = _gpu(mesh, **kw).reconstruct(u)["fval"].cpu().numpy()
+    f1 = _gpu(mesh, balance=True, **kw).reconstruct(u)["fval"].cpu().numpy()
+    gpu_refit = np.any(f0 != f1, axis=(0, 2, 3))
+    ref = _oracle(mesh, balance=True, **kw).reconstruct(u0)
+    _say(f"[case] balance dim {dim}: {int(ref['rebalanced'].sum())} of {mesh.n_cell} cells refitted")
+    assert ref["rebalanced"].sum() > 0
+    assert np.array_equal(gpu_refit, ref["rebalanced"].astype(bool))
+    _compare_all(mesh, u0, 3, None, f"balance{dim}d", balance=True, **kw)
 
 
 FREE_STREAM = (1.0, 1.0, 1.0, 1.0 / 0.4 + 1.0)   # rho = p = 1, velocity (1, 1)

@@ -137,6 +137,14 @@ def test_error_paths(lib):
     assert "slip wall" in str(e.value)
     w.stencil_build(p=3, n_lo=12, n_hi=20, flux="euler", bc=3)
     w.stencil_build(p=3, n_lo=12, n_hi=20, flux="euler", bc=2, far_state=(1.0, 0.0, 0.0, 2.5))
+    # balanced-stencil refit: scalar fluxes, compiled for p = 3
+    with pytest.raises(WLSENOError) as e:
+        w.stencil_build(p=3, n_lo=12, n_hi=20, flux="euler", balance=True)
+    assert e.value.status == 1
+    with pytest.raises(WLSENOError) as e:
+        w.stencil_build(p=4, n_lo=18, n_hi=24, flux="burgers", balance=True)
+    assert e.value.status == 5
+    w.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers", balance=True)
     # device call on a host-only context
     w.stencil_build(p=3, n_lo=12, n_hi=20)
     rc = lib.wlseno_rhs(w._h, C.c_void_p(16), C.c_void_p(32))
