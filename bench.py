@@ -337,6 +337,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="square", choices=sorted(WORKLOADS) + ["batch"])
+    ap.add_argument("--balance", action="store_true",
+                    help="single-mesh workloads: balanced-stencil refit of out-of-range cells")
     ap.add_argument("--characteristic", action="store_true",
                     help="batch workload: reconstruct characteristic fields per facet")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -366,7 +368,8 @@ def main():
     w = WLSENO(device=0)
     t1 = time.time()
     w.mesh_upload(dim, mesh.verts, mesh.cells)
-    w.stencil_build(p=cfg["p"], n_lo=cfg["n_lo"], n_hi=cfg["n_hi"], flux=cfg["flux"], velocity=cfg["velocity"])
+    w.stencil_build(p=cfg["p"], n_lo=cfg["n_lo"], n_hi=cfg["n_hi"], flux=cfg["flux"], velocity=cfg["velocity"],
+                    balance=args.balance)
     info = w.info()
     rp, _ = w.stencil()
     nsz = np.diff(rp)
@@ -413,7 +416,8 @@ def main():
     achieved = flops / (k1_avg * 1e-3) / 1e12
     log(f"[bench] k_reconstruct avg {k1_avg * 1e3:.2f} us ({k1_n} launches), "
         f"k_update avg {k2_avg * 1e3:.2f} us ({k2_n} launches); {flops / nc:.0f} flop/cell")
-    traffic = traffic_record("k_reconstruct", args.workload)
+    tkey = args.workload + ("-balance" if args.balance else "")
+    traffic = traffic_record("k_reconstruct", tkey)
     roofline = {
         "bound": "alu",
         "kernel": "k_reconstruct",
@@ -434,7 +438,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": ach_u / HBM_PEAK_GBS,
-        "traffic": traffic_record("k_update", args.workload),
+        "traffic": traffic_record("k_update", tkey),
         "avg_launch_us": k2_avg * 1e3,
         "bytes_per_launch": ub,
     }
@@ -453,7 +457,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": wl.name,
+            "workload": wl.name + ("-balanced" if args.balance else ""),
+            "balanced_refit": bool(args.balance),
             "mesh": (f"Delaunay triangulation of a jittered {cfg['side']}^{dim} lattice on [0,1]^{dim}"
                      f" (seed {cfg['seed']})"),
             "n_cell": nc,
@@ -471,7 +476,7 @@ def main():
     if args.cpu_seconds > 0 and args.workload == "square":
         import oracle
 
-        o = oracle.from_workload(wl)
+        o = oracle.from_workload(wl, balance=args.balance)
         nthreads = oracle.core.num_threads()
         tt = time.perf_counter()
         o.step(u0, dt, 1)

@@ -598,7 +598,9 @@ __device__ __forceinline__ void back_solve(const double (&Rs)[RS][M], const doub
 // --------------------------------------------------------------- K1
 // Reconstruction of one cell by a group of G lanes (g = lane in the group),
 // component by component (V = 1, or DIM + 2 conserved variables for Euler).
-template <int DIM, int P, int G, int RPL, int FLUX>
+// BAL: scalar fluxes, list cells for the balanced-stencil refit (a variant of
+// its own, so that the plain kernels carry none of its registers).
+template <int DIM, int P, int G, int RPL, int FLUX, bool BAL = false>
 __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, int64_t cell_begin, int64_t cell_end,
                                                  const int32_t *spad, int stride, int g, double *lds, int slot)
 {
@@ -843,8 +845,10 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
                     a.fv[(lf * N + c) * Q + q] = val;
                     if (a.fv_user) a.fv_user[(uid * F + lf) * Q + q] = val;
                     if constexpr (FLUX == kFluxBurgers) am = fmax(am, fabs(val * nsm[t]));
-                    vhi = fmax(vhi, val);
-                    vlo = fmin(vlo, val);
+                    if constexpr (BAL) {
+                        vhi = fmax(vhi, val);
+                        vlo = fmin(vlo, val);
+                    }
                 }
             } else {
                 lfv[(v * F + lf) * Q + q] = val;
@@ -856,7 +860,7 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
         for (int o = 0; o < M; ++o)
             if ((o % G) == g) a.coef_user[((int64_t)v * N + uid) * M + o] = coef[o];
     }
-    if constexpr (V == 1) {
+    if constexpr (V == 1 && BAL) {
         if (a.balance) {
             // facet values beyond the range of the stencil's averages (outside
             // a rounding band): list the cell for a refit on a balanced stencil
@@ -982,7 +986,7 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
 }
 
 // One workgroup = 256/G cells of one stencil-size bucket, G lanes per cell.
-template <int DIM, int P, int FLUX, int G, int R0, int R1, int R2>
+template <int DIM, int P, int FLUX, int G, int R0, int R1, int R2, bool BAL = false>
 __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
 {
     constexpr int CPB = 256 / G;   // cells per workgroup
@@ -994,15 +998,15 @@ __global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
     const int slot = (int)(threadIdx.x / G);
     if (L < a.blk0[1]) {
         const int64_t cell = a.cell0[0] + (int64_t)(L - a.blk0[0]) * CPB + slot;
-        reconstruct_cell<DIM, P, G, R0, FLUX>(a, cell, a.cell0[0], a.cell0[1], a.spad + a.spad_off[0], a.stride[0], g,
+        reconstruct_cell<DIM, P, G, R0, FLUX, BAL>(a, cell, a.cell0[0], a.cell0[1], a.spad + a.spad_off[0], a.stride[0], g,
                                               lds, slot);
     } else if (L < a.blk0[2]) {
         const int64_t cell = a.cell0[1] + (int64_t)(L - a.blk0[1]) * CPB + slot;
-        reconstruct_cell<DIM, P, G, R1, FLUX>(a, cell, a.cell0[1], a.cell0[2], a.spad + a.spad_off[1], a.stride[1], g,
+        reconstruct_cell<DIM, P, G, R1, FLUX, BAL>(a, cell, a.cell0[1], a.cell0[2], a.spad + a.spad_off[1], a.stride[1], g,
                                               lds, slot);
     } else {
         const int64_t cell = a.cell0[2] + (int64_t)(L - a.blk0[2]) * CPB + slot;
-        reconstruct_cell<DIM, P, G, R2, FLUX>(a, cell, a.cell0[2], a.cell0[3], a.spad + a.spad_off[2], a.stride[2], g,
+        reconstruct_cell<DIM, P, G, R2, FLUX, BAL>(a, cell, a.cell0[2], a.cell0[3], a.spad + a.spad_off[2], a.stride[2], g,
                                               lds, slot);
     }
 }
@@ -1695,11 +1699,12 @@ int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
             a2.balance = 0;
             const int nb2 = blocks_for(dm.nc, 256 / G);
             if (dm.flux == kFluxBurgers) {
-                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st,
-                                   args);
+                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2, true>), dim3(nb), dim3(256), 0,
+                                   st, args);
                 hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxBurgers, G, R2>), dim3(nb2), dim3(256), 0, st, a2, b);
             } else if (dm.flux == kFluxAdv) {
-                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxAdv, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
+                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxAdv, G, R0, R1, R2, true>), dim3(nb), dim3(256), 0, st,
+                                   args);
                 hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxAdv, G, R2>), dim3(nb2), dim3(256), 0, st, a2, b);
             } else {
                 return (int)hipErrorInvalidValue;

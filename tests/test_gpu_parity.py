@@ -368,9 +368,11 @@ def test_balanced_refit(dim):
     ref0 = _oracle(mesh, **kw).reconstruct(u0)
     ref = _oracle(mesh, balance=True, **kw).reconstruct(u0)
     # a refit whose balanced stencil is the cell's own stencil changes
-    # nothing, so cells are compared by whether the refit changed them
-    gpu_changed = np.any(f0 != f1, axis=(0, 2, 3))
-    ora_changed = np.any(ref0["fval"] != ref["fval"], axis=(0, 2, 3))
+    # nothing, so cells are compared by whether the refit changed them (the
+    # first fit runs in a kernel variant of its own, equal to rounding)
+    scale = 1e-8 * np.max(np.abs(ref0["fval"]))
+    gpu_changed = np.any(np.abs(f0 - f1) > scale, axis=(0, 2, 3))
+    ora_changed = np.any(np.abs(ref0["fval"] - ref["fval"]) > scale, axis=(0, 2, 3))
     _say(f"[case] balance dim {dim}: {int(ref['rebalanced'].sum())} of {mesh.n_cell} cells refitted, "
          f"{int(ora_changed.sum())} changed (gpu {int(gpu_changed.sum())})")
     assert ora_changed.sum() > 0
