@@ -598,6 +598,12 @@ __device__ __forceinline__ void back_solve(const double (&Rs)[RS][M], const doub
 // --------------------------------------------------------------- K1
 // Reconstruction of one cell by a group of G lanes (g = lane in the group),
 // component by component (V = 1, or DIM + 2 conserved variables for Euler).
+// Threads per workgroup of the per-cell kernels: one wavefront in 2-D, so
+// that a small mesh's few waves spread over all CUs instead of filling a
+// fraction of them four at a time (19.6 k triangles: 9.1 against 10.2 us per
+// launch); four in 3-D (64 measured 2% slower).
+constexpr int recon_block(int dim) { return dim == 3 ? 256 : 64; }
+
 // BAL: scalar fluxes, list cells for the balanced-stencil refit (a variant of
 // its own, so that the plain kernels carry none of its registers).
 template <int DIM, int P, int G, int RPL, int FLUX, bool BAL = false>
@@ -617,7 +623,7 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     constexpr int V = EULER ? DIM + 2 : 1;
     // solves per cell: one per component, or (characteristic) one per field and facet
     constexpr int NIT = CHAR ? V * F : V;
-    constexpr int CPB = 256 / G;
+    constexpr int CPB = recon_block(DIM) / G;
 
     const bool live = cell < cell_end;
     const int64_t c = live ? cell : cell_end - 1;
@@ -987,9 +993,9 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
 
 // One workgroup = 256/G cells of one stencil-size bucket, G lanes per cell.
 template <int DIM, int P, int FLUX, int G, int R0, int R1, int R2, bool BAL = false>
-__global__ void __launch_bounds__(256) k_reconstruct(RArgs a)
+__global__ void __launch_bounds__(recon_block(DIM)) k_reconstruct(RArgs a)
 {
-    constexpr int CPB = 256 / G;   // cells per workgroup
+    constexpr int CPB = recon_block(DIM) / G;   // cells per workgroup
     // per cell: M coefficients; for the Euler system also its facet values [V][F][Q]
     __shared__ double lds[CPB * (Basis<DIM, P>::M +
                                  (FLUX == kFluxEuler || FLUX == kFluxEulerChar ? (DIM + 2) * (DIM + 1) * num_q<DIM, P>() : 0))];
@@ -1039,9 +1045,9 @@ __device__ __forceinline__ unsigned long long lowest_bits(unsigned long long x, 
 }
 
 template <int DIM, int P, int FLUX, int G, int RPL>
-__global__ void __launch_bounds__(256) k_rebalance(RArgs a, BArgs b)
+__global__ void __launch_bounds__(recon_block(DIM)) k_rebalance(RArgs a, BArgs b)
 {
-    constexpr int CPB = 256 / G;
+    constexpr int CPB = recon_block(DIM) / G;
     constexpr int GS = geo_stride<DIM, P>();
     __shared__ double lds[CPB * Basis<DIM, P>::M];
     __shared__ int32_t rows[CPB][RPL * G];
@@ -1677,11 +1683,12 @@ constexpr int char_lanes(int p) { return p == 5 ? 16 : 4; }
 template <int DIM, int P, int G, int R0, int R1, int R2>
 int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
 {
-    // workgroup ranges of the buckets for 256/G cells per workgroup
+    // workgroup ranges of the buckets for BS/G cells per workgroup
+    constexpr int BS = recon_block(DIM);
     int nb = 0;
     for (int b = 0; b < kMaxBuckets; ++b) {
         args.blk0[b] = nb;
-        nb += blocks_for(args.cell0[b + 1] - args.cell0[b], 256 / G);
+        nb += blocks_for(args.cell0[b + 1] - args.cell0[b], BS / G);
     }
     args.blk0[kMaxBuckets] = nb;
     if (nb == 0) return 0;
@@ -1697,15 +1704,15 @@ int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
             b.pool_cap = dm.pool_cap;
             RArgs a2 = args;
             a2.balance = 0;
-            const int nb2 = blocks_for(dm.nc, 256 / G);
+            const int nb2 = blocks_for(dm.nc, BS / G);
             if (dm.flux == kFluxBurgers) {
-                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2, true>), dim3(nb), dim3(256), 0,
+                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2, true>), dim3(nb), dim3(BS), 0,
                                    st, args);
-                hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxBurgers, G, R2>), dim3(nb2), dim3(256), 0, st, a2, b);
+                hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxBurgers, G, R2>), dim3(nb2), dim3(BS), 0, st, a2, b);
             } else if (dm.flux == kFluxAdv) {
-                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxAdv, G, R0, R1, R2, true>), dim3(nb), dim3(256), 0, st,
+                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxAdv, G, R0, R1, R2, true>), dim3(nb), dim3(BS), 0, st,
                                    args);
-                hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxAdv, G, R2>), dim3(nb2), dim3(256), 0, st, a2, b);
+                hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxAdv, G, R2>), dim3(nb2), dim3(BS), 0, st, a2, b);
             } else {
                 return (int)hipErrorInvalidValue;
             }
@@ -1714,24 +1721,24 @@ int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
     }
     if (dm.balance) return (int)hipErrorInvalidValue;   // no refit variant for this shape
     if (dm.flux == kFluxBurgers) {
-        hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
+        hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2>), dim3(nb), dim3(BS), 0, st, args);
     } else if (dm.flux == kFluxEuler) {
         if constexpr (DIM == 2) {
             if (dm.characteristic) {
                 // one lane count per order (launch_reconstruct picks it)
                 if constexpr (G == char_lanes(P))
-                    hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxEulerChar, G, R0, R1, R2>), dim3(nb), dim3(256), 0,
+                    hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxEulerChar, G, R0, R1, R2>), dim3(nb), dim3(BS), 0,
                                        st, args);
                 else
                     return (int)hipErrorInvalidValue;
             } else {
-                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxEuler, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
+                hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxEuler, G, R0, R1, R2>), dim3(nb), dim3(BS), 0, st, args);
             }
         } else {
             return (int)hipErrorInvalidValue;
         }
     } else {
-        hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxAdv, G, R0, R1, R2>), dim3(nb), dim3(256), 0, st, args);
+        hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxAdv, G, R0, R1, R2>), dim3(nb), dim3(BS), 0, st, args);
     }
     return (int)hipGetLastError();
 }
