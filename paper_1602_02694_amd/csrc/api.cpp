@@ -188,6 +188,8 @@ void upload_build(wlseno_ctx *c)
         dm.bal_grad = (double *)dev_alloc(c, m.nc * m.dim * sizeof(double));
         dm.bal_count = (unsigned long long *)dev_alloc(c, 32 * sizeof(unsigned long long));
         check_hip(hipMemset(dm.bal_count, 0, 32 * sizeof(unsigned long long)), "hipMemset");
+        dm.bal_alpha = (unsigned long long *)dev_alloc(c, (size_t)dm.alpha_slots() * 16 * sizeof(unsigned long long));
+        check_hip(hipMemset(dm.bal_alpha, 0, (size_t)dm.alpha_slots() * 16 * sizeof(unsigned long long)), "hipMemset");
     }
     dm.geo = upload(c, b.geo);
     dm.vrel = upload(c, b.vrel);

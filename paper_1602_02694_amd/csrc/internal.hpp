@@ -107,6 +107,7 @@ struct DevMesh {
     int32_t *bal_list = nullptr;
     unsigned long long *bal_count = nullptr;
     double *bal_grad = nullptr;
+    unsigned long long *bal_alpha = nullptr;   // scratch alpha slots of the discarded first fits
     int lanes = 0;   // lanes per cell in the reconstruction: 0 = automatic, 4 or 8
     int64_t nc = 0;
     int nbuckets = 0;

@@ -287,12 +287,8 @@ struct RArgs {
     int spm;                         // alpha slots per mesh
     double eh2, alpha_w, rank_tol, period, gamma;
     int weight_mode;
-    // balanced-stencil refit: list the cells whose facet values leave their
-    // stencil's range (count, ids, gradients of the first fit)
-    int balance;
-    unsigned long long *bal_count;
-    int32_t *bal_list;
-    double *bal_grad;
+    double *bal_grad;                // balanced-stencil refit: gradients of the first fit
+    unsigned long long *bal_count;   // and this stage's list length (read by the refit)
     // stencil-size buckets: cells [cell0[b], cell0[b+1]) run with rpl[b] rows
     // per lane, in workgroups [blk0[b], blk0[b+1])
     int64_t cell0[kMaxBuckets + 1];
@@ -604,8 +600,8 @@ __device__ __forceinline__ void back_solve(const double (&Rs)[RS][M], const doub
 // launch); four in 3-D (64 measured 2% slower).
 constexpr int recon_block(int dim) { return dim == 3 ? 256 : 64; }
 
-// BAL: scalar fluxes, list cells for the balanced-stencil refit (a variant of
-// its own, so that the plain kernels carry none of its registers).
+// BAL: scalar fluxes, also store each cell's gradient for the balanced-stencil
+// refit (a variant of its own, so that the plain kernels carry none of it).
 template <int DIM, int P, int G, int RPL, int FLUX, bool BAL = false>
 __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, int64_t cell_begin, int64_t cell_end,
                                                  const int32_t *spad, int stride, int g, double *lds, int slot)
@@ -691,7 +687,6 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     const int64_t uid = user ? (int64_t)a.perm[c] : 0;
 
     int rkm = 0;   // characteristic: smallest rank of a field over the facets
-    double vhi = -INFINITY, vlo = INFINITY;   // scalar: range of this lane's facet values
 #pragma unroll 1
     for (int it = 0; it < NIT; ++it) {
     // component v, or (characteristic) field v of facet fl
@@ -851,10 +846,6 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
                     a.fv[(lf * N + c) * Q + q] = val;
                     if (a.fv_user) a.fv_user[(uid * F + lf) * Q + q] = val;
                     if constexpr (FLUX == kFluxBurgers) am = fmax(am, fabs(val * nsm[t]));
-                    if constexpr (BAL) {
-                        vhi = fmax(vhi, val);
-                        vlo = fmin(vlo, val);
-                    }
                 }
             } else {
                 lfv[(v * F + lf) * Q + q] = val;
@@ -867,32 +858,11 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
             if ((o % G) == g) a.coef_user[((int64_t)v * N + uid) * M + o] = coef[o];
     }
     if constexpr (V == 1 && BAL) {
-        if (a.balance) {
-            // facet values beyond the range of the stencil's averages (outside
-            // a rounding band): list the cell for a refit on a balanced stencil
-            double rlo = uc, rhi = uc;
+        // balanced-stencil refit: the first fit's gradient, for the cells the
+        // range check will list
+        if (live && g == 0) {
 #pragma unroll
-            for (int s = 0; s < RPL; ++s) {
-                if (jrow[s] >= 0) {
-                    rlo = fmin(rlo, ug[s]);
-                    rhi = fmax(rhi, ug[s]);
-                }
-            }
-            rlo = group_min<G>(rlo);
-            rhi = group_max<G>(rhi);
-            const double band = 1e-10 * (rhi - rlo) + 1e-14 * fmax(fabs(rhi), fabs(rlo));
-            const double out = (vhi > rhi + band || vlo < rlo - band) ? 1.0 : 0.0;
-            if (group_sum<G>(out) > 0.0) {
-                am = 0.0;   // the refit posts this cell's alpha bound
-                if (live && g == 0) {
-                    const unsigned long long k = atomicAdd(a.bal_count, 1ull);
-                    if (k < (unsigned long long)N) {
-                        a.bal_list[k] = (int32_t)c;
-#pragma unroll
-                        for (int d = 0; d < DIM; ++d) a.bal_grad[c * DIM + d] = coef[1 + d];
-                    }
-                }
-            }
+            for (int d = 0; d < DIM; ++d) a.bal_grad[c * DIM + d] = coef[1 + d];
         }
     }
     }   // component-wise evaluation
@@ -1026,6 +996,78 @@ __global__ void __launch_bounds__(recon_block(DIM)) k_reconstruct(RArgs a)
 // classifies enlarged-stencil entries g, g+G, ...; the sides are 128-bit
 // masks in stencil order, OR-ed over the group, so the choice is a prefix
 // count.
+// Range check of the first fit (one thread per cell): a cell whose facet
+// values leave [min, max] of its stencil's averages by more than a rounding
+// band goes on the refit list; every other cell posts its Lax-Friedrichs alpha
+// bound (the first fit posted into scratch slots, so that the refit's values,
+// not the discarded ones, bound alpha).
+struct FArgs {
+    int64_t nc;
+    const double *u, *fv, *nsum;
+    const int32_t *sptr, *scol, *mid;
+    unsigned long long *alpha_acc, *count;
+    int32_t *list;
+    int spm;
+};
+
+template <int DIM, int Q, int FLUX>
+__global__ void __launch_bounds__(256) k_flag(FArgs a)
+{
+    constexpr int F = DIM + 1;
+    const int64_t N = a.nc;
+    const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool live = i0 < N;
+    const int64_t c = live ? i0 : N - 1;
+    double lo = a.u[c], hi = lo;
+    // the stencil's averages in batches of 16 independent loads (clamped
+    // indices repeat the centre), so that their latencies overlap
+    const int32_t t0 = a.sptr[c], t1 = a.sptr[c + 1];
+    for (int32_t tb = t0; tb < t1; tb += 16) {
+        int32_t id[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) id[k] = tb + k < t1 ? a.scol[tb + k] : (int32_t)c;
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = a.u[id[k]];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            lo = fmin(lo, v[k]);
+            hi = fmax(hi, v[k]);
+        }
+    }
+    double vlo = INFINITY, vhi = -INFINITY, am = 0.0;
+#pragma unroll
+    for (int lf = 0; lf < F; ++lf) {
+        const double nsm = FLUX == kFluxBurgers ? a.nsum[lf * N + c] : 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const double v = a.fv[(lf * N + c) * Q + q];
+            vlo = fmin(vlo, v);
+            vhi = fmax(vhi, v);
+            am = fmax(am, fabs(v * nsm));
+        }
+    }
+    const double band = 1e-10 * (hi - lo) + 1e-14 * fmax(fabs(hi), fabs(lo));
+    if (live && (vhi > hi + band || vlo < lo - band)) {
+        am = 0.0;   // the refit posts this cell's bound
+        const unsigned long long k = atomicAdd(a.count, 1ull);
+        if (k < (unsigned long long)N) a.list[k] = (int32_t)c;
+    }
+    if (!live) am = 0.0;
+    if constexpr (FLUX == kFluxBurgers) {
+        const int32_t mesh = a.mid ? a.mid[c] : 0;
+        const int wv = (int)((blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % a.spm);
+        const int m0 = __builtin_amdgcn_readfirstlane(mesh);
+        if (__ballot(mesh != m0) == 0) {
+            am = wave_max(am);
+            if ((threadIdx.x & 63) == 0)
+                atomicMax(a.alpha_acc + ((int64_t)m0 * a.spm + wv) * 16, (unsigned long long)__double_as_longlong(am));
+        } else if (am > 0.0) {
+            atomicMax(a.alpha_acc + ((int64_t)mesh * a.spm + wv) * 16, (unsigned long long)__double_as_longlong(am));
+        }
+    }
+}
+
 struct BArgs {
     const unsigned long long *count;
     const int32_t *list, *pool, *sptr;
@@ -1069,17 +1111,35 @@ __global__ void __launch_bounds__(recon_block(DIM)) k_rebalance(RArgs a, BArgs b
     }
     const int32_t *pool = b.pool + c * b.pool_cap;
     unsigned long long mp[2] = {0ull, 0ull}, mm[2] = {0ull, 0ull};
-    for (int r = g; r < b.pool_cap; r += G) {
-        const int32_t j = pool[r];
-        if (r == 0 || j < 0) continue;   // the centre; padding
-        double sd = 0.0;
+    // entries g, g+G, ... in batches of 8 independent loads (clamped to the
+    // centre), so that their latencies overlap
+    for (int rb = g; rb < b.pool_cap; rb += 8 * G) {
+        int32_t jj[8];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) sd += gr[d] * (a.geo[(int64_t)j * GS + d] - xc[d]);
-        const unsigned long long bit = 1ull << (r & 63);
-        if (sd > 0.0)
-            mp[r >> 6] |= bit;
-        else
-            mm[r >> 6] |= bit;
+        for (int k = 0; k < 8; ++k) {
+            const int r = rb + k * G;
+            jj[k] = r < b.pool_cap ? pool[r] : -1;
+        }
+        double gx[8][DIM];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t j = jj[k] >= 0 ? (int64_t)jj[k] : c;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) gx[k][d] = a.geo[j * GS + d];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int r = rb + k * G;
+            if (r == 0 || jj[k] < 0) continue;   // the centre; padding or past the end
+            double sd = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) sd += gr[d] * (gx[k][d] - xc[d]);
+            const unsigned long long bit = 1ull << (r & 63);
+            if (sd > 0.0)
+                mp[r >> 6] |= bit;
+            else
+                mm[r >> 6] |= bit;
+        }
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -1694,25 +1754,42 @@ int launch_k1(const DevMesh &dm, RArgs args, hipStream_t st)
     if (nb == 0) return 0;
     if constexpr (DIM >= 2 && P == 3 && G == (DIM == 3 ? 8 : 2)) {
         if (dm.balance) {
-            // first fit and listing, then the refit of the listed cells
+            // first fit (alpha bounds into scratch slots, gradients kept), range
+            // check and listing, then the refit of the listed cells
             BArgs b;
             b.count = args.bal_count;
-            b.list = args.bal_list;
+            b.list = dm.bal_list;
             b.pool = dm.pool;
             b.sptr = dm.sptr;
             b.grad = args.bal_grad;
             b.pool_cap = dm.pool_cap;
-            RArgs a2 = args;
-            a2.balance = 0;
+            FArgs f;
+            f.nc = dm.nc;
+            f.u = args.u;
+            f.fv = dm.fv;
+            f.nsum = dm.nsum;
+            f.sptr = dm.sptr;
+            f.scol = dm.scol;
+            f.mid = dm.mid;
+            f.alpha_acc = args.alpha_acc;
+            f.count = args.bal_count;
+            f.list = dm.bal_list;
+            f.spm = args.spm;
+            RArgs a1 = args;
+            a1.alpha_acc = dm.bal_alpha;
             const int nb2 = blocks_for(dm.nc, BS / G);
+            const int nbf = blocks_for(dm.nc, 256);
+            constexpr int Q = num_q<DIM, P>();
             if (dm.flux == kFluxBurgers) {
                 hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxBurgers, G, R0, R1, R2, true>), dim3(nb), dim3(BS), 0,
-                                   st, args);
-                hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxBurgers, G, R2>), dim3(nb2), dim3(BS), 0, st, a2, b);
+                                   st, a1);
+                hipLaunchKernelGGL((k_flag<DIM, Q, kFluxBurgers>), dim3(nbf), dim3(256), 0, st, f);
+                hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxBurgers, G, R2>), dim3(nb2), dim3(BS), 0, st, args, b);
             } else if (dm.flux == kFluxAdv) {
                 hipLaunchKernelGGL((k_reconstruct<DIM, P, kFluxAdv, G, R0, R1, R2, true>), dim3(nb), dim3(BS), 0, st,
-                                   args);
-                hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxAdv, G, R2>), dim3(nb2), dim3(BS), 0, st, a2, b);
+                                   a1);
+                hipLaunchKernelGGL((k_flag<DIM, Q, kFluxAdv>), dim3(nbf), dim3(256), 0, st, f);
+                hipLaunchKernelGGL((k_rebalance<DIM, P, kFluxAdv, G, R2>), dim3(nb2), dim3(BS), 0, st, args, b);
             } else {
                 return (int)hipErrorInvalidValue;
             }
@@ -1825,10 +1902,8 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     a.period = dm.period;
     a.gamma = dm.gamma;
     a.weight_mode = dm.weight_mode;
-    a.balance = dm.balance;
-    a.bal_count = dm.bal_count ? dm.bal_count + (size_t)parity * 16 : nullptr;
-    a.bal_list = dm.bal_list;
     a.bal_grad = dm.bal_grad;
+    a.bal_count = dm.bal_count ? dm.bal_count + (size_t)parity * 16 : nullptr;
     // bucket b covers the variant's b-th rows-per-lane value; unused buckets are empty
     for (int b = 0; b <= kMaxBuckets; ++b) {
         a.cell0[b] = dm.bucket_cell0[b < dm.nbuckets ? b : dm.nbuckets];
