@@ -349,8 +349,8 @@ def main():
                     help="random directions of the adjoint's finite-difference check")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md and is not run.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs a mesh, or a "
+              "batch of meshes, on a single device; sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

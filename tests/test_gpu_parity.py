@@ -458,8 +458,11 @@ def _batch(flux, seed):
     return meshes, us
 
 
-@pytest.mark.parametrize("flux,p,n_lo,n_hi", [("euler", 3, 12, 20), ("euler", 4, 20, 36), ("burgers", 3, 12, 20)])
-def test_batch_matches_single_meshes(flux, p, n_lo, n_hi):
+@pytest.mark.parametrize("flux,p,n_lo,n_hi,extra", [
+    ("euler", 3, 12, 20, {}), ("euler", 4, 20, 36, {}), ("burgers", 3, 12, 20, {}),
+    ("euler", 4, 20, 36, {"characteristic": True}), ("burgers", 3, 12, 20, {"balance": True})],
+    ids=["euler-p3", "euler-p4", "burgers-p3", "euler-p4-characteristic", "burgers-p3-balance"])
+def test_batch_matches_single_meshes(flux, p, n_lo, n_hi, extra):
     """A batch of three meshes gives, bit for bit, what three single-mesh
     contexts give (rhs, per-mesh alpha, steps with a time step per mesh), and
     each mesh's rhs matches its own oracle."""
@@ -467,8 +470,8 @@ def test_batch_matches_single_meshes(flux, p, n_lo, n_hi):
     from paper_1602_02694_amd import WLSENO
 
     meshes, us = _batch(flux, 3301)
-    kw = dict(p=p, n_lo=n_lo, n_hi=n_hi, flux=flux)
-    _say(f"[case] batch {flux} p={p}: cells {[m.n_cell for m in meshes]}")
+    kw = dict(p=p, n_lo=n_lo, n_hi=n_hi, flux=flux, **extra)
+    _say(f"[case] batch {flux} p={p} {extra}: cells {[m.n_cell for m in meshes]}")
     wb = WLSENO(device=0)
     for k, m in enumerate(meshes):
         assert wb.batch_add_mesh(2, m.verts, m.cells) == k
@@ -489,7 +492,11 @@ def test_batch_matches_single_meshes(flux, p, n_lo, n_hi):
         Lo, alpha_o = o.rhs(us[k] if V > 1 else us[k][0])
         Lo = Lo.reshape(V, -1)
         ref = o.reconstruct(us[k] if V > 1 else us[k][0])
-        kap = cell_conditions(o, us[k])
+        if extra.get("characteristic"):
+            kc = char_cell_conditions(o, us[k])
+            kap = np.broadcast_to(kc.max(axis=0, keepdims=True), kc.shape)
+        else:
+            kap = cell_conditions(o, us[k])
         kap_nb = np.broadcast_to(neighbourhood_max(o, kap.max(axis=0, keepdims=True)), kap.shape)
         S = np.asarray(flux_scale(o, ref["fval"], alpha_o)).reshape(V, -1)
         assert_parity(Lb[:, off:off + m.n_cell], Lo, f"batch mesh {k} rhs", scale=S, tol_floor=floor_tol(kap_nb))
