@@ -313,6 +313,22 @@ def test_cube_p2():
                  velocity=(0.3, -1.0, 0.5))
 
 
+def test_cube_largest_compiled_stencils():
+    """3-D stencils at the largest compiled capacity (56 rows per cell) match
+    the oracle; a larger rule is refused cleanly at the device upload."""
+    from paper_1602_02694_amd import WLSENO, WLSENOError
+
+    mesh = jittered_cube(7, 0.15, 4111)
+    u0 = fields.cell_averages(mesh, fields.sine_with_sphere_3d)
+    _compare_all(mesh, u0, 2, None, "cube7-n56", p=3, n_lo=50, n_hi=56, flux="advection",
+                 velocity=(1.0, 0.5, 0.25))
+    w = WLSENO(device=0)
+    w.mesh_upload(3, mesh.verts, mesh.cells)
+    with pytest.raises(WLSENOError) as e:
+        w.stencil_build(p=3, n_lo=60, n_hi=64, flux="advection")
+    assert e.value.status == 5
+
+
 # ----------------------------------------------------------------- Euler
 
 @pytest.mark.parametrize("p,n_lo,n_hi,lanes", [(3, 12, 20, 0), (4, 20, 36, 0), (4, 20, 36, 16)])

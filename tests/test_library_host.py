@@ -102,6 +102,10 @@ def test_error_paths(lib):
     with pytest.raises(WLSENOError) as e:
         w.mesh_upload(2, mesh.verts, bad)
     assert e.value.status == 1
+    # empty mesh
+    with pytest.raises(WLSENOError) as e:
+        w.mesh_upload(2, np.zeros((0, 2)), np.zeros((0, 3), dtype=np.int32))
+    assert e.value.status == 1 and "at least one cell" in str(e.value)
     # periodic flag outside 1-D
     with pytest.raises(WLSENOError):
         w.mesh_upload(2, mesh.verts, mesh.cells, periodic=True)
