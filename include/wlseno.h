@@ -68,6 +68,11 @@ enum {
 /* mesh flags */
 #define WLSENO_MESH_PERIODIC_1D 1u /* 1-D only: first and last node are one point;
                                        period = x_last - x_first */
+#define WLSENO_MESH_PERIODIC_2D 2u /* 2-D only: the mesh fills its bounding box and
+                                       closes into a torus: every vertex on the upper
+                                       x (y) side has a partner on the lower side with
+                                       the identical y (x) coordinate, else EINVAL;
+                                       periods = the box's extents */
 
 /* Method parameters.  wlseno_params_default() fills the readings used
  * throughout: eps = 1e-2 and alpha_w = 1.5 (the example values of Sec. 3.1.2),
@@ -161,7 +166,8 @@ wlseno_status wlseno_set_stream(wlseno_t ctx, void *hip_stream);
  *   cells : int32[n_cell * (dim+1)] vertex ids; every cell must have positive
  *           measure (2-D counter-clockwise, 3-D positively oriented), else EINVAL
  *           naming the cell.
- *   flags : WLSENO_MESH_PERIODIC_1D or 0.
+ *   flags : WLSENO_MESH_PERIODIC_1D, WLSENO_MESH_PERIODIC_2D or 0.  On a periodic
+ *           mesh stencils, centroid offsets and facet neighbours wrap around.
  * Facets shared by more than two cells give EINVAL.  Invalidates any previous
  * stencil build.  (Sec. 3.3.1: cells, sibling half-facets, vertex-to-cell map.) */
 wlseno_status wlseno_mesh_upload(wlseno_t ctx, int dim, int64_t n_vert, const double *xyz,

@@ -96,6 +96,7 @@ class _Problem(C.Structure):
         ("pool_ptr", C.POINTER(C.c_int)),
         ("pool_col", C.POINTER(C.c_int)),
         ("balance", C.c_int),
+        ("period_y", C.c_double),
     ]
 
 
@@ -215,6 +216,7 @@ class Oracle:
         for v in range(5):
             P.far[v] = float(far_state[v]) if far_state is not None and v < len(far_state) else 0.0
         P.period, P.eps, P.alpha_w, P.rank_tol = om.period, eps, alpha_w, rank_tol
+        P.period_y = om.period_y
         P.h, P.gamma = self.h, gamma
         for d in range(3):
             P.adv[d] = float(velocity[d]) if d < len(velocity) else 0.0

@@ -49,10 +49,18 @@ class OracleMesh:
         self.dim = int(dim)
         self.verts = np.ascontiguousarray(np.asarray(verts, dtype=np.float64).reshape(-1, dim))
         self.cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).reshape(-1, dim + 1))
-        self.periodic = bool(periodic) and dim == 1
+        self.periodic = bool(periodic) and dim in (1, 2)
         self.nc = self.cells.shape[0]
         self.nv = self.verts.shape[0]
-        self.period = float(self.verts[-1, 0] - self.verts[0, 0]) if self.periodic else 0.0
+        # periods per axis: 1-D the circle (last node minus first); 2-D the
+        # bounding box, whose opposite sides carry identical vertices
+        self.period, self.period_y = 0.0, 0.0
+        if self.periodic and dim == 1:
+            self.period = float(self.verts[-1, 0] - self.verts[0, 0])
+        elif self.periodic:
+            lo, hi = self.verts.min(axis=0), self.verts.max(axis=0)
+            self.period, self.period_y = float(hi[0] - lo[0]), float(hi[1] - lo[1])
+            self._box = (lo, hi)
         self.p = int(p)
         self._geometry()
         self._topology()
@@ -79,16 +87,34 @@ class OracleMesh:
         self.cent = np.ascontiguousarray(_seq_sum([cv[:, v] for v in range(d + 1)]) / (d + 1))
 
     def vid(self, v):
-        """Vertex id with the periodic end node identified with node 0."""
-        if self.periodic and v == self.nv - 1:
-            return 0
-        return int(v)
+        """Vertex id with periodic images identified (1-D: the end node is
+        node 0; 2-D: a vertex on the upper x or y side is its partner on the
+        lower side, the one with the same other coordinate)."""
+        return int(self._vid[v]) if self.periodic else int(v)
+
+    def _identify(self):
+        if self.dim == 1:
+            ident = np.arange(self.nv)
+            ident[self.nv - 1] = 0
+            return ident
+        lo, hi = self._box
+        rep = {}
+        ident = np.arange(self.nv)
+        for v in range(self.nv):
+            x, y = float(self.verts[v, 0]), float(self.verts[v, 1])
+            if abs(x - hi[0]) <= 1e-12 * self.period:
+                x = float(lo[0])
+            if abs(y - hi[1]) <= 1e-12 * self.period_y:
+                y = float(lo[1])
+            ident[v] = rep.setdefault((x, y), v)
+        return ident
 
     def _topology(self):
         d = self.dim
         cells = self.cells.copy()
         if self.periodic:
-            cells[cells == self.nv - 1] = 0
+            self._vid = self._identify()
+            cells = self._vid[cells]
         self.cells_id = cells
         # vertex -> incident cells
         v2c = [[] for _ in range(self.nv)]
@@ -243,8 +269,8 @@ class OracleMesh:
         d = 0.0
         for k in range(self.dim):
             dx = float(self.cent[j, k]) - float(self.cent[i, k])
-            if self.periodic:
-                L = self.period
+            L = (self.period if k == 0 else self.period_y if k == 1 else 0.0) if self.periodic else 0.0
+            if L > 0.0:
                 if dx > 0.5 * L:
                     dx -= L
                 elif dx < -0.5 * L:

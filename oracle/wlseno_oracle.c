@@ -72,6 +72,7 @@ typedef struct {
     const int *pool_ptr;  /* balance: enlarged stencils (CSR, centre first, canonical order) */
     const int *pool_col;
     int balance;          /* scalar fluxes: refit out-of-range cells on a balanced stencil */
+    double period_y;      /* 2-D periodic meshes: period along y (period: along x) */
 } or_problem;
 
 /* Threads the per-cell loops use (1 without OpenMP). */
@@ -126,13 +127,16 @@ int or_basis(int dim, int p, int *exps)
     return k;
 }
 
-/* Nearest periodic image of a 1-D difference. */
-static real wrap(const or_problem *P, real d)
+/* Nearest periodic image of a coordinate difference along `axis` (1-D
+ * circle: axis 0; 2-D periodic square: axes 0 and 1). */
+static real wrap(const or_problem *P, int axis, real d)
 {
     if (P->periodic) {
-        real L = P->period;
-        if (d > 0.5 * L) d -= L;
-        else if (d < -0.5 * L) d += L;
+        real L = axis == 0 ? P->period : (axis == 1 ? P->period_y : 0.0);
+        if (L > 0.0) {
+            if (d > 0.5 * L) d -= L;
+            else if (d < -0.5 * L) d += L;
+        }
     }
     return d;
 }
@@ -187,18 +191,19 @@ double or_simplex_avg_monomial(int dim, const double *verts, const double *c, co
 
 static int stencil_size(const or_problem *P, int i) { return P->row_ptr[i + 1] - P->row_ptr[i]; }
 
-/* Vertices of cell j shifted to the periodic image nearest cell i (1-D). */
+/* Vertices of cell j shifted to the periodic image nearest cell i. */
 static void image_vertices(const or_problem *P, int i, int j, real *out)
 {
     int nv = P->dim + 1;
-    real shift = 0.0;
-    if (P->periodic) {
-        real d = (real)P->cent[j] - (real)P->cent[i];
-        shift = wrap(P, d) - d;
-    }
+    real shift[OR_MAXDIM] = {0.0, 0.0, 0.0};
+    if (P->periodic)
+        for (int d = 0; d < P->dim; ++d) {
+            real dd = (real)P->cent[(size_t)j * P->dim + d] - (real)P->cent[(size_t)i * P->dim + d];
+            shift[d] = wrap(P, d, dd) - dd;
+        }
     for (int v = 0; v < nv; ++v)
         for (int d = 0; d < P->dim; ++d)
-            out[v * P->dim + d] = (real)P->cv[((size_t)j * nv + v) * P->dim + d] + (d == 0 ? shift : 0.0);
+            out[v * P->dim + d] = (real)P->cv[((size_t)j * nv + v) * P->dim + d] + shift[d];
 }
 
 /* A (n x m): averages over each stencil cell of the Taylor monomials about x_i. */
@@ -581,7 +586,7 @@ static int balanced_rows(const or_problem *P, int i, const real *g, int n, int *
         real s = 0.0;
         for (int d = 0; d < D; ++d) {
             real dd = (real)P->cent[(size_t)j * D + d] - (real)P->cent[(size_t)i * D + d];
-            if (d == 0) dd = wrap(P, dd);
+            dd = wrap(P, d, dd);
             s += g[d] * dd;
         }
         plus[r] = s > 0.0;
@@ -875,7 +880,7 @@ static void divergence_cell(const or_problem *P, int i, const real *u, const rea
                         real dd = 0.0;
                         for (int d = 0; d < D; ++d) {
                             real e = (real)y[d] - (real)x[d];
-                            if (d == 0) e = wrap(P, e);
+                            e = wrap(P, d, e);
                             dd += e * e;
                         }
                         if (bf < 0 || dd < bd) { bf = f2; bq = q2; bd = dd; }
@@ -886,7 +891,7 @@ static void divergence_cell(const or_problem *P, int i, const real *u, const rea
                 const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
                 real dx[OR_MAXDIM];
                 for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)j * D + d];
-                dx[0] = wrap(P, dx[0]);
+                for (int d = 0; d < D; ++d) dx[d] = wrap(P, d, dx[d]);
                 for (int var = 0; var < V; ++var) {
                     if (fallback && fallback[j])
                         up[var] = u[(size_t)var * P->nc + j];

@@ -11,6 +11,7 @@ WLSENO_OK = 0
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EUNSUPPORTED"}
 FLUX = {"advection": 0, "burgers": 1, "euler": 2}
 MESH_PERIODIC_1D = 1
+MESH_PERIODIC_2D = 2
 
 # every symbol include/wlseno.h declares
 EXPORTS = [

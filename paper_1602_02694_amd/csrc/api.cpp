@@ -175,6 +175,7 @@ void upload_build(wlseno_ctx *c)
     dm.alpha_w = b.prm.alpha_w;
     dm.rank_tol = b.prm.rank_tol;
     dm.period = m.periodic ? m.period : 0.0;
+    dm.period_y = m.periodic ? m.period_y : 0.0;
     dm.gamma = b.prm.gamma;
     dm.bc = b.prm.bc;
     dm.characteristic = b.prm.characteristic;

@@ -32,10 +32,10 @@ struct HostMesh {
     int dim = 0;
     int64_t nv = 0, nc = 0;
     bool periodic = false;
-    double period = 0.0;
+    double period = 0.0, period_y = 0.0;   // along x (1-D: the circle) and, 2-D, along y
     std::vector<double> xyz;         // nv*dim
     std::vector<int32_t> cells;      // nc*(dim+1), user vertex ids
-    std::vector<int32_t> vid;        // nc*(dim+1), periodic end node identified with node 0
+    std::vector<int32_t> vid;        // nc*(dim+1), periodic images identified (one id per point)
     std::vector<double> vol;         // nc
     std::vector<double> cent;        // nc*dim
     std::vector<int32_t> sib;        // nc*(dim+1): (cell << 2 | lf) of the sibling half-facet, or -1
@@ -113,7 +113,7 @@ struct DevMesh {
     int nbuckets = 0;
     int bucket_cap[kMaxBuckets] = {0, 0, 0};
     int64_t bucket_cell0[kMaxBuckets + 1] = {0, 0, 0, 0};
-    double eh2 = 0.0, alpha_w = 1.5, rank_tol = 1e-12, period = 0.0, gamma = 1.4;
+    double eh2 = 0.0, alpha_w = 1.5, rank_tol = 1e-12, period = 0.0, period_y = 0.0, gamma = 1.4;
     double vel[3] = {0, 0, 0};
     const double *geo = nullptr, *vrel = nullptr, *normal = nullptr, *rvol = nullptr;   // normal = |f| n
     const double *nsum = nullptr;   // [F][nc] sum_d n_d of the unit normal

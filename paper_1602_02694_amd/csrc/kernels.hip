@@ -285,7 +285,7 @@ struct RArgs {
     const int32_t *mid;              // batches: mesh of each cell (else null)
     const double *eh2_tab;           // batches: eps h^2 per mesh
     int spm;                         // alpha slots per mesh
-    double eh2, alpha_w, rank_tol, period, gamma;
+    double eh2, alpha_w, rank_tol, period, period_y, gamma;
     int weight_mode;
     double *bal_grad;                // balanced-stencil refit: gradients of the first fit
     unsigned long long *bal_count;   // and this stage's list length (read by the refit)
@@ -375,16 +375,20 @@ __device__ __forceinline__ void char_vectors(const double *u, const double *norm
 }
 
 // Centroid offset of a stencil cell (record gxs: centroid, then moments) from
-// x_c, wrapped into the period on a periodic line.
+// x_c, wrapped to the nearest periodic image on a periodic line (period) or
+// square (period along x, period_y along y).
 template <int DIM>
 __device__ __forceinline__ void centroid_offset(const double *gxs, const double (&xc)[DIM], double period,
-                                                double (&dl)[DIM])
+                                                double period_y, double (&dl)[DIM])
 {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) dl[d] = gxs[d] - xc[d];
-    if constexpr (DIM == 1) {
-        if (period > 0.0)
-            dl[0] = dl[0] > 0.5 * period ? dl[0] - period : (dl[0] < -0.5 * period ? dl[0] + period : dl[0]);
+    if constexpr (DIM <= 2) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const double L = d == 0 ? period : period_y;
+            if (L > 0.0) dl[d] = dl[d] > 0.5 * L ? dl[d] - L : (dl[d] < -0.5 * L ? dl[d] + L : dl[d]);
+        }
     }
 }
 
@@ -734,7 +738,7 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
         const int r = s * G + g;
         const bool valid = jrow[s] >= 0;
         double dl[DIM];
-        centroid_offset<DIM>(gx[s], xc, a.period, dl);
+        centroid_offset<DIM>(gx[s], xc, a.period, a.period_y, dl);
         const double uj = ug[s];
         double row[M];
         taylor_row<DIM, P>(dl, gx[s] + DIM, row);
@@ -1131,9 +1135,11 @@ __global__ void __launch_bounds__(recon_block(DIM)) k_rebalance(RArgs a, BArgs b
         for (int k = 0; k < 8; ++k) {
             const int r = rb + k * G;
             if (r == 0 || jj[k] < 0) continue;   // the centre; padding or past the end
+            double dl[DIM];
+            centroid_offset<DIM>(gx[k], xc, a.period, a.period_y, dl);
             double sd = 0.0;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) sd += gr[d] * (gx[k][d] - xc[d]);
+            for (int d = 0; d < DIM; ++d) sd += gr[d] * dl[d];
             const unsigned long long bit = 1ull << (r & 63);
             if (sd > 0.0)
                 mp[r >> 6] |= bit;
@@ -1196,7 +1202,7 @@ struct AArgs {
     const int32_t *spad, *sib;
     double *contrib;                   // contributions, in transposed-stencil order
     const int32_t *tpos;               // position in contrib of each padded slot, then of each facet slot
-    double eh2, alpha_w, rank_tol, period;
+    double eh2, alpha_w, rank_tol, period, period_y;
     int weight_mode, bc;
     double vel[3];
     int64_t cell0[kMaxBuckets + 1];
@@ -1260,7 +1266,7 @@ __device__ __forceinline__ void adjoint_cell(const AArgs &a, int64_t cell, int64
         const int r = s * G + g;
         const int64_t j = jrow[s] >= 0 ? (int64_t)jrow[s] : c;
         double dl[DIM];
-        centroid_offset<DIM>(a.geo + j * GS, xc, a.period, dl);
+        centroid_offset<DIM>(a.geo + j * GS, xc, a.period, a.period_y, dl);
         double row[M];
         taylor_row<DIM, P>(dl, a.geo + j * GS + DIM, row);
         const double uj = a.u[j];
@@ -1403,7 +1409,7 @@ __device__ __forceinline__ void adjoint_cell(const AArgs &a, int64_t cell, int64
         const bool valid = jrow[s] >= 0;
         const int64_t j = valid ? (int64_t)jrow[s] : c;
         double dl[DIM];
-        centroid_offset<DIM>(a.geo + j * GS, xc, a.period, dl);
+        centroid_offset<DIM>(a.geo + j * GS, xc, a.period, a.period_y, dl);
         double row[M];
         taylor_row<DIM, P>(dl, a.geo + j * GS + DIM, row);
         const double uj = a.u[j];
@@ -1902,6 +1908,7 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     a.alpha_w = dm.alpha_w;
     a.rank_tol = dm.rank_tol;
     a.period = dm.period;
+    a.period_y = dm.period_y;
     a.gamma = dm.gamma;
     a.weight_mode = dm.weight_mode;
     a.bal_grad = dm.bal_grad;
@@ -2035,6 +2042,7 @@ int launch_adjoint(const DevMesh &dm, const double *u, const double *v, const in
     a.alpha_w = dm.alpha_w;
     a.rank_tol = dm.rank_tol;
     a.period = dm.period;
+    a.period_y = dm.period_y;
     a.weight_mode = dm.weight_mode;
     a.bc = dm.bc;
     for (int d = 0; d < 3; ++d) a.vel[d] = dm.vel[d];

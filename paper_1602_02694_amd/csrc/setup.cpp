@@ -10,6 +10,8 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <string>
 #include <numeric>
 #include <utility>
 
@@ -63,9 +65,10 @@ void mesh_setup(HostMesh &out, int dim, int64_t nv, const double *xyz, int64_t n
     if (nv < dim + 1 || nc < 1) throw inval("mesh needs at least one cell and dim+1 vertices");
     if (nc > (int64_t)(INT32_MAX / 8) || nv > (int64_t)INT32_MAX)
         throw inval("mesh too large for 32-bit indices");
-    if (flags & ~WLSENO_MESH_PERIODIC_1D) throw inval("unknown mesh flags");
-    const bool periodic = (flags & WLSENO_MESH_PERIODIC_1D) != 0;
-    if (periodic && dim != 1) throw inval("WLSENO_MESH_PERIODIC_1D requires dim = 1");
+    if (flags & ~(WLSENO_MESH_PERIODIC_1D | WLSENO_MESH_PERIODIC_2D)) throw inval("unknown mesh flags");
+    if ((flags & WLSENO_MESH_PERIODIC_1D) && dim != 1) throw inval("WLSENO_MESH_PERIODIC_1D requires dim = 1");
+    if ((flags & WLSENO_MESH_PERIODIC_2D) && dim != 2) throw inval("WLSENO_MESH_PERIODIC_2D requires dim = 2");
+    const bool periodic = (flags & (WLSENO_MESH_PERIODIC_1D | WLSENO_MESH_PERIODIC_2D)) != 0;
 
     HostMesh m;
     m.dim = dim;
@@ -79,14 +82,53 @@ void mesh_setup(HostMesh &out, int dim, int64_t nv, const double *xyz, int64_t n
         if (m.cells[t] < 0 || m.cells[t] >= nv)
             throw inval("cell " + std::to_string(t / nvc) + " references vertex " +
                         std::to_string(m.cells[t]) + " out of range");
-    if (periodic) {
+    if (periodic && dim == 1) {
         m.period = xyz[nv - 1] - xyz[0];
         if (!(m.period > 0.0)) throw inval("periodic 1-D mesh: last node must lie right of the first");
     }
     m.vid = m.cells;
-    if (periodic)
+    if (periodic && dim == 1)
         for (auto &v : m.vid)
             if (v == nv - 1) v = 0;
+    if (periodic && dim == 2) {
+        // one id per point of the torus: a vertex on an upper side stands for
+        // its partner on the lower side (same other coordinate)
+        double lo[2] = {xyz[0], xyz[1]}, hi[2] = {xyz[0], xyz[1]};
+        for (int64_t v = 0; v < nv; ++v)
+            for (int d = 0; d < 2; ++d) {
+                lo[d] = std::min(lo[d], xyz[v * 2 + d]);
+                hi[d] = std::max(hi[d], xyz[v * 2 + d]);
+            }
+        m.period = hi[0] - lo[0];
+        m.period_y = hi[1] - lo[1];
+        if (!(m.period > 0.0) || !(m.period_y > 0.0)) throw inval("periodic 2-D mesh: degenerate bounding box");
+        const double tol[2] = {1e-12 * m.period, 1e-12 * m.period_y};
+        std::map<std::pair<double, double>, int32_t> rep;
+        std::vector<int32_t> ident(nv);
+        std::vector<char> upper(nv, 0);
+        for (int64_t v = 0; v < nv; ++v) {
+            double c[2];
+            for (int d = 0; d < 2; ++d) {
+                c[d] = xyz[v * 2 + d];
+                if (std::fabs(c[d] - lo[d]) <= tol[d]) c[d] = lo[d];
+                if (std::fabs(c[d] - hi[d]) <= tol[d]) upper[v] = 1;
+            }
+            if (!upper[v]) ident[v] = rep.emplace(std::make_pair(c[0], c[1]), (int32_t)v).first->second;
+        }
+        for (int64_t v = 0; v < nv; ++v) {
+            if (!upper[v]) continue;
+            double c[2];
+            for (int d = 0; d < 2; ++d) {
+                c[d] = xyz[v * 2 + d];
+                if (std::fabs(c[d] - lo[d]) <= tol[d] || std::fabs(c[d] - hi[d]) <= tol[d]) c[d] = lo[d];
+            }
+            auto it = rep.find(std::make_pair(c[0], c[1]));
+            if (it == rep.end())
+                throw inval("periodic 2-D mesh: vertex " + std::to_string(v) + " on an upper side has no partner");
+            ident[v] = it->second;
+        }
+        for (auto &v : m.vid) v = ident[v];
+    }
 
     // measures and centroids
     m.vol.resize(nc);
@@ -292,8 +334,8 @@ double sqdist(const HostMesh &m, int64_t i, int64_t j)
     double d2 = 0.0;
     for (int d = 0; d < m.dim; ++d) {
         double dx = m.cent[j * m.dim + d] - m.cent[i * m.dim + d];
-        if (m.periodic) {
-            double L = m.period;
+        const double L = m.periodic ? (d == 0 ? m.period : (d == 1 ? m.period_y : 0.0)) : 0.0;
+        if (L > 0.0) {
             if (dx > 0.5 * L)
                 dx -= L;
             else if (dx < -0.5 * L)

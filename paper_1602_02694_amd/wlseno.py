@@ -66,7 +66,8 @@ class WLSENO:
         c = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, dim + 1))
         self._check(self._lib.wlseno_mesh_upload(
             self._h, int(dim), v.shape[0], v.ctypes.data_as(C.POINTER(C.c_double)), c.shape[0],
-            c.ctypes.data_as(C.POINTER(C.c_int32)), N.MESH_PERIODIC_1D if periodic else 0))
+            c.ctypes.data_as(C.POINTER(C.c_int32)),
+            (N.MESH_PERIODIC_1D if dim == 1 else N.MESH_PERIODIC_2D) if periodic else 0))
         self.dim = int(dim)
         self.n_cell = int(c.shape[0])
 

@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import riemann
-from workloads import jittered_square, fields
+from workloads import jittered_square, jittered_square_periodic, fields
 
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +45,7 @@ def _advance(mesh, u0, T, **kw):
     from paper_1602_02694_amd import WLSENO
 
     w = WLSENO(device=0)
-    w.mesh_upload(2, mesh.verts, mesh.cells)
+    w.mesh_upload(2, mesh.verts, mesh.cells, mesh.periodic)
     w.stencil_build(flux="euler", **kw)
     u = torch.tensor(u0.reshape(-1), device="cuda")
     w.rhs(u)
@@ -72,6 +72,26 @@ def test_vortex_convergence(p, n_lo, n_hi, char, min_order, max_err):
         errs.append(float(np.sum(A * np.abs(u[0] - exact[0])) / A.sum()))
     orders = [np.log2(errs[k] / errs[k + 1]) for k in range(2)]
     print(f"[vortex p={p} char={char}] L1 {errs} orders {orders}", flush=True)
+    assert min(orders) >= min_order
+    assert errs[-1] <= max_err
+
+
+@pytest.mark.parametrize("p,n_lo,n_hi,char,min_order,max_err", [
+    (3, 12, 20, False, 1.8, 2.5e-4),
+    (5, 24, 30, True, 3.3, 1.0e-5),
+])
+def test_vortex_convergence_periodic(p, n_lo, n_hi, char, min_order, max_err):
+    """The paper's own set-up: [0,10]^2 extended periodically."""
+    errs = []
+    for n in (21, 41, 81):
+        mesh = jittered_square_periodic(n, 0.3, 6100 + n, lo=0.0, hi=10.0)
+        u0 = fields.cell_averages(mesh, fields.isentropic_vortex(0.0))
+        exact = fields.cell_averages(mesh, fields.isentropic_vortex(1.0))
+        u = _advance(mesh, u0, 1.0, p=p, n_lo=n_lo, n_hi=n_hi, characteristic=char)
+        A = _areas(mesh)
+        errs.append(float(np.sum(A * np.abs(u[0] - exact[0])) / A.sum()))
+    orders = [np.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    print(f"[vortex periodic p={p} char={char}] L1 {errs} orders {orders}", flush=True)
     assert min(orders) >= min_order
     assert errs[-1] <= max_err
 

@@ -10,7 +10,8 @@ import pytest
 
 from parity import (assert_parity, assert_poly_parity, cell_conditions, cell_noise, char_cell_conditions, flux_scale,
                     floor_tol, momentum_scale, neighbourhood_max)
-from workloads import configs, periodic_line, uniform_periodic_line, jittered_cube, jittered_square, fields
+from workloads import (configs, periodic_line, uniform_periodic_line, jittered_cube, jittered_square,
+                       jittered_square_periodic, fields)
 
 pytestmark = pytest.mark.gpu
 
@@ -395,6 +396,23 @@ def test_balanced_refit(dim):
     assert np.all(ora_changed <= ref["rebalanced"].astype(bool))
     assert np.array_equal(gpu_changed, ora_changed)
     _compare_all(mesh, u0, 3, None, f"balance{dim}d", balance=True, **kw)
+
+
+def test_torus_burgers():
+    """Doubly periodic mesh: facet neighbours and stencils wrap around."""
+    mesh = jittered_square_periodic(16, 0.3, 3121)
+    u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+    w, o = _compare_all(mesh, u0, 10, 0.002, "torus16-burgers", p=3, n_lo=12, n_hi=20, flux="burgers")
+    assert o.mesh.nbr.min() >= 0
+
+
+@pytest.mark.parametrize("p,n_lo,n_hi,char", [(3, 12, 20, False), (5, 24, 30, True)])
+def test_torus_vortex(p, n_lo, n_hi, char):
+    """The isentropic vortex on the periodic square [0,10]^2 (Sec. 5.2.3)."""
+    mesh = jittered_square_periodic(13, 0.3, 3122, lo=0.0, hi=10.0)
+    u0 = fields.cell_averages(mesh, fields.isentropic_vortex(0.0))
+    _compare_all(mesh, u0, 4, None, f"torus13-vortex-p{p}-char{int(char)}", p=p, n_lo=n_lo, n_hi=n_hi,
+                 flux="euler", characteristic=char)
 
 
 FREE_STREAM = (1.0, 1.0, 1.0, 1.0 / 0.4 + 1.0)   # rho = p = 1, velocity (1, 1)

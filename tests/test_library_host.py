@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from conftest import ROOT
-from workloads import periodic_line, jittered_square, jittered_cube, configs
+from workloads import periodic_line, jittered_square, jittered_square_periodic, jittered_cube, configs
 
 
 @pytest.fixture(scope="module")
@@ -49,7 +49,7 @@ def _host_ctx(mesh, **kw):
     return w
 
 
-@pytest.mark.parametrize("case", ["line", "square", "square_p4", "square_p5", "cube"])
+@pytest.mark.parametrize("case", ["line", "square", "square_p4", "square_p5", "cube", "torus", "torus_p5"])
 def test_stencils_equal_oracle(lib, case):
     from oracle.mesh import OracleMesh
 
@@ -61,6 +61,10 @@ def test_stencils_equal_oracle(lib, case):
         mesh, kw = jittered_square(16, 0.3, 3001), dict(p=4, n_lo=20, n_hi=36)
     elif case == "square_p5":
         mesh, kw = jittered_square(16, 0.3, 3002), dict(p=5, n_lo=24, n_hi=30)
+    elif case == "torus":
+        mesh, kw = jittered_square_periodic(20, 0.3, 2003), dict(p=3, n_lo=12, n_hi=20)
+    elif case == "torus_p5":
+        mesh, kw = jittered_square_periodic(14, 0.3, 2004), dict(p=5, n_lo=24, n_hi=30)
     else:
         mesh, kw = jittered_cube(6, 0.15, 4001), dict(p=3, n_lo=30, n_hi=50)
     w = _host_ctx(mesh, **kw)
@@ -106,9 +110,14 @@ def test_error_paths(lib):
     with pytest.raises(WLSENOError) as e:
         w.mesh_upload(2, np.zeros((0, 2)), np.zeros((0, 3), dtype=np.int32))
     assert e.value.status == 1 and "at least one cell" in str(e.value)
-    # periodic flag outside 1-D
-    with pytest.raises(WLSENOError):
+    # a square whose opposite sides do not match is no torus
+    with pytest.raises(WLSENOError) as e:
         w.mesh_upload(2, mesh.verts, mesh.cells, periodic=True)
+    assert "no partner" in str(e.value)
+    # periodic flags outside their dimension
+    cube = jittered_cube(3, 0.0, 1)
+    with pytest.raises(WLSENOError):
+        w.mesh_upload(3, cube.verts, cube.cells, periodic=True)
     # stencil before mesh / reversed size rule / too few coefficients
     w2 = WLSENO(device=-1)
     with pytest.raises(WLSENOError) as e:

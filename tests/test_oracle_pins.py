@@ -517,3 +517,49 @@ def test_far_field_and_slip_wall_boundaries():
     assert abs(np.sum(vol * Lw[3])) < 1e-12 * scale[3]
     # momentum is not conserved: the walls push back with the pressure
     assert abs(np.sum(vol * Lw[1])) > 1e-6 * scale[1]
+
+
+@pytest.mark.parametrize("flux", ["burgers", "euler"])
+def test_torus_conservation_and_free_stream(flux):
+    """On a doubly periodic mesh every facet has a neighbour: the total of
+    |tau| L vanishes to rounding for any data, and a uniform state is steady."""
+    import oracle
+    from workloads import jittered_square_periodic
+
+    mesh = jittered_square_periodic(12, 0.3, 45)
+    o = oracle.Oracle(2, mesh.verts, mesh.cells, True, p=3, n_lo=12, n_hi=20, flux=flux)
+    assert (o.mesh.nbr < 0).sum() == 0
+    if flux == "euler":
+        u = fields.cell_averages(mesh, fields.euler_quadrants(46))
+        U = np.array([0.8, 0.24, -0.16, 2.6])
+        uu = np.repeat(U[:, None], o.nc, axis=1)
+    else:
+        u = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)[None]
+        uu = np.full((1, o.nc), 0.7)
+    L, _ = o.rhs(u)
+    tot = np.sum(o.mesh.vol * L, axis=1)
+    assert np.all(np.abs(tot) < 1e-13 * np.max(np.abs(L), axis=1) * o.mesh.vol.sum())
+    L0, _ = o.rhs(uu)
+    assert np.max(np.abs(L0)) < 1e-10
+
+
+def test_torus_linear_advection_is_translation_invariant():
+    """Advecting a periodic field across a whole period on the torus returns
+    it close to its start, and shrinking the cells shrinks the error at
+    second order or better (the paper's 2-D wave equation runs on a periodic
+    square, Sec. 5.2.1)."""
+    import oracle
+    from workloads import jittered_square_periodic
+
+    errs = []
+    for n in (13, 25):
+        mesh = jittered_square_periodic(n, 0.3, 47 + n)
+        fn = lambda x: np.sin(2 * np.pi * x[:, 0]) * np.sin(2 * np.pi * x[:, 1])
+        u0 = fields.cell_averages(mesh, fn)
+        o = oracle.Oracle(2, mesh.verts, mesh.cells, True, p=3, n_lo=12, n_hi=20, flux="advection",
+                          velocity=(1.0, 0.0, 0.0))
+        dt0 = 0.25 * (1.0 / (n - 1))
+        steps = int(np.ceil(1.0 / dt0))
+        u = o.step(u0, 1.0 / steps, steps)[0]
+        errs.append(np.sum(o.mesh.vol * np.abs(u - u0)))
+    assert errs[1] < errs[0] / 3.0

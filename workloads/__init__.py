@@ -9,7 +9,7 @@ Every generator is deterministic for a given seed (numpy PCG64 via
 ``numpy.random.default_rng``).
 """
 
-from .meshes import Mesh, periodic_line, uniform_periodic_line, jittered_square, jittered_cube
+from .meshes import Mesh, periodic_line, uniform_periodic_line, jittered_square, jittered_square_periodic, jittered_cube
 from .fields import (
     cell_averages,
     line_cell_averages,
@@ -27,6 +27,7 @@ __all__ = [
     "periodic_line",
     "uniform_periodic_line",
     "jittered_square",
+    "jittered_square_periodic",
     "jittered_cube",
     "cell_averages",
     "line_cell_averages",

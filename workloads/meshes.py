@@ -40,8 +40,11 @@ class Mesh:
 
     @property
     def period(self) -> float:
+        """1-D: the circle's length; 2-D: the period along x."""
         if not self.periodic:
             return 0.0
+        if self.dim == 2:
+            return float(self.meta["periods"][0])
         return float(self.verts[-1, 0] - self.verts[0, 0])
 
 
@@ -115,6 +118,36 @@ def jittered_square(n_per_side: int, jitter: float = 0.3, seed: int = 2001,
     tri = Delaunay(pts)
     cells = _orient(pts, tri.simplices.astype(np.int64))
     return Mesh(2, pts, cells, name=f"square{n_per_side}_j{jitter}_s{seed}")
+
+
+def jittered_square_periodic(n_per_side: int, jitter: float = 0.3, seed: int = 2001,
+                             lo: float = 0.0, hi: float = 1.0) -> Mesh:
+    """Delaunay triangulation of an ``n x n`` jittered lattice on ``[lo,hi]^2``
+    whose opposite boundaries carry identical points (a boundary point slides
+    along its edge by the same amount as its partner across the square), so
+    the mesh closes into a doubly periodic one.  ``meta["periods"]`` holds
+    ``(hi - lo, hi - lo)``."""
+    from scipy.spatial import Delaunay
+
+    rng = np.random.default_rng(seed)
+    n = n_per_side
+    s = (hi - lo) / (n - 1)
+    g = lo + np.arange(n) * s
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    noise = rng.uniform(-jitter * s, jitter * s, size=(n, n, 2))
+    noise[n - 1, :, 1] = noise[0, :, 1]       # x = hi copies the slide of x = lo
+    noise[:, n - 1, 0] = noise[:, 0, 0]       # y = hi copies the slide of y = lo
+    noise[0, :, 0] = noise[n - 1, :, 0] = 0.0
+    noise[:, 0, 1] = noise[:, n - 1, 1] = 0.0
+    X = X + noise[:, :, 0]
+    Y = Y + noise[:, :, 1]
+    X[0, :], X[n - 1, :] = lo, hi
+    Y[:, 0], Y[:, n - 1] = lo, hi
+    pts = np.stack([X.ravel(), Y.ravel()], axis=1)
+    tri = Delaunay(pts)
+    cells = _orient(pts, tri.simplices.astype(np.int64))
+    return Mesh(2, pts, cells, periodic=True, name=f"torus{n_per_side}_j{jitter}_s{seed}",
+                meta={"periods": (hi - lo, hi - lo)})
 
 
 def jittered_cube(n_per_side: int, jitter: float = 0.15, seed: int = 4001,
