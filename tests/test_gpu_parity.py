@@ -571,8 +571,9 @@ def test_batch_errors():
 
 @pytest.mark.parametrize("case", ["single", "batch"])
 def test_graph_replays_equal_direct_launches(case):
-    """Steps replayed from the captured graph equal directly launched steps
-    bit for bit, over several replays with other device work in between."""
+    """Steps replayed from the captured graphs (32-step and 2-step) equal
+    directly launched steps bit for bit, over several replays with other
+    device work in between."""
     torch = _torch()
     from paper_1602_02694_amd import WLSENO
 
@@ -601,7 +602,8 @@ def test_graph_replays_equal_direct_launches(case):
         stepper = lambda w, u, n: w.batch_step(u, dts, n)
     ug = torch.tensor(np.asarray(u0).reshape(-1), device="cuda")
     ud = ug.clone()
-    for n in (4, 5, 2, 3):
+    # 70 = two 32-step replays + three pairs; 33 = one 32-step replay + a direct step
+    for n in (4, 5, 2, 3, 70, 33):
         stepper(ctxs[0], ug, n)
         stepper(ctxs[1], ud, n)
         torch.cuda.synchronize()
