@@ -122,6 +122,11 @@ typedef struct {
                             cells on the gradient's side and floor((n-1)/2) on the other (a
                             short side leaves its share to the other), n its own stencil
                             size.  The lanes setting is then automatic. */
+    int32_t lf_alpha;    /* Lax-Friedrichs alpha of Burgers and Euler: 0 = one global bound per
+                            stage (per mesh in a batch), the maximum over all facet points of
+                            the normal spectral radius; 1 = local (Rusanov): at each facet
+                            point the larger spectral radius of its two states.  Linear
+                            advection always uses |a.n| per facet. */
 } wlseno_params;
 
 typedef struct {

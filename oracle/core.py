@@ -97,6 +97,7 @@ class _Problem(C.Structure):
         ("pool_col", C.POINTER(C.c_int)),
         ("balance", C.c_int),
         ("period_y", C.c_double),
+        ("lf_alpha", C.c_int),
     ]
 
 
@@ -173,7 +174,7 @@ class Oracle:
     def __init__(self, dim, verts, cells, periodic=False, *, p=3, n_lo=None, n_hi=None,
                  flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2, alpha_w=1.5,
                  rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None, extended=False, bc=0,
-                 characteristic=False, far_state=None, balance=False):
+                 characteristic=False, far_state=None, balance=False, lf_alpha=0):
         self.extended = bool(extended)
         self.mesh = OracleMesh(dim, verts, cells, periodic, p=p)
         om = self.mesh
@@ -235,6 +236,7 @@ class Oracle:
             self.pool_col = np.ascontiguousarray(pool[1], dtype=np.int32)
             P.pool_ptr, P.pool_col = _ip(self.pool_ptr), _ip(self.pool_col)
         P.balance = int(bool(balance))
+        P.lf_alpha = int(lf_alpha)
         self._P = P
         self._lib = lib(self.extended)
         self.flux = flux

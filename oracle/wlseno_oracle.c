@@ -73,6 +73,7 @@ typedef struct {
     const int *pool_col;
     int balance;          /* scalar fluxes: refit out-of-range cells on a balanced stencil */
     double period_y;      /* 2-D periodic meshes: period along y (period: along x) */
+    int lf_alpha;         /* 1: local (Rusanov) alpha per facet point for Burgers and Euler */
 } or_problem;
 
 /* Threads the per-cell loops use (1 without OpenMP). */
@@ -900,7 +901,13 @@ static void divergence_cell(const or_problem *P, int i, const real *u, const rea
                 }
             }
             real a = alpha;
-            if (P->flux == OR_ADVECTION) a = spectral_radius(P, um, n);
+            if (P->flux == OR_ADVECTION) {
+                a = spectral_radius(P, um, n);
+            } else if (P->lf_alpha == 1) {
+                /* local (Rusanov): the larger spectral radius of the two states */
+                real ra = spectral_radius(P, um, n), rb = spectral_radius(P, up, n);
+                a = ra > rb ? ra : rb;
+            }
             lf_flux(P, um, up, n, a, fh);
             for (int var = 0; var < V; ++var) facc[var] += (real)P->qw[q] * fh[var];
         }

@@ -187,6 +187,7 @@ void upload_build(wlseno_ctx *c)
     dm.gamma = b.prm.gamma;
     dm.bc = b.prm.bc;
     dm.characteristic = b.prm.characteristic;
+    dm.lf_alpha = b.prm.lf_alpha;
     for (int v = 0; v < 5; ++v) dm.far[v] = b.prm.far_state[v];
     for (int d = 0; d < 3; ++d) dm.vel[d] = b.prm.velocity[d];
     if (b.prm.balance) {
@@ -320,6 +321,7 @@ void wlseno_params_default(wlseno_params *out)
     out->bc = 0;
     out->characteristic = 0;
     out->balance = 0;
+    out->lf_alpha = 0;
     for (int v = 0; v < 5; ++v) out->far_state[v] = 0.0;
 }
 

@@ -99,6 +99,7 @@ struct DevMesh {
     int flux = 0, weight_mode = 0, max_stencil = 0;
     int bc = 0;   // boundary facets: 0 outside state = inside state, 1 outside state = 0
     int characteristic = 0;   // Euler: reconstruct characteristic fields per facet
+    int lf_alpha = 0;         // 1: local Lax-Friedrichs (Rusanov) alpha per facet point
     double far[5] = {0, 0, 0, 0, 0};   // bc = 2: outside state
     // balanced-stencil refit: enlarged stencils, the refit list of each stage
     // parity (count at bal_count[parity * 16]) and the listed cells' gradients

@@ -1516,7 +1516,8 @@ struct UArgs {
     double gamma;
     int mode;
     int bc;
-    double far[5];   // bc = 2: outside state
+    int local_alpha;   // 1: Rusanov alpha per facet point
+    double far[5];     // bc = 2: outside state
 };
 
 // Euler normal flux F(U).m for the area-scaled normal m (linear in m).
@@ -1569,6 +1570,39 @@ __device__ __forceinline__ void lf_flux(const double (&ua)[V], const double (&ub
         euler_flux<DIM, V>(ub, m, gamma, fb);
 #pragma unroll
         for (int v = 0; v < V; ++v) out[v] = 0.5 * ((fa[v] + fb[v]) - af * (ub[v] - ua[v]));
+    }
+}
+
+// Local (Rusanov) alpha at a facet point: the larger normal spectral radius of
+// its two states, for the area-scaled normal m (per unit normal).
+template <int DIM, int FLUX, int V>
+__device__ __forceinline__ double point_alpha(const double (&ua)[V], const double (&ub)[V], const double (&m)[DIM],
+                                              double gamma)
+{
+    double mm = 0.0, sm = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        mm += m[d] * m[d];
+        sm += m[d];
+    }
+    const double im = 1.0 / sqrt(mm);
+    if constexpr (FLUX == kFluxBurgers) {
+        return fmax(fabs(ua[0] * sm), fabs(ub[0] * sm)) * im;
+    } else {
+        double r[2];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const double *U = side == 0 ? ua : ub;
+            double vm = 0.0, ke = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                vm += U[1 + d] * m[d];
+                ke += U[1 + d] * U[1 + d];
+            }
+            const double pr = (gamma - 1.0) * (U[DIM + 1] - 0.5 * ke / U[0]);
+            r[side] = fabs(vm / U[0]) * im + sqrt(gamma * pr / U[0]);
+        }
+        return fmax(r[0], r[1]);
     }
 }
 
@@ -1667,7 +1701,11 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
                         ux[DIM + 1] = uo[DIM + 1];
                     }
                 }
-                lf_flux<DIM, FLUX, V>(uo, ux, m[lf], alpha, vel, a.gamma, fl);
+                double al = alpha;
+                if constexpr (FLUX != kFluxAdv) {
+                    if (a.local_alpha) al = point_alpha<DIM, FLUX, V>(uo, ux, m[lf], a.gamma);
+                }
+                lf_flux<DIM, FLUX, V>(uo, ux, m[lf], al, vel, a.gamma, fl);
 #pragma unroll
                 for (int v = 0; v < V; ++v) facc[v] += quad_weight<DIM, Q>(q) * fl[v];
             }
@@ -1698,7 +1736,11 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
                     ua[v] = ow ? own[v][lf][q] : oth_q;
                     ub[v] = ow ? oth_qo : own_qo;
                 }
-                lf_flux<DIM, FLUX, V>(ua, ub, mm, alpha, vel, a.gamma, fl);
+                double al = alpha;
+                if constexpr (FLUX != kFluxAdv) {
+                    if (a.local_alpha) al = point_alpha<DIM, FLUX, V>(ua, ub, mm, a.gamma);
+                }
+                lf_flux<DIM, FLUX, V>(ua, ub, mm, al, vel, a.gamma, fl);
 #pragma unroll
                 for (int v = 0; v < V; ++v) facc[v] += quad_weight<DIM, Q>(q) * fl[v];
             }
@@ -2006,6 +2048,7 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
     a.mode = mode;
     a.bc = dm.bc;
     for (int v = 0; v < 5; ++v) a.far[v] = dm.far[v];
+    a.local_alpha = dm.lf_alpha;
     hipStream_t st = (hipStream_t)stream;
     if (dm.dim == 1) return launch_k23<1, 1>(dm, a, st);
     if (dm.dim == 2) {

@@ -490,6 +490,7 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
     if (prm.characteristic && prm.flux != WLSENO_FLUX_EULER)
         throw inval("characteristic = 1 applies to the Euler system only");
     if (prm.balance != 0 && prm.balance != 1) throw inval("balance must be 0 or 1");
+    if (prm.lf_alpha != 0 && prm.lf_alpha != 1) throw inval("lf_alpha must be 0 or 1");
     if (prm.balance && prm.flux == WLSENO_FLUX_EULER) throw inval("balance = 1 applies to scalar fluxes only");
     if (prm.balance && !((dim == 2 || dim == 3) && prm.p == 3))
         throw Error{WLSENO_EUNSUPPORTED, "balanced stencils are compiled for p = 3 in 2-D and 3-D"};

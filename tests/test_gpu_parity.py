@@ -415,6 +415,19 @@ def test_torus_vortex(p, n_lo, n_hi, char):
                  flux="euler", characteristic=char)
 
 
+@pytest.mark.parametrize("flux", ["burgers", "euler"])
+def test_local_alpha(flux):
+    """Local (Rusanov) Lax-Friedrichs alpha at every facet point."""
+    mesh = jittered_square(14, 0.3, 3125)
+    if flux == "euler":
+        u0 = fields.cell_averages(mesh, fields.euler_quadrants(4125))
+        kw = dict(p=4, n_lo=20, n_hi=36, flux="euler")
+    else:
+        u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+        kw = dict(p=3, n_lo=12, n_hi=20, flux="burgers")
+    _compare_all(mesh, u0, 4, None, f"local-alpha-{flux}", lf_alpha=1, **kw)
+
+
 FREE_STREAM = (1.0, 1.0, 1.0, 1.0 / 0.4 + 1.0)   # rho = p = 1, velocity (1, 1)
 
 

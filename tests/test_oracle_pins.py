@@ -563,3 +563,31 @@ def test_torus_linear_advection_is_translation_invariant():
         u = o.step(u0, 1.0 / steps, steps)[0]
         errs.append(np.sum(o.mesh.vol * np.abs(u - u0)))
     assert errs[1] < errs[0] / 3.0
+
+
+@pytest.mark.parametrize("flux", ["burgers", "euler"])
+def test_local_alpha_conserves_and_dissipates_less(flux):
+    """Local (Rusanov) alpha: still exactly conservative on a closed torus,
+    the same as the global bound where every facet point attains it, and
+    never more dissipative: its alpha at a point is at most the global one."""
+    import oracle
+    from workloads import jittered_square_periodic
+
+    mesh = jittered_square_periodic(12, 0.3, 49)
+    kw = dict(p=3, n_lo=12, n_hi=20, flux=flux)
+    if flux == "euler":
+        u = fields.cell_averages(mesh, fields.euler_quadrants(50))
+    else:
+        u = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)[None]
+    og = oracle.Oracle(2, mesh.verts, mesh.cells, True, **kw)
+    ol = oracle.Oracle(2, mesh.verts, mesh.cells, True, lf_alpha=1, **kw)
+    Lg, ag = og.rhs(u)
+    Ll, al = ol.rhs(u)
+    assert al == ag                                   # the reported bound is the global one
+    tot = np.sum(ol.mesh.vol * Ll, axis=1)
+    assert np.all(np.abs(tot) < 1e-13 * np.max(np.abs(Ll), axis=1) * ol.mesh.vol.sum())
+    assert np.max(np.abs(Ll - Lg)) > 1e-6 * np.max(np.abs(Lg))
+    # a uniform state: both modes give zero
+    U = np.array([0.9, 0.2, -0.3, 2.7]) if flux == "euler" else np.array([0.6])
+    uu = np.repeat(U[:, None], ol.nc, axis=1)
+    assert np.max(np.abs(ol.rhs(uu)[0])) < 1e-10
