@@ -127,6 +127,9 @@ typedef struct {
                             the normal spectral radius; 1 = local (Rusanov): at each facet
                             point the larger spectral radius of its two states.  Linear
                             advection always uses |a.n| per facet. */
+    int32_t h_mode;      /* h in eps h^2: 0 = the mesh-mean edge length (per mesh in a batch;
+                            1-D: mean width); 1 = each cell's own mean edge length (1-D: its
+                            width).  The adjoint requires 0 (EUNSUPPORTED otherwise). */
 } wlseno_params;
 
 typedef struct {

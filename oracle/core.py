@@ -98,6 +98,7 @@ class _Problem(C.Structure):
         ("balance", C.c_int),
         ("period_y", C.c_double),
         ("lf_alpha", C.c_int),
+        ("h_cell", C.POINTER(C.c_double)),
     ]
 
 
@@ -174,7 +175,7 @@ class Oracle:
     def __init__(self, dim, verts, cells, periodic=False, *, p=3, n_lo=None, n_hi=None,
                  flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2, alpha_w=1.5,
                  rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None, extended=False, bc=0,
-                 characteristic=False, far_state=None, balance=False, lf_alpha=0):
+                 characteristic=False, far_state=None, balance=False, lf_alpha=0, h_mode=0):
         self.extended = bool(extended)
         self.mesh = OracleMesh(dim, verts, cells, periodic, p=p)
         om = self.mesh
@@ -237,6 +238,10 @@ class Oracle:
             P.pool_ptr, P.pool_col = _ip(self.pool_ptr), _ip(self.pool_col)
         P.balance = int(bool(balance))
         P.lf_alpha = int(lf_alpha)
+        if h_mode:
+            # h_i: the mean length of cell i's edges (1-D: its width)
+            self.h_cell = np.ascontiguousarray(om.cell_mean_edge(), dtype=np.float64)
+            P.h_cell = _dp(self.h_cell)
         self._P = P
         self._lib = lib(self.extended)
         self.flux = flux

@@ -86,6 +86,15 @@ class OracleMesh:
         self.vol = np.ascontiguousarray(vol)
         self.cent = np.ascontiguousarray(_seq_sum([cv[:, v] for v in range(d + 1)]) / (d + 1))
 
+    def cell_mean_edge(self):
+        """Mean length of each cell's edges (1-D: the cell's width)."""
+        if self.dim == 1:
+            return self.vol.copy()
+        cv = self.cv
+        nv = self.dim + 1
+        lens = [np.sqrt(((cv[:, w] - cv[:, v]) ** 2).sum(axis=1)) for v in range(nv) for w in range(v + 1, nv)]
+        return np.mean(np.stack(lens), axis=0)
+
     def vid(self, v):
         """Vertex id with periodic images identified (1-D: the end node is
         node 0; 2-D: a vertex on the upper x or y side is its partner on the

@@ -74,6 +74,7 @@ typedef struct {
     int balance;          /* scalar fluxes: refit out-of-range cells on a balanced stencil */
     double period_y;      /* 2-D periodic meshes: period along y (period: along x) */
     int lf_alpha;         /* 1: local (Rusanov) alpha per facet point for Burgers and Euler */
+    const double *h_cell; /* nullable: h in eps h^2 per cell (else the mesh's h) */
 } or_problem;
 
 /* Threads the per-cell loops use (1 without OpenMP). */
@@ -242,7 +243,7 @@ static void weights_from_values(const or_problem *P, int i, int n, const int *ro
         for (int r = 0; r < n; ++r) w[r] = 1.0;
         return;
     }
-    real h = P->h;
+    real h = P->h_cell ? (real)P->h_cell[i] : (real)P->h;
     real eh2 = (real)P->eps * h * h;
     /* beta of the centre: the smallest indicator among its facet neighbours */
     real beta_i = -1.0;

@@ -28,7 +28,7 @@ class Params(C.Structure):
         ("p", C.c_int32), ("n_lo", C.c_int32), ("n_hi", C.c_int32), ("flux", C.c_int32),
         ("weight_mode", C.c_int32), ("lanes", C.c_int32),
         ("eps", C.c_double), ("alpha_w", C.c_double), ("rank_tol", C.c_double),
-        ("velocity", C.c_double * 3), ("gamma", C.c_double), ("bc", C.c_int32), ("characteristic", C.c_int32), ("far_state", C.c_double * 5), ("balance", C.c_int32), ("lf_alpha", C.c_int32),
+        ("velocity", C.c_double * 3), ("gamma", C.c_double), ("bc", C.c_int32), ("characteristic", C.c_int32), ("far_state", C.c_double * 5), ("balance", C.c_int32), ("lf_alpha", C.c_int32), ("h_mode", C.c_int32),
     ]
 
 

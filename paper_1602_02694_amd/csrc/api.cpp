@@ -188,6 +188,7 @@ void upload_build(wlseno_ctx *c)
     dm.bc = b.prm.bc;
     dm.characteristic = b.prm.characteristic;
     dm.lf_alpha = b.prm.lf_alpha;
+    if (b.prm.h_mode == 1) dm.eh2_cell = upload(c, b.eh2_cell);
     for (int v = 0; v < 5; ++v) dm.far[v] = b.prm.far_state[v];
     for (int d = 0; d < 3; ++d) dm.vel[d] = b.prm.velocity[d];
     if (b.prm.balance) {
@@ -322,6 +323,7 @@ void wlseno_params_default(wlseno_params *out)
     out->characteristic = 0;
     out->balance = 0;
     out->lf_alpha = 0;
+    out->h_mode = 0;
     for (int v = 0; v < 5; ++v) out->far_state[v] = 0.0;
 }
 

@@ -87,6 +87,8 @@ struct Build {
     // first, pool_cap entries per cell (-1 padding)
     std::vector<int32_t> pool;
     int pool_cap = 0;
+    // h_mode 1: eps h_i^2 per device cell, h_i the cell's mean edge length
+    std::vector<double> eh2_cell;
 };
 
 void mesh_setup(HostMesh &mesh, int dim, int64_t nv, const double *xyz, int64_t nc,
@@ -100,6 +102,7 @@ struct DevMesh {
     int bc = 0;   // boundary facets: 0 outside state = inside state, 1 outside state = 0
     int characteristic = 0;   // Euler: reconstruct characteristic fields per facet
     int lf_alpha = 0;         // 1: local Lax-Friedrichs (Rusanov) alpha per facet point
+    const double *eh2_cell = nullptr;   // h_mode 1: eps h_i^2 per cell
     double far[5] = {0, 0, 0, 0, 0};   // bc = 2: outside state
     // balanced-stencil refit: enlarged stencils, the refit list of each stage
     // parity (count at bal_count[parity * 16]) and the listed cells' gradients

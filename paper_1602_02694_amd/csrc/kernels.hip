@@ -284,6 +284,7 @@ struct RArgs {
     unsigned long long *alpha_acc;   // this stage's parity: nmesh x spm slots (stride 16)
     const int32_t *mid;              // batches: mesh of each cell (else null)
     const double *eh2_tab;           // batches: eps h^2 per mesh
+    const double *eh2_cell;          // h_mode 1: eps h_i^2 per cell (else null)
     int spm;                         // alpha slots per mesh
     double eh2, alpha_w, rank_tol, period, period_y, gamma;
     int weight_mode;
@@ -630,7 +631,7 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     const int32_t *srow = spad + (c - cell_begin) * stride;
     const int64_t N = a.nc;
     const int32_t mesh = a.mid ? a.mid[c] : 0;
-    const double eh2 = a.mid ? a.eh2_tab[mesh] : a.eh2;
+    const double eh2 = a.eh2_cell ? a.eh2_cell[c] : (a.mid ? a.eh2_tab[mesh] : a.eh2);
 
     const double *gc = a.geo + c * GS;
     double xc[DIM];
@@ -1945,6 +1946,7 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     a.alpha_acc = dm.alpha + (size_t)parity * dm.alpha_slots() * 16;
     a.mid = dm.mid;
     a.eh2_tab = dm.eh2_tab;
+    a.eh2_cell = dm.eh2_cell;
     a.spm = dm.slots_per_mesh;
     a.eh2 = dm.eh2;
     a.alpha_w = dm.alpha_w;
@@ -2062,7 +2064,8 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
 
 bool adjoint_supported(const DevMesh &dm)
 {
-    return dm.flux == WLSENO_FLUX_ADVECTION && dm.nvars == 1 && dm.nmesh == 1 && !dm.balance && reconstruct_supported(dm);
+    return dm.flux == WLSENO_FLUX_ADVECTION && dm.nvars == 1 && dm.nmesh == 1 && !dm.balance && !dm.eh2_cell &&
+           reconstruct_supported(dm);
 }
 
 int launch_adjoint(const DevMesh &dm, const double *u, const double *v, const int32_t *tpos, double *contrib,

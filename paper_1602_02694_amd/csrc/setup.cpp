@@ -491,6 +491,7 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
         throw inval("characteristic = 1 applies to the Euler system only");
     if (prm.balance != 0 && prm.balance != 1) throw inval("balance must be 0 or 1");
     if (prm.lf_alpha != 0 && prm.lf_alpha != 1) throw inval("lf_alpha must be 0 or 1");
+    if (prm.h_mode != 0 && prm.h_mode != 1) throw inval("h_mode must be 0 or 1");
     if (prm.balance && prm.flux == WLSENO_FLUX_EULER) throw inval("balance = 1 applies to scalar fluxes only");
     if (prm.balance && !((dim == 2 || dim == 3) && prm.p == 3))
         throw Error{WLSENO_EUNSUPPORTED, "balanced stencils are compiled for p = 3 in 2-D and 3-D"};
@@ -605,6 +606,34 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
         for (int64_t d = 0; d < nc; ++d) {
             const int32_t u = b.perm[d];
             for (int32_t t = 0; t < cnt2[u]; ++t) b.pool[d * pc + t] = b.iperm[flat2[u * cap2 + t]];
+        }
+    }
+
+    // h_mode 1: eps h_i^2 with h_i the mean length of cell i's edges
+    if (prm.h_mode == 1) {
+        b.eh2_cell.resize(nc);
+        for (int64_t dd = 0; dd < nc; ++dd) {
+            const int64_t u = b.perm[dd];
+            double hi;
+            if (dim == 1) {
+                hi = m.vol[u];
+            } else {
+                double s = 0.0;
+                int ne = 0;
+                for (int v = 0; v < nvc; ++v)
+                    for (int w = v + 1; w < nvc; ++w) {
+                        double l2 = 0.0;
+                        for (int k = 0; k < dim; ++k) {
+                            const double t = m.xyz[(int64_t)m.cells[u * nvc + w] * dim + k] -
+                                             m.xyz[(int64_t)m.cells[u * nvc + v] * dim + k];
+                            l2 = l2 + t * t;
+                        }
+                        s = s + std::sqrt(l2);
+                        ++ne;
+                    }
+                hi = s / ne;
+            }
+            b.eh2_cell[dd] = prm.eps * hi * hi;
         }
     }
 

@@ -85,7 +85,7 @@ class WLSENO:
 
     def stencil_build(self, p=3, n_lo=12, n_hi=20, flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2,
                       alpha_w=1.5, rank_tol=1e-12, weight_mode=0, gamma=1.4, lanes=0, bc=0, characteristic=False,
-                      far_state=None, balance=False, lf_alpha=0):
+                      far_state=None, balance=False, lf_alpha=0, h_mode=0):
         prm = N.Params()
         self._lib.wlseno_params_default(C.byref(prm))
         prm.p, prm.n_lo, prm.n_hi = int(p), int(n_lo), int(n_hi)
@@ -96,6 +96,7 @@ class WLSENO:
         prm.characteristic = int(bool(characteristic))
         prm.balance = int(bool(balance))
         prm.lf_alpha = int(lf_alpha)
+        prm.h_mode = int(h_mode)
         for v in range(5):
             prm.far_state[v] = float(far_state[v]) if far_state is not None and v < len(far_state) else 0.0
         prm.eps, prm.alpha_w, prm.rank_tol, prm.gamma = float(eps), float(alpha_w), float(rank_tol), float(gamma)

@@ -428,6 +428,13 @@ def test_local_alpha(flux):
     _compare_all(mesh, u0, 4, None, f"local-alpha-{flux}", lf_alpha=1, **kw)
 
 
+def test_per_cell_h():
+    """eps h_i^2 with each cell's own mean edge length (h_mode = 1)."""
+    mesh = jittered_square(14, 0.4, 3126)
+    u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+    _compare_all(mesh, u0, 4, 0.002, "per-cell-h", p=3, n_lo=12, n_hi=20, flux="burgers", h_mode=1)
+
+
 FREE_STREAM = (1.0, 1.0, 1.0, 1.0 / 0.4 + 1.0)   # rho = p = 1, velocity (1, 1)
 
 

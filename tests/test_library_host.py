@@ -158,6 +158,11 @@ def test_error_paths(lib):
         w.stencil_build(p=4, n_lo=18, n_hi=24, flux="burgers", balance=True)
     assert e.value.status == 5
     w.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers", balance=True)
+    # h_mode and lf_alpha take 0 or 1
+    with pytest.raises(WLSENOError):
+        w.stencil_build(p=3, n_lo=12, n_hi=20, h_mode=2)
+    with pytest.raises(WLSENOError):
+        w.stencil_build(p=3, n_lo=12, n_hi=20, lf_alpha=2)
     # device call on a host-only context
     w.stencil_build(p=3, n_lo=12, n_hi=20)
     rc = lib.wlseno_rhs(w._h, C.c_void_p(16), C.c_void_p(32))

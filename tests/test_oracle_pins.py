@@ -591,3 +591,26 @@ def test_local_alpha_conserves_and_dissipates_less(flux):
     U = np.array([0.9, 0.2, -0.3, 2.7]) if flux == "euler" else np.array([0.6])
     uu = np.repeat(U[:, None], ol.nc, axis=1)
     assert np.max(np.abs(ol.rhs(uu)[0])) < 1e-10
+
+
+def test_per_cell_h_uses_each_cells_mean_edge():
+    """h_mode = 1: eps h_i^2 with h_i the cell's mean edge length.  On a
+    lattice of congruent right triangles every h_i is s (2 + sqrt 2) / 3,
+    so the result equals the mesh-wide mode run with that h; on a jittered
+    mesh the two modes differ."""
+    import oracle
+
+    n = 9
+    mesh = jittered_square(n, 0.0, 51)
+    s = 1.0 / (n - 1)
+    u = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+    kw = dict(p=3, n_lo=12, n_hi=20, flux="burgers")
+    o1 = oracle.Oracle(2, mesh.verts, mesh.cells, h_mode=1, **kw)
+    assert np.allclose(o1.h_cell, s * (2.0 + np.sqrt(2.0)) / 3.0, rtol=1e-14)
+    o0 = oracle.Oracle(2, mesh.verts, mesh.cells, h=s * (2.0 + np.sqrt(2.0)) / 3.0, **kw)
+    np.testing.assert_allclose(o1.rhs(u)[0], o0.rhs(u)[0], rtol=1e-12, atol=1e-12 * np.max(np.abs(o0.rhs(u)[0])))
+    mj = jittered_square(n, 0.3, 52)
+    uj = fields.cell_averages(mj, fields.gaussian_bump_with_step_2d)
+    a = oracle.Oracle(2, mj.verts, mj.cells, h_mode=1, **kw).rhs(uj)[0]
+    b = oracle.Oracle(2, mj.verts, mj.cells, **kw).rhs(uj)[0]
+    assert np.max(np.abs(a - b)) > 1e-8 * np.max(np.abs(b))
