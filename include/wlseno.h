@@ -88,7 +88,8 @@ typedef struct {
                             are compiled for 2-D p = 3, 4, 8 and 16 for 2-D p = 4, 8 and 16
                             for 2-D p = 5 and 3-D p = 3.  Other values are EINVAL; a value not
                             compiled for (dim, p) uses the automatic choice.  Results agree to
-                            rounding either way. */
+                            rounding either way.  Characteristic fields (4 lanes, 16 at
+                            p = 5) and the balanced refit use their own fixed choice. */
     double eps;          /* epsilon in beta_j = (u_j - u_i)^2 + eps h^2 */
     double alpha_w;      /* centre weight factor alpha > 1 in eq. (weight) */
     double rank_tol;     /* numerical rank: |R_kk| > rank_tol |R_11| */
