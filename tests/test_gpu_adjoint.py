@@ -12,7 +12,7 @@
 import numpy as np
 import pytest
 
-from workloads import fields, jittered_square
+from workloads import fields, jittered_square, jittered_square_periodic
 
 pytestmark = pytest.mark.gpu
 
@@ -25,12 +25,12 @@ def _torch():
     return torch
 
 
-def _setup(n=12, seed=5101, weight_mode=0, p=3, bc=0):
+def _setup(n=12, seed=5101, weight_mode=0, p=3, bc=0, torus=False):
     from paper_1602_02694_amd import WLSENO
 
-    mesh = jittered_square(n, 0.3, seed)
+    mesh = jittered_square_periodic(n, 0.3, seed) if torus else jittered_square(n, 0.3, seed)
     w = WLSENO(device=0)
-    w.mesh_upload(2, mesh.verts, mesh.cells)
+    w.mesh_upload(2, mesh.verts, mesh.cells, mesh.periodic)
     kw = dict(p=p, n_lo=12 if p == 3 else 20, n_hi=20 if p == 3 else 36, flux="advection", velocity=(1.0, 0.5, 0.0),
               weight_mode=weight_mode, bc=bc)
     w.stencil_build(**kw)
@@ -43,11 +43,11 @@ def _say(msg):
     print(msg, flush=True)
 
 
-@pytest.mark.parametrize("p,bc", [(3, 0), (4, 0), (3, 1)])
-def test_vjp_is_exact_transpose_with_unit_weights(p, bc):
+@pytest.mark.parametrize("p,bc,torus", [(3, 0, False), (4, 0, False), (3, 1, False), (3, 0, True)])
+def test_vjp_is_exact_transpose_with_unit_weights(p, bc, torus):
     torch = _torch()
-    mesh, w, kw, u0, _ = _setup(weight_mode=1, p=p, bc=bc)
-    _say(f"[case] transpose p={p} bc={bc} n_cell={mesh.n_cell}")
+    mesh, w, kw, u0, _ = _setup(weight_mode=1, p=p, bc=bc, torus=torus)
+    _say(f"[case] transpose p={p} bc={bc} torus={torus} n_cell={mesh.n_cell}")
     rng = np.random.default_rng(7)
     v = torch.tensor(rng.standard_normal(mesh.n_cell), device="cuda")
     x = torch.tensor(rng.standard_normal(mesh.n_cell), device="cuda")
@@ -59,10 +59,11 @@ def test_vjp_is_exact_transpose_with_unit_weights(p, bc):
     assert abs(a - b) <= 1e-12 * scale, (a, b)
 
 
-def test_vjp_against_central_differences():
+@pytest.mark.parametrize("torus", [False, True])
+def test_vjp_against_central_differences(torus):
     torch = _torch()
-    mesh, w, kw, u0, _ = _setup()
-    _say(f"[case] vjp-fd n_cell={mesh.n_cell}")
+    mesh, w, kw, u0, _ = _setup(torus=torus)
+    _say(f"[case] vjp-fd torus={torus} n_cell={mesh.n_cell}")
     rng = np.random.default_rng(8)
     u = torch.tensor(u0, device="cuda")
     for trial in range(4):
