@@ -174,22 +174,24 @@ def assert_poly_parity(gcoef, ocoef, o, u, what="", rel=REL, floor=FLOOR, xcoef=
     return float(err.max())
 
 
-def cell_conditions(o, u):
+def cell_conditions(o, u, cells=None):
     """kappa = cond_2(W A S) per (component, cell) from the oracle's own
     per-cell matrix and weights (rows padded with zeros, which leaves the
-    singular values unchanged)."""
+    singular values unchanged).  With ``cells``, only those cells are
+    evaluated; the others are left at zero."""
     u = np.asarray(u, dtype=np.float64).reshape(o.nvars, o.nc)
+    cells = np.arange(o.nc) if cells is None else np.asarray(cells, dtype=np.int64)
     nmax = int(np.max(np.diff(o.row_ptr)))
     out = np.zeros((o.nvars, o.nc))
-    mats = [o.cell_matrix(i) for i in range(o.nc)]
+    mats = [o.cell_matrix(int(i)) for i in cells]
     for v in range(o.nvars):
-        M = np.zeros((o.nc, nmax, o.m))
-        for i in range(o.nc):
-            WA = o.cell_weights(i, u[v])[:, None] * mats[i]
+        M = np.zeros((len(cells), nmax, o.m))
+        for k, i in enumerate(cells):
+            WA = o.cell_weights(int(i), u[v])[:, None] * mats[k]
             nr = np.linalg.norm(WA, axis=0)
-            M[i, :len(WA)] = WA / np.where(nr > 0, nr, 1.0)
+            M[k, :len(WA)] = WA / np.where(nr > 0, nr, 1.0)
         sv = np.linalg.svd(M, compute_uv=False)
-        out[v] = sv[:, 0] / np.maximum(sv[:, -1], 1e-300)
+        out[v, cells] = sv[:, 0] / np.maximum(sv[:, -1], 1e-300)
     return out
 
 
