@@ -211,24 +211,28 @@ wlseno_status wlseno_reconstruct(wlseno_t ctx, const double *u_dev, double *coef
                                  double *facevals_dev, int32_t *rank_dev);
 
 /* dudt_dev = L(u_dev): the semi-discrete right-hand side
- * -(1/|tau_i|) sum_f |f| sum_q w_q Fhat(u-, u+, n).  Boundary facets use the
- * transmissive ghost u+ = u-.  dudt_dev must not alias u_dev. */
+ * -(1/|tau_i|) sum_f |f| sum_q w_q Fhat(u-, u+, n) (Sec. 1, the finite-volume
+ * and Lax-Friedrichs flux equations), with the alpha that wlseno_params.lf_alpha
+ * selects.  At boundary facets u+ is the outside state that wlseno_params.bc
+ * selects.  dudt_dev must not alias u_dev. */
 wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev);
 
 /* Advance u_dev in place by n_steps steps of size dt of third-order TVD
  * Runge-Kutta (three right-hand sides per step). */
 wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps);
 
-/* The Lax-Friedrichs alpha used by the last rhs stage (Burgers/Euler; 0 for
- * advection; for a batch the largest over its meshes), read back from the
+/* The global Lax-Friedrichs alpha of the last rhs stage: the largest normal
+ * spectral radius over all facet points (Burgers/Euler; 0 for advection; for
+ * a batch the largest over its meshes), also when lf_alpha = 1 selects local
+ * values for the flux (it bounds the CFL time step).  Read back from the
  * device (synchronises the stream). */
 wlseno_status wlseno_last_alpha(wlseno_t ctx, double *alpha);
 
-/* wlseno_step and wlseno_batch_step replay pairs of RK3 steps from a HIP
- * graph captured on first use (per context, per time step; recaptured when
- * the time step or the stencil build changes), and launch an odd last step
- * directly.  enable = 0 launches every kernel directly; results are
- * identical either way.  The default is enabled. */
+/* wlseno_step and wlseno_batch_step replay runs of 32 RK3 steps, then pairs
+ * of steps, from HIP graphs captured on first use (per context and time step;
+ * recaptured when the time step or the stencil build changes), and launch an
+ * odd last step directly.  enable = 0 launches every kernel directly; results
+ * are identical either way.  The default is enabled. */
 wlseno_status wlseno_set_graphs(wlseno_t ctx, int enable);
 
 /* Batches of independent meshes (several meshes stepped by one set of
