@@ -3,15 +3,12 @@
 The GPU runs the whole mesh with the automatic lane count and the direct
 launches of the reconstruction and update kernels that the benchmark's stages
 make.  The oracle cannot build stencils for millions of cells within a test,
-so it runs on a sub-mesh: every cell within R vertex rings of a seeded sample
-of cells (random cells and cells on the domain boundary), kept in the full
-mesh's order (so ties between equally distant cells, if any, break the same
-way) and given the full mesh's mean edge length h for eps h^2.  R is chosen
-so that a sampled cell's k-ring stencil, its facet neighbours and their
-stencils lie inside the sub-mesh; the sampled cells' stencils are compared as
-integers, mapped back to full-mesh numbering, which shows R was enough.
-Facet values, polynomials and right-hand sides of the sampled cells then meet
-the parity rule of tests/parity.py.
+so it runs on the sub-mesh of every cell within R vertex rings of a seeded
+sample (random cells and cells on the domain boundary; tests/submesh.py).
+The sampled cells' stencils are compared as integers, mapped back to
+full-mesh numbering, which shows R was enough; their facet values,
+polynomials and right-hand sides then meet the parity rule of
+tests/parity.py.
 
 A right-hand side with the global Lax-Friedrichs alpha (Burgers, Euler) needs
 every cell's facet values.  On the 2 M-triangle mesh it is compared with the
@@ -26,6 +23,7 @@ import pytest
 
 from parity import (assert_parity, assert_poly_parity, cell_conditions, cell_noise, flux_scale, floor_tol,
                     momentum_scale, neighbourhood_max)
+from submesh import SubOracle, sample_cells
 from workloads import configs, fields, jittered_cube, jittered_square
 
 pytestmark = pytest.mark.gpu
@@ -41,72 +39,6 @@ def _torch():
 
 def _say(msg):
     print(msg, flush=True)
-
-
-def _rings(cells, nv, start, R):
-    """Cells within R vertex rings of the cells ``start`` (sorted ids)."""
-    mask = np.zeros(len(cells), dtype=bool)
-    mask[start] = True
-    for _ in range(R):
-        vm = np.zeros(nv, dtype=bool)
-        vm[cells[mask]] = True
-        mask = vm[cells].any(axis=1)
-    return np.flatnonzero(mask)
-
-
-def _mean_edge(verts, cells):
-    """Mean length over the mesh's distinct edges."""
-    nv = len(verts)
-    k = cells.shape[1]
-    pairs = np.concatenate([np.sort(cells[:, [a, b]].astype(np.int64), axis=1)
-                            for a in range(k) for b in range(a + 1, k)])
-    key = np.unique(pairs[:, 0] * nv + pairs[:, 1])
-    a, b = key // nv, key % nv
-    return float(np.mean(np.linalg.norm(verts[a] - verts[b], axis=1)))
-
-
-def _sample(mesh, n_random, n_boundary, seed):
-    """Seeded random cells plus cells with a vertex on the domain boundary."""
-    rng = np.random.default_rng(seed)
-    lo, hi = mesh.verts.min(axis=0), mesh.verts.max(axis=0)
-    on_bnd = (np.isclose(mesh.verts, lo) | np.isclose(mesh.verts, hi)).any(axis=1)
-    bcells = np.flatnonzero(on_bnd[mesh.cells].any(axis=1))
-    pick = np.concatenate([rng.choice(mesh.n_cell, n_random, replace=False),
-                           rng.choice(bcells, n_boundary, replace=False)])
-    return np.unique(pick)
-
-
-class _SubOracle:
-    """FP64 and extended-precision oracles on the sub-mesh around ``sample``."""
-
-    def __init__(self, mesh, u0, sample, R, **kw):
-        import oracle
-
-        self.keep = _rings(mesh.cells, len(mesh.verts), sample, R)
-        vids, inv = np.unique(mesh.cells[self.keep], return_inverse=True)
-        sub_cells = inv.reshape(len(self.keep), -1).astype(np.int32)
-        sub_verts = mesh.verts[vids]
-        self.loc = np.searchsorted(self.keep, sample)
-        assert np.array_equal(self.keep[self.loc], sample)
-        h = _mean_edge(mesh.verts, mesh.cells)
-        V = 4 if kw.get("flux") == "euler" else 1
-        self.u = np.ascontiguousarray(np.asarray(u0).reshape(V, -1)[:, self.keep])
-        self.o = oracle.Oracle(mesh.dim, sub_verts, sub_cells, False, h=h, **kw)
-        self.ox = oracle.Oracle(mesh.dim, sub_verts, sub_cells, False, h=h, extended=True,
-                                stencil=(self.o.row_ptr, self.o.col), **kw)
-        _say(f"[oracle] sub-mesh of {len(self.keep)} cells around {len(sample)} sampled cells (R = {R})")
-
-    def stencil_rows(self):
-        o = self.o
-        return [self.keep[o.col[o.row_ptr[i]:o.row_ptr[i + 1]]] for i in self.loc]
-
-    def kappas(self):
-        """kappa at the sampled cells, and its max over each sampled cell's facet neighbours."""
-        o = self.o
-        nb = o.mesh.nbr[self.loc]
-        need = np.unique(np.concatenate([self.loc, nb[nb >= 0]]))
-        k = cell_conditions(o, self.u, cells=need)
-        return k, neighbourhood_max(o, k.max(axis=0, keepdims=True))
 
 
 def _check_sample(w, u_dev, sub, name, rhs=True):
@@ -176,16 +108,16 @@ def test_square_large_burgers_sampled():
     u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
     _say(f"[case] square-large burgers: n_cell={mesh.n_cell}")
     kw = dict(p=3, n_lo=12, n_hi=20, flux="burgers")
-    sample = _sample(mesh, 48, 16, 9101)
+    sample = sample_cells(mesh, 48, 16, 9101)
     u = torch.tensor(u0, device="cuda")
     w = _gpu(mesh, **kw)
-    sub = _SubOracle(mesh, u0, sample, 4, **kw)
+    sub = SubOracle(mesh, u0, sample, 4, **kw)
     _check_sample(w, u, sub, "square-large global alpha", rhs=False)
     a = w.last_alpha()
     assert np.isfinite(a) and a > 0
     del w
     w = _gpu(mesh, lf_alpha=1, **kw)
-    sub = _SubOracle(mesh, u0, sample, 4, lf_alpha=1, **kw)
+    sub = SubOracle(mesh, u0, sample, 4, lf_alpha=1, **kw)
     _check_sample(w, u, sub, "square-large local alpha")
 
 
@@ -196,10 +128,10 @@ def test_cube_advection_sampled():
     u0 = fields.cell_averages(mesh, fields.sine_with_sphere_3d)
     _say(f"[case] cube40 advection: n_cell={mesh.n_cell}")
     kw = dict(p=3, n_lo=30, n_hi=50, flux="advection", velocity=(1.0, 0.5, 0.25))
-    sample = _sample(mesh, 24, 8, 9102)
+    sample = sample_cells(mesh, 24, 8, 9102)
     u = torch.tensor(u0, device="cuda")
     w = _gpu(mesh, **kw)
-    sub = _SubOracle(mesh, u0, sample, 3, **kw)
+    sub = SubOracle(mesh, u0, sample, 3, **kw)
     _check_sample(w, u, sub, "cube40")
 
 
@@ -213,10 +145,10 @@ def test_adjoint_workload_sampled():
     s = wl.settings
     kw = dict(p=s["p"], n_lo=s["n_lo"], n_hi=s["n_hi"], flux=s["flux"], velocity=s["velocity"], bc=s["bc"])
     _say(f"[case] adjoint workload: n_cell={mesh.n_cell}")
-    sample = _sample(mesh, 48, 16, 9103)
+    sample = sample_cells(mesh, 48, 16, 9103)
     u = torch.tensor(u0, device="cuda")
     w = _gpu(mesh, **kw)
-    sub = _SubOracle(mesh, u0, sample, 4, **kw)
+    sub = SubOracle(mesh, u0, sample, 4, **kw)
     _check_sample(w, u, sub, "adjoint workload")
     rng = np.random.default_rng(9104)
     x = np.zeros(mesh.n_cell)
