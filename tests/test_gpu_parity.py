@@ -126,6 +126,26 @@ def test_line_p5_seven_cells_and_burgers():
     _compare_all(mesh, u0, 20, dt, "line97-p5-burgers", p=5, n_lo=7, n_hi=7, flux="burgers")
 
 
+@pytest.mark.parametrize("p,n", [(2, 3), (3, 5), (4, 5), (5, 7)])
+@pytest.mark.parametrize("flux", ["advection", "burgers"])
+def test_line_orders(p, n, flux):
+    """1-D periodic, every order and both scalar fluxes: a 61-cell jittered
+    line (not a multiple of the block size), sine plus square wave."""
+    mesh = periodic_line(61, 0.2, 7100 + p)
+    u0 = fields.square_wave_sine_1d(mesh)
+    dt = 0.3 * np.min(np.diff(mesh.verts[:, 0]))
+    _compare_all(mesh, u0, 8, dt, f"line61-p{p}-{flux}", p=p, n_lo=n, n_hi=n, flux=flux, velocity=(1.0, 0, 0))
+
+
+def test_line_unit_weights():
+    """1-D with unit weights (the plain least-squares limit)."""
+    mesh = periodic_line(61, 0.2, 7106)
+    u0 = fields.square_wave_sine_1d(mesh)
+    dt = 0.3 * np.min(np.diff(mesh.verts[:, 0]))
+    _compare_all(mesh, u0, 8, dt, "line61-p3-ls", p=3, n_lo=5, n_hi=5, flux="advection", velocity=(1.0, 0, 0),
+                 weight_mode=1)
+
+
 @pytest.mark.parametrize("lanes", [2, 4, 8, 16])
 def test_square_small_advection_ragged(lanes):
     """2-D p=3 on a small mesh whose cell count is not a multiple of the block size."""
