@@ -194,6 +194,16 @@ def test_square_p2():
                  velocity=(0.3, -1.0, 0))
 
 
+@pytest.mark.parametrize("p,n_lo,n_hi,flux", [(2, 3, 6, "burgers"), (4, 20, 36, "advection"),
+                                             (5, 24, 30, "advection")])
+def test_square_other_order_flux_pairs(p, n_lo, n_hi, flux):
+    """The 2-D order/flux pairs the other cases leave out."""
+    mesh = jittered_square(13, 0.3, 7200 + p)
+    u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+    _compare_all(mesh, u0, 4, 0.001, f"square13-p{p}-{flux}", p=p, n_lo=n_lo, n_hi=n_hi, flux=flux,
+                 velocity=(0.6, -0.8, 0))
+
+
 def test_tiny_mesh_whole_domain_stencils():
     """Edge case: 8 triangles; every stencil is the whole mesh."""
     mesh = jittered_square(3, 0.0, 1)
@@ -332,6 +342,14 @@ def test_cube_p2():
     u0 = fields.cell_averages(mesh, fields.sine_with_sphere_3d)
     _compare_all(mesh, u0, 3, None, "cube7-p2", p=2, n_lo=8, n_hi=16, flux="advection",
                  velocity=(0.3, -1.0, 0.5))
+
+
+def test_cube_burgers_p2():
+    from workloads import jittered_cube
+
+    mesh = jittered_cube(7, 0.15, 4104)
+    u0 = fields.cell_averages(mesh, fields.sine_with_sphere_3d)
+    _compare_all(mesh, u0, 3, None, "cube7-burgers-p2", p=2, n_lo=8, n_hi=16, flux="burgers")
 
 
 def test_cube_largest_compiled_stencils():
