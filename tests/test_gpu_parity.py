@@ -370,7 +370,8 @@ def test_cube_largest_compiled_stencils():
 
 # ----------------------------------------------------------------- Euler
 
-@pytest.mark.parametrize("p,n_lo,n_hi,lanes", [(3, 12, 20, 0), (4, 20, 36, 0), (4, 20, 36, 16)])
+@pytest.mark.parametrize("p,n_lo,n_hi,lanes", [(2, 3, 6, 0), (3, 12, 20, 0), (4, 20, 36, 0), (4, 20, 36, 16),
+                                              (5, 24, 30, 0)])
 def test_euler_quadrants(p, n_lo, n_hi, lanes):
     """2-D Euler, four Riemann states about a random split (conserved
     variables, gamma = 1.4), component-wise reconstruction."""
@@ -380,7 +381,7 @@ def test_euler_quadrants(p, n_lo, n_hi, lanes):
                  lanes=lanes)
 
 
-@pytest.mark.parametrize("p,n_lo,n_hi", [(3, 12, 20), (4, 20, 36), (5, 24, 30)])
+@pytest.mark.parametrize("p,n_lo,n_hi", [(2, 3, 6), (3, 12, 20), (4, 20, 36), (5, 24, 30)])
 def test_euler_characteristic(p, n_lo, n_hi):
     """2-D Euler reconstructed in characteristic fields per facet (4 x 3
     fits per cell): facet values, ranks, rhs and steps against the oracle."""
