@@ -201,7 +201,7 @@ def test_euler_batch_full_size():
         ref = o.reconstruct(u0)
         Lo, alpha_o = o.rhs(u0)
         Lx, _ = ox.rhs(u0)
-        assert ab[k] == pytest.approx(alpha_o, rel=1e-13), f"mesh {k} alpha"
+        assert ab[k] == pytest.approx(alpha_o, rel=1e-12), f"mesh {k} alpha"
         # the smallest mesh whole; the others at their 64 largest |rhs| cells
         # and a seeded sample (kappa is costly on the CPU)
         rng = np.random.default_rng(9105 + k)
