@@ -632,7 +632,7 @@ def test_batch_errors():
     assert e.value.status == 1
 
 
-@pytest.mark.parametrize("case", ["single", "batch"])
+@pytest.mark.parametrize("case", ["single", "batch", "balance", "characteristic", "cube-local-alpha"])
 def test_graph_replays_equal_direct_launches(case):
     """Steps replayed from the captured graphs (32-step and 2-step) equal
     directly launched steps bit for bit, over several replays with other
@@ -640,15 +640,30 @@ def test_graph_replays_equal_direct_launches(case):
     torch = _torch()
     from paper_1602_02694_amd import WLSENO
 
-    if case == "single":
-        wl = configs.square_burgers(20, 2021)
+    if case != "batch":
+        # single meshes: Burgers; with the balanced refit (range check, list
+        # counter and refit kernels in the graph); Euler in characteristic
+        # fields; 3-D Burgers with the local alpha
+        if case == "characteristic":
+            mesh = jittered_square(12, 0.3, 3312)
+            u0 = fields.cell_averages(mesh, fields.euler_quadrants(3313))
+            kw = dict(p=3, n_lo=12, n_hi=20, flux="euler", characteristic=True)
+        elif case == "cube-local-alpha":
+            mesh = jittered_cube(6, 0.15, 3314)
+            u0 = fields.cell_averages(mesh, fields.sine_with_sphere_3d)
+            kw = dict(p=3, n_lo=30, n_hi=50, flux="burgers", lf_alpha=1)
+        else:
+            wl = configs.square_burgers(20, 2021)
+            mesh, u0 = wl.mesh, wl.u0
+            kw = dict(p=3, n_lo=12, n_hi=20, flux="burgers", balance=case == "balance")
         ctxs = []
         for graphs in (True, False):
-            w = _gpu(wl.mesh, p=3, n_lo=12, n_hi=20, flux="burgers")
+            w = _gpu(mesh, **kw)
             w.set_graphs(graphs)
             ctxs.append(w)
-        u0 = wl.u0
-        dt = 0.5 * ctxs[0].info()["min_insphere"] / (np.sqrt(2.0) * np.max(np.abs(u0)))
+        w = ctxs[1]
+        w.rhs(torch.tensor(np.asarray(u0).reshape(-1), device="cuda"))
+        dt = 0.3 * w.info()["min_insphere"] / w.last_alpha()
         stepper = lambda w, u, n: w.step(u, dt, n)
     else:
         meshes, us = _batch("euler", 3311)
