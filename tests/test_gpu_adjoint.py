@@ -59,6 +59,61 @@ def test_vjp_is_exact_transpose_with_unit_weights(p, bc, torus):
     assert abs(a - b) <= 1e-12 * scale, (a, b)
 
 
+def _setup_other(kind, weight_mode):
+    """1-D (periodic line, p = 3 and 5), 2-D p = 5 and 3-D (p = 2 and 3) advection."""
+    from paper_1602_02694_amd import WLSENO
+    from workloads import jittered_cube, periodic_line
+
+    if kind.startswith("line"):
+        mesh = periodic_line(83, 0.2, 5201)
+        p = int(kind[-1])
+        kw = dict(p=p, n_lo=p + 2, n_hi=p + 2, velocity=(1.0, 0.0, 0.0))
+        u0 = fields.line_cell_averages(mesh, lambda x: np.sin(2 * np.pi * x) + 0.3 * np.cos(6 * np.pi * x))
+    elif kind == "square-p5":
+        mesh = jittered_square(12, 0.3, 5202)
+        kw = dict(p=5, n_lo=24, n_hi=30, velocity=(1.0, 0.5, 0.0))
+        u0 = fields.cell_averages(mesh, fields.gaussian_sum(5202, 8, 2))
+    else:
+        mesh = jittered_cube(6, 0.15, 5203)
+        p = int(kind[-1])
+        kw = dict(p=p, n_lo=30 if p == 3 else 8, n_hi=50 if p == 3 else 16, velocity=(1.0, 0.5, 0.25))
+        u0 = fields.cell_averages(mesh, lambda x: np.sin(2 * np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 1])
+                                  + 0.5 * x[:, 2])
+    kw.update(flux="advection", weight_mode=weight_mode)
+    w = WLSENO(device=0)
+    w.mesh_upload(mesh.dim, mesh.verts, mesh.cells, mesh.periodic)
+    w.stencil_build(**kw)
+    return mesh, w, u0
+
+
+@pytest.mark.parametrize("kind", ["line-p3", "line-p5", "square-p5", "cube-p2", "cube-p3"])
+def test_vjp_other_dimensions_and_orders(kind):
+    """Exact transpose with unit weights, and J(u)^T against central
+    differences of L with the WLS-ENO weights."""
+    torch = _torch()
+    mesh, w, u0 = _setup_other(kind, 1)
+    _say(f"[case] vjp {kind} n_cell={mesh.n_cell}")
+    rng = np.random.default_rng(11)
+    v = torch.tensor(rng.standard_normal(mesh.n_cell), device="cuda")
+    x = torch.tensor(rng.standard_normal(mesh.n_cell), device="cuda")
+    Lv = w.rhs(v)
+    a = float(torch.dot(x, Lv))
+    b = float(torch.dot(w.rhs_vjp(v, x), v))
+    assert abs(a - b) <= 1e-12 * float(torch.linalg.norm(x) * torch.linalg.norm(Lv)), (kind, a, b)
+    mesh, w, u0 = _setup_other(kind, 0)
+    u = torch.tensor(u0, device="cuda")
+    d = torch.tensor(rng.standard_normal(mesh.n_cell), device="cuda")
+    # L is smooth only between switches (a facet neighbour becoming the
+    # smallest indicator, a pivot near-tie); in the p = 5 case one lies
+    # between 1.25e-7 and 2.5e-7 along d (the quotient meets J^T to 2e-11
+    # below it, to 1e-6 above), so h stays below that
+    h = 1e-7 * float(u.abs().max()) / float(d.abs().max())
+    fd = (w.rhs(u + h * d) - w.rhs(u - h * d)) / (2 * h)
+    a = float(torch.dot(x, fd))
+    b = float(torch.dot(w.rhs_vjp(u, x), d))
+    assert abs(a - b) <= 1e-6 * abs(b), (kind, a, b)
+
+
 @pytest.mark.parametrize("torus", [False, True])
 def test_vjp_against_central_differences(torus):
     torch = _torch()
