@@ -10,7 +10,7 @@ import pytest
 
 from parity import (assert_parity, assert_poly_parity, cell_conditions, cell_noise, char_cell_conditions, flux_scale,
                     floor_tol, momentum_scale, neighbourhood_max)
-from workloads import (configs, periodic_line, uniform_periodic_line, jittered_cube, jittered_square,
+from workloads import (configs, periodic_line, jittered_cube, jittered_square,
                        jittered_square_periodic, fields)
 
 pytestmark = pytest.mark.gpu
