@@ -204,6 +204,22 @@ def test_square_other_order_flux_pairs(p, n_lo, n_hi, flux):
                  velocity=(0.6, -0.8, 0))
 
 
+@pytest.mark.parametrize("p,cap", [(3, 20), (4, 36), (5, 40)])
+def test_square_largest_compiled_stencils(p, cap):
+    """2-D stencils up to the largest compiled capacity of each order match
+    the oracle; a larger rule is refused cleanly at the device upload."""
+    from paper_1602_02694_amd import WLSENO, WLSENOError
+
+    mesh = jittered_square(13, 0.3, 7300 + p)
+    u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+    _compare_all(mesh, u0, 2, 0.001, f"square13-p{p}-n{cap}", p=p, n_lo=cap - 4, n_hi=cap, flux="burgers")
+    w = WLSENO(device=0)
+    w.mesh_upload(2, mesh.verts, mesh.cells)
+    with pytest.raises(WLSENOError) as e:
+        w.stencil_build(p=p, n_lo=cap + 2, n_hi=cap + 4, flux="burgers")
+    assert e.value.status == 5
+
+
 def test_tiny_mesh_whole_domain_stencils():
     """Edge case: 8 triangles; every stencil is the whole mesh."""
     mesh = jittered_square(3, 0.0, 1)
