@@ -90,7 +90,9 @@ typedef struct {
                             compiled for (dim, p) uses the automatic choice.  Results agree to
                             rounding either way.  Characteristic fields (4 lanes, 16 at
                             p = 5) and the balanced refit use their own fixed choice. */
-    double eps;          /* epsilon in beta_j = (u_j - u_i)^2 + eps h^2 */
+    double eps;          /* epsilon in beta_j = (u_j - u_i)^2 + eps h^2; must be > 0 with
+                            weight_mode 0 (equal averages would give an infinite weight),
+                            else EINVAL */
     double alpha_w;      /* centre weight factor alpha > 1 in eq. (weight) */
     double rank_tol;     /* numerical rank: |R_kk| > rank_tol |R_11| */
     double velocity[3];  /* advection velocity a */

@@ -1185,7 +1185,9 @@ __global__ void __launch_bounds__(recon_block(DIM)) k_rebalance(RArgs a, BArgs b
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    reconstruct_cell<DIM, P, G, RPL, FLUX>(a, c, c, live ? c + 1 : c, rw, n2, g, lds, slot);
+    // cell range [c, c + 1): a lane past the end of the list passes c + 1, which
+    // reconstruct_cell clamps back to c (a listed cell), and stores nothing
+    reconstruct_cell<DIM, P, G, RPL, FLUX>(a, live ? c : c + 1, c, c + 1, rw, n2, g, lds, slot);
 }
 
 // ------------------------------------------------------------ adjoint
@@ -1502,7 +1504,7 @@ __global__ void __launch_bounds__(256) k_adjoint_gather(int64_t nc, const int64_
 
 // --------------------------------------------------------------- K2/K3
 struct UArgs {
-    int nc;
+    int64_t nc;
     const double *fv, *snormal, *rvol;    // snormal = |f| n, [F][N][DIM]
     const int32_t *sib, *qperm;
     const double *u0, *prev;
@@ -1612,10 +1614,11 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
 {
     constexpr int F = DIM + 1;
     constexpr int V = FLUX == kFluxEuler ? DIM + 2 : 1;
-    const unsigned N = (unsigned)a.nc;
-    const unsigned c0 = (unsigned)xcd_block((int)blockIdx.x, (int)gridDim.x) * (unsigned)BS + threadIdx.x;
+    // 64-bit cell indices: [V][F][N][Q] offsets pass 2^32 well within 288 GB
+    const int64_t N = a.nc;
+    const int64_t c0 = (int64_t)xcd_block((int)blockIdx.x, (int)gridDim.x) * BS + threadIdx.x;
     const bool live = c0 < N;
-    const unsigned c = live ? c0 : N - 1;   // lanes past the end work on the last cell, store nothing
+    const int64_t c = live ? c0 : N - 1;   // lanes past the end work on the last cell, store nothing
     if constexpr (FLUX != kFluxAdv) {
         if (blockIdx.x == 0)
             for (int t = (int)threadIdx.x; t < a.nslot; t += BS) a.alpha_clr[t * 16] = 0ull;
@@ -1653,8 +1656,8 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
 #pragma unroll
     for (int lf = 0; lf < F; ++lf) {
         const bool inner = sb[lf] >= 0;
-        const unsigned j = inner ? (unsigned)sb[lf] >> 2 : c;
-        const unsigned l2 = inner ? (unsigned)sb[lf] & 3u : (unsigned)lf;
+        const int64_t j = inner ? (int64_t)(sb[lf] >> 2) : c;
+        const int l2 = inner ? (sb[lf] & 3) : lf;
         owner[lf] = c < j;
         qp[lf] = 0;
         if constexpr (DIM == 3) qp[lf] = inner ? (owner[lf] ? a.qperm[lf * N + c] : a.qperm[l2 * N + j]) : 0;
@@ -1754,7 +1757,7 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
     if (!live) return;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        const unsigned vc = v * N + c;
+        const int64_t vc = v * N + c;
         const double L = -tot[v] * rv;
         a.out[vc] = a.mode == 0 ? L : a.A * a.u0[vc] + a.B * a.prev[vc] + cdt * L;
     }
@@ -2025,7 +2028,7 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
                   double Cdt, int mode, int parity, void *stream)
 {
     UArgs a;
-    a.nc = (int)dm.nc;
+    a.nc = dm.nc;
     a.fv = dm.fv;
     a.snormal = dm.normal;
     a.rvol = dm.rvol;

@@ -499,6 +499,9 @@ void build_setup(const HostMesh &m, const wlseno_params &prm, Build &out)
         throw inval("lanes must be 0, 2, 4, 8 or 16");
     if (!(prm.eps >= 0.0) || !(prm.alpha_w > 0.0) || !(prm.rank_tol >= 0.0))
         throw inval("eps >= 0, alpha_w > 0 and rank_tol >= 0 required");
+    // WLS-ENO weights 1/((u_j - u_i)^2 + eps h^2): eps h^2 is the positive
+    // constant that keeps them finite where neighbouring averages are equal
+    if (prm.weight_mode == 0 && !(prm.eps > 0.0)) throw inval("eps > 0 required with WLS-ENO weights (weight_mode 0)");
     Build b;
     b.prm = prm;
     b.m = num_coeffs(dim, prm.p);

@@ -453,6 +453,23 @@ def test_balanced_refit(dim):
     _compare_all(mesh, u0, 3, None, f"balance{dim}d", balance=True, **kw)
 
 
+def test_balanced_refit_short_list():
+    """Balanced refit with only two listed cells: the refit's one live
+    wavefront holds two cells and 30 lane groups past the end of the list,
+    which must read only the listed cells' records and store nothing.  A
+    linear field refits just two boundary cells (found with the oracle)."""
+    _torch()
+    mesh = jittered_square(10, 0.3, 3113)
+    cent = mesh.verts[mesh.cells].mean(axis=1)
+    th = 2.4435
+    u0 = 0.5 + np.cos(th) * cent[:, 0] + np.sin(th) * cent[:, 1]
+    kw = dict(p=3, n_lo=12, n_hi=20, flux="burgers")
+    ref = _oracle(mesh, balance=True, **kw).reconstruct(u0)
+    _say(f"[case] balance short list: {int(ref['rebalanced'].sum())} of {mesh.n_cell} cells refitted")
+    assert int(ref["rebalanced"].sum()) == 2
+    _compare_all(mesh, u0, 2, None, "balance-short-list", balance=True, **kw)
+
+
 def test_torus_burgers():
     """Doubly periodic mesh: facet neighbours and stencils wrap around."""
     mesh = jittered_square_periodic(16, 0.3, 3121)

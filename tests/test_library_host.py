@@ -163,6 +163,11 @@ def test_error_paths(lib):
         w.stencil_build(p=3, n_lo=12, n_hi=20, h_mode=2)
     with pytest.raises(WLSENOError):
         w.stencil_build(p=3, n_lo=12, n_hi=20, lf_alpha=2)
+    # eps h^2 keeps the WLS-ENO weights finite: eps = 0 only with unit weights
+    with pytest.raises(WLSENOError) as e:
+        w.stencil_build(p=3, n_lo=12, n_hi=20, eps=0.0)
+    assert e.value.status == 1 and "eps > 0" in str(e.value)
+    w.stencil_build(p=3, n_lo=12, n_hi=20, eps=0.0, weight_mode=1)
     # device call on a host-only context
     w.stencil_build(p=3, n_lo=12, n_hi=20)
     rc = lib.wlseno_rhs(w._h, C.c_void_p(16), C.c_void_p(32))
