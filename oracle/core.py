@@ -17,20 +17,30 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wlseno_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _LIB_LD = os.path.join(_HERE, "liboracle_ld.so")
+_LIB_TAN = os.path.join(_HERE, "liboracle_tan.so")
+_TAN_HDR = os.path.join(_HERE, "tangent.hpp")
 
 FLUX = {"advection": 0, "burgers": 1, "euler": 2}
 
 
-def build(force: bool = False, extended: bool = False) -> str:
+def build(force: bool = False, extended: bool = False, tangent: bool = False) -> str:
     """Compile the C core with gcc (-O2 -ffp-contract=off, OpenMP).  The
     extended build runs the same algorithm in x87 long double; it is used only
-    to measure the FP64 rounding floor of individual cells."""
-    out = _LIB_LD if extended else _LIB
-    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+    to measure the FP64 rounding floor of individual cells.  The tangent build
+    compiles the same file as C++ on the dual numbers of tangent.hpp (values
+    bitwise those of the FP64 build, plus exact directional derivatives on
+    the active branch); stencils up to 64 rows and 15 coefficients."""
+    out = _LIB_TAN if tangent else (_LIB_LD if extended else _LIB)
+    deps = [_SRC] + ([_TAN_HDR] if tangent else [])
+    if force or not os.path.exists(out) or any(os.path.getmtime(out) < os.path.getmtime(d) for d in deps):
         tmp = out + ".tmp"
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99"]
-        if extended:
-            cmd.append("-DOR_REAL=long double")
+        if tangent:
+            cmd = ["g++", "-x", "c++", "-std=c++17", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                   "-include", _TAN_HDR, "-DOR_REAL=or_dual", "-DOR_GREAL=double", "-DOR_TANGENT", "-DOR_MAXM=15", "-DOR_MAXN=64"]
+        else:
+            cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99"]
+            if extended:
+                cmd.append("-DOR_REAL=long double")
         cmd += ["-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, out)
@@ -40,11 +50,12 @@ def build(force: bool = False, extended: bool = False) -> str:
 _libs = {}
 
 
-def lib(extended: bool = False):
-    _lib = _libs.get(extended)
+def lib(extended: bool = False, tangent: bool = False):
+    key = "tan" if tangent else ("ld" if extended else "fp64")
+    _lib = _libs.get(key)
     if _lib is None:
-        _lib = C.CDLL(build(extended=extended))
-        _libs[extended] = _lib
+        _lib = C.CDLL(build(extended=extended, tangent=tangent))
+        _libs[key] = _lib
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int)
         _lib.or_num_coeffs.argtypes = [C.c_int, C.c_int]
@@ -66,6 +77,10 @@ def lib(extended: bool = False):
         _lib.or_rhs.argtypes = [pp, dp, dp, dp]
         _lib.or_rk3.argtypes = [pp, dp, C.c_double, C.c_int]
         _lib.or_num_threads.argtypes = []
+        if tangent:
+            _lib.or_ndir.argtypes = []
+            _lib.or_rhs_tangent.argtypes = [pp, dp, dp, C.c_int, dp, dp]
+            _lib.or_rk3_tangent.argtypes = [pp, dp, dp, C.c_int, C.c_double, C.c_int]
     return _lib
 
 
@@ -175,8 +190,11 @@ class Oracle:
     def __init__(self, dim, verts, cells, periodic=False, *, p=3, n_lo=None, n_hi=None,
                  flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2, alpha_w=1.5,
                  rank_tol=1e-12, gamma=1.4, weight_mode=0, stencil=None, h=None, extended=False, bc=0,
-                 characteristic=False, far_state=None, balance=False, lf_alpha=0, h_mode=0):
+                 characteristic=False, far_state=None, balance=False, lf_alpha=0, h_mode=0, tangent=False):
         self.extended = bool(extended)
+        self.tangent = bool(tangent)
+        if self.tangent and self.extended:
+            raise ValueError("the tangent build is FP64")
         self.mesh = OracleMesh(dim, verts, cells, periodic, p=p)
         om = self.mesh
         self.dim, self.p, self.nc = om.dim, int(p), om.nc
@@ -243,7 +261,9 @@ class Oracle:
             self.h_cell = np.ascontiguousarray(om.cell_mean_edge(), dtype=np.float64)
             P.h_cell = _dp(self.h_cell)
         self._P = P
-        self._lib = lib(self.extended)
+        self._lib = lib(self.extended, self.tangent)
+        if self.tangent and (self.m > 15 or int(np.max(np.diff(self.row_ptr))) > 64):
+            raise ValueError("the tangent build holds stencils up to 64 rows and 15 coefficients")
         self.flux = flux
         self.nq = om.nq
         self.nf = dim + 1
@@ -307,6 +327,49 @@ class Oracle:
         if self._lib.or_rk3(C.byref(self._P), _dp(u), float(dt), int(nsteps)):
             raise MemoryError("oracle rk3 allocation failed")
         return u
+
+    # ----------------------------------------------------------- tangents
+    def _dirs(self, dirs):
+        d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, self.nvars * self.nc))
+        return d
+
+    def rhs_tangent(self, u, dirs):
+        """L(u) and J(u) d for every direction d (rows of dirs), exact on the
+        active branch (tangent build only)."""
+        if not self.tangent:
+            raise ValueError("construct the oracle with tangent=True")
+        u = self._u(u)
+        D = self._dirs(dirs)
+        width = int(self._lib.or_ndir())
+        L = np.zeros_like(u)
+        JD = np.zeros_like(D)
+        for k0 in range(0, max(D.shape[0], 1), width):
+            blk = np.ascontiguousarray(D[k0:k0 + width])
+            out = np.zeros_like(blk)
+            if self._lib.or_rhs_tangent(C.byref(self._P), _dp(u), _dp(blk), blk.shape[0], _dp(L), _dp(out)):
+                raise MemoryError("oracle tangent rhs failed")
+            JD[k0:k0 + width] = out
+        return L, JD
+
+    def step_tangent(self, u, dirs, dt, nsteps):
+        """u(T) after nsteps RK3 steps and (d u(T) / d u0) d for every
+        direction d (rows of dirs): the exact tangent of the trajectory on its
+        active branch (tangent build only).  Directions run or_ndir() at a time."""
+        if not self.tangent:
+            raise ValueError("construct the oracle with tangent=True")
+        u0 = self._u(u)
+        D = self._dirs(dirs)
+        width = int(self._lib.or_ndir())
+        uT = None
+        JD = np.zeros_like(D)
+        for k0 in range(0, max(D.shape[0], 1), width):
+            us = u0.copy()
+            blk = np.ascontiguousarray(D[k0:k0 + width]).copy()
+            if self._lib.or_rk3_tangent(C.byref(self._P), _dp(us), _dp(blk), blk.shape[0], float(dt), int(nsteps)):
+                raise MemoryError("oracle tangent rk3 failed")
+            JD[k0:k0 + width] = blk
+            uT = us
+        return uT, JD
 
 
 def from_workload(wl, **kw) -> Oracle:

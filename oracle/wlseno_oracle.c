@@ -24,8 +24,13 @@
  * Compiled with -O2 -ffp-contract=off; per-cell loops may run under OpenMP.
  * The arithmetic type `real` is double; building with -DOR_REAL='long double'
  * gives the same algorithm in x87 extended precision, used only to measure
- * the FP64 rounding floor of individual cells.  Arrays crossing the API are
- * double in both builds.
+ * the FP64 rounding floor of individual cells.  A third build compiles this
+ * file as C++ with oracle/tangent.hpp force-included, -DOR_REAL=or_dual and
+ * -DOR_TANGENT: the same algorithm on forward-mode dual numbers, giving the
+ * exact directional derivative of the right-hand side and of the RK3
+ * trajectory with every branch held at the point (or_rhs_tangent,
+ * or_rk3_tangent at the end of this file).  Arrays crossing the API are
+ * double in every build.
  */
 #include <stdlib.h>
 #include <string.h>
@@ -35,8 +40,12 @@
 #endif
 
 #define OR_MAXDIM 3
+#ifndef OR_MAXM
 #define OR_MAXM 35
+#endif
+#ifndef OR_MAXN
 #define OR_MAXN 128
+#endif
 #define OR_MAXV 5
 #define OR_MAXF 4
 #define OR_MAXQ 8
@@ -46,6 +55,17 @@
 #define OR_REAL double
 #endif
 typedef OR_REAL real;
+/* Geometry (vertex coordinates, monomial averages, facet-point offsets) never
+ * depends on the cell averages: in the tangent build it stays plain double,
+ * which gives the same values as the FP64 build without dual-number work. */
+#ifndef OR_GREAL
+#define OR_GREAL OR_REAL
+#endif
+typedef OR_GREAL greal;
+
+#ifdef __cplusplus
+extern "C" {
+#endif
 
 enum { OR_ADVECTION = 0, OR_BURGERS = 1, OR_EULER = 2 };
 
@@ -89,10 +109,10 @@ int or_num_threads(void)
 
 /* ------------------------------------------------------------------ basis */
 
-static real factorial(int k)
+static greal factorial(int k)
 {
-    real f = 1.0;
-    for (int i = 2; i <= k; ++i) f *= (real)i;
+    greal f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= (greal)i;
     return f;
 }
 
@@ -131,10 +151,10 @@ int or_basis(int dim, int p, int *exps)
 
 /* Nearest periodic image of a coordinate difference along `axis` (1-D
  * circle: axis 0; 2-D periodic square: axes 0 and 1). */
-static real wrap(const or_problem *P, int axis, real d)
+static greal wrap(const or_problem *P, int axis, greal d)
 {
     if (P->periodic) {
-        real L = axis == 0 ? P->period : (axis == 1 ? P->period_y : 0.0);
+        greal L = axis == 0 ? P->period : (axis == 1 ? P->period_y : 0.0);
         if (L > 0.0) {
             if (d > 0.5 * L) d -= L;
             else if (d < -0.5 * L) d += L;
@@ -151,7 +171,7 @@ static real wrap(const or_problem *P, int axis, real d)
  *   prod_t l_t(x) = sum over maps s:{1..q}->{0..dim} of prod_t lambda_{s(t)} l_t(V_{s(t)}),
  * and the simplex integral of lambda^alpha is |T| dim! alpha! / (dim+|alpha|)!.
  * The sum runs over all (dim+1)^q maps. */
-static real simplex_avg(int dim, const real *verts, const real *c, const int *a)
+static greal simplex_avg(int dim, const greal *verts, const greal *c, const int *a)
 {
     int q = 0, fac_dim[8];
     for (int d = 0; d < dim; ++d)
@@ -160,30 +180,30 @@ static real simplex_avg(int dim, const real *verts, const real *c, const int *a)
     int nv = dim + 1;
     long total = 1;
     for (int t = 0; t < q; ++t) total *= nv;
-    real sum = 0.0;
+    greal sum = 0.0;
     int s[8];
     for (long code = 0; code < total; ++code) {
         long rem = code;
         for (int t = 0; t < q; ++t) { s[t] = (int)(rem % nv); rem /= nv; }
         int mult[4] = {0, 0, 0, 0};
-        real prod = 1.0;
+        greal prod = 1.0;
         for (int t = 0; t < q; ++t) {
             mult[s[t]] += 1;
             prod *= verts[s[t] * dim + fac_dim[t]] - c[fac_dim[t]];
         }
-        real mf = 1.0;
+        greal mf = 1.0;
         for (int v = 0; v < nv; ++v) mf *= factorial(mult[v]);
         sum += mf * prod;
     }
-    real avg = sum * factorial(dim) / factorial(dim + q);
-    real af = 1.0;
+    greal avg = sum * factorial(dim) / factorial(dim + q);
+    greal af = 1.0;
     for (int d = 0; d < dim; ++d) af *= factorial(a[d]);
     return avg / af;
 }
 
 double or_simplex_avg_monomial(int dim, const double *verts, const double *c, const int *a)
 {
-    real vr[(OR_MAXDIM + 1) * OR_MAXDIM], cr[OR_MAXDIM];
+    greal vr[(OR_MAXDIM + 1) * OR_MAXDIM], cr[OR_MAXDIM];
     for (int t = 0; t < (dim + 1) * dim; ++t) vr[t] = verts[t];
     for (int d = 0; d < dim; ++d) cr[d] = c[d];
     return (double)simplex_avg(dim, vr, cr, a);
@@ -194,18 +214,18 @@ double or_simplex_avg_monomial(int dim, const double *verts, const double *c, co
 static int stencil_size(const or_problem *P, int i) { return P->row_ptr[i + 1] - P->row_ptr[i]; }
 
 /* Vertices of cell j shifted to the periodic image nearest cell i. */
-static void image_vertices(const or_problem *P, int i, int j, real *out)
+static void image_vertices(const or_problem *P, int i, int j, greal *out)
 {
     int nv = P->dim + 1;
-    real shift[OR_MAXDIM] = {0.0, 0.0, 0.0};
+    greal shift[OR_MAXDIM] = {0.0, 0.0, 0.0};
     if (P->periodic)
         for (int d = 0; d < P->dim; ++d) {
-            real dd = (real)P->cent[(size_t)j * P->dim + d] - (real)P->cent[(size_t)i * P->dim + d];
+            greal dd = (greal)P->cent[(size_t)j * P->dim + d] - (greal)P->cent[(size_t)i * P->dim + d];
             shift[d] = wrap(P, d, dd) - dd;
         }
     for (int v = 0; v < nv; ++v)
         for (int d = 0; d < P->dim; ++d)
-            out[v * P->dim + d] = (real)P->cv[((size_t)j * nv + v) * P->dim + d] + shift[d];
+            out[v * P->dim + d] = (greal)P->cv[((size_t)j * nv + v) * P->dim + d] + shift[d];
 }
 
 /* A (n x m): averages over each stencil cell of the Taylor monomials about x_i. */
@@ -213,7 +233,7 @@ static void image_vertices(const or_problem *P, int i, int j, real *out)
 static void cell_matrix_rows(const or_problem *P, int i, const int *rows, int n, real *A)
 {
     int m = P->m;
-    real verts[(OR_MAXDIM + 1) * OR_MAXDIM], ci[OR_MAXDIM];
+    greal verts[(OR_MAXDIM + 1) * OR_MAXDIM], ci[OR_MAXDIM];
     for (int d = 0; d < P->dim; ++d) ci[d] = P->cent[(size_t)i * P->dim + d];
     for (int r = 0; r < n; ++r) {
         image_vertices(P, i, rows[r], verts);
@@ -393,14 +413,14 @@ int or_wls_qrcp_solve(int n, int m, const double *A, const double *w, const doub
 }
 
 /* sum_k v_k prod_d dx_d^{a_kd} / a_kd! */
-static real eval_taylor(int dim, int m, const int *exps, const real *v, const real *dx)
+static real eval_taylor(int dim, int m, const int *exps, const real *v, const greal *dx)
 {
     real acc = 0.0;
     for (int k = 0; k < m; ++k) {
         real term = v[k];
         for (int d = 0; d < dim; ++d) {
             int a = exps[3 * k + d];
-            term *= pow(dx[d], (real)a) / factorial(a);
+            term *= pow(dx[d], (greal)a) / factorial(a);
         }
         acc += term;
     }
@@ -409,7 +429,8 @@ static real eval_taylor(int dim, int m, const int *exps, const real *v, const re
 
 double or_eval_taylor(int dim, int m, const int *exps, const double *v, const double *dx)
 {
-    real vr[OR_MAXM], xr[OR_MAXDIM];
+    real vr[OR_MAXM];
+    greal xr[OR_MAXDIM];
     for (int k = 0; k < m; ++k) vr[k] = v[k];
     for (int d = 0; d < dim; ++d) xr[d] = dx[d];
     return (double)eval_taylor(dim, m, exps, vr, xr);
@@ -587,7 +608,7 @@ static int balanced_rows(const or_problem *P, int i, const real *g, int n, int *
         int j = pool[r];
         real s = 0.0;
         for (int d = 0; d < D; ++d) {
-            real dd = (real)P->cent[(size_t)j * D + d] - (real)P->cent[(size_t)i * D + d];
+            greal dd = (greal)P->cent[(size_t)j * D + d] - (greal)P->cent[(size_t)i * D + d];
             dd = wrap(P, d, dd);
             s += g[d] * dd;
         }
@@ -667,8 +688,8 @@ static void reconstruct_cell(const or_problem *P, int i, const real *u, real *co
                 if (rank && rk < rank[(size_t)k * P->nc + i]) rank[(size_t)k * P->nc + i] = rk;
                 for (int q = 0; q < P->nq; ++q) {
                     const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
-                    real dx[OR_MAXDIM];
-                    for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)i * D + d];
+                    greal dx[OR_MAXDIM];
+                    for (int d = 0; d < D; ++d) dx[d] = (greal)x[d] - (greal)P->cent[(size_t)i * D + d];
                     wq[k][q] = eval_taylor(D, m, P->exps, vk, dx);
                 }
             }
@@ -691,8 +712,8 @@ static void reconstruct_cell(const or_problem *P, int i, const real *u, real *co
         for (int lf = 0; lf < F; ++lf)
             for (int q = 0; q < P->nq; ++q) {
                 const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
-                real dx[OR_MAXDIM];
-                for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)i * D + d];
+                greal dx[OR_MAXDIM];
+                for (int d = 0; d < D; ++d) dx[d] = (greal)x[d] - (greal)P->cent[(size_t)i * D + d];
                 for (int var = 0; var < V; ++var) vals[var][lf][q] = eval_taylor(D, m, P->exps, v[var], dx);
             }
         if (P->balance && V == 1) {
@@ -727,8 +748,8 @@ static void reconstruct_cell(const or_problem *P, int i, const real *u, real *co
                 for (int lf = 0; lf < F; ++lf)
                     for (int q = 0; q < P->nq; ++q) {
                         const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
-                        real dx[OR_MAXDIM];
-                        for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)i * D + d];
+                        greal dx[OR_MAXDIM];
+                        for (int d = 0; d < D; ++d) dx[d] = (greal)x[d] - (greal)P->cent[(size_t)i * D + d];
                         vals[0][lf][q] = eval_taylor(D, m, P->exps, v[0], dx);
                     }
                 if (rebal) rebal[i] = 1;
@@ -874,14 +895,14 @@ static void divergence_cell(const or_problem *P, int i, const real *u, const rea
                  * shares with cell i */
                 const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
                 int bf = -1, bq = -1;
-                real bd = 0.0;
+                greal bd = 0.0;
                 for (int f2 = 0; f2 < F; ++f2) {
                     if (P->nbr[(size_t)j * F + f2] != i) continue;
                     for (int q2 = 0; q2 < P->nq; ++q2) {
                         const double *y = P->qx + (((size_t)j * F + f2) * P->nq + q2) * D;
-                        real dd = 0.0;
+                        greal dd = 0.0;
                         for (int d = 0; d < D; ++d) {
-                            real e = (real)y[d] - (real)x[d];
+                            greal e = (greal)y[d] - (greal)x[d];
                             e = wrap(P, d, e);
                             dd += e * e;
                         }
@@ -891,8 +912,8 @@ static void divergence_cell(const or_problem *P, int i, const real *u, const rea
                 for (int var = 0; var < V; ++var) up[var] = fval[fval_index(P, var, j, bf, bq)];
             } else {
                 const double *x = P->qx + (((size_t)i * F + lf) * P->nq + q) * D;
-                real dx[OR_MAXDIM];
-                for (int d = 0; d < D; ++d) dx[d] = (real)x[d] - (real)P->cent[(size_t)j * D + d];
+                greal dx[OR_MAXDIM];
+                for (int d = 0; d < D; ++d) dx[d] = (greal)x[d] - (greal)P->cent[(size_t)j * D + d];
                 for (int d = 0; d < D; ++d) dx[d] = wrap(P, d, dx[d]);
                 for (int var = 0; var < V; ++var) {
                     if (fallback && fallback[j])
@@ -951,30 +972,100 @@ int or_rhs(const or_problem *P, const double *u, double *dudt, double *alpha_out
     return st;
 }
 
-/* n steps of the third-order TVD Runge-Kutta scheme, in place on u (the
- * state is carried in working precision between stages and steps). */
-int or_rk3(const or_problem *P, double *u, double dt_in, int nsteps)
+/* n steps of the third-order TVD Runge-Kutta scheme, in place on the
+ * working-precision state U (carried in working precision between stages
+ * and steps):
+ *   k1 = u + dt L(u);  k2 = 3/4 u + 1/4 k1 + 1/4 dt L(k1);
+ *   u  = 1/3 u + 2/3 k2 + 2/3 dt L(k2). */
+static int rk3_real(const or_problem *P, real *U, real dt, int nsteps)
 {
     size_t N = (size_t)P->nvars * P->nc;
-    real dt = dt_in;
-    real *U = to_real(u, N);
+    int st = -1;
     real *L = (real *)malloc(N * sizeof(real));
     real *k1 = (real *)malloc(N * sizeof(real));
     real *k2 = (real *)malloc(N * sizeof(real));
-    if (!U || !L || !k1 || !k2) goto fail;
+    if (!L || !k1 || !k2) goto done;
     for (int s = 0; s < nsteps; ++s) {
-        if (rhs_real(P, U, L, NULL)) goto fail;
+        if (rhs_real(P, U, L, NULL)) goto done;
         for (size_t t = 0; t < N; ++t) k1[t] = U[t] + dt * L[t];
-        if (rhs_real(P, k1, L, NULL)) goto fail;
+        if (rhs_real(P, k1, L, NULL)) goto done;
         for (size_t t = 0; t < N; ++t) k2[t] = 0.75 * U[t] + 0.25 * k1[t] + 0.25 * dt * L[t];
-        if (rhs_real(P, k2, L, NULL)) goto fail;
+        if (rhs_real(P, k2, L, NULL)) goto done;
         for (size_t t = 0; t < N; ++t)
             U[t] = ((real)1.0 / 3.0) * U[t] + ((real)2.0 / 3.0) * k2[t] + ((real)2.0 / 3.0) * dt * L[t];
     }
-    to_double(U, u, N);
-    free(U); free(L); free(k1); free(k2);
-    return 0;
-fail:
-    free(U); free(L); free(k1); free(k2);
-    return -1;
+    st = 0;
+done:
+    free(L); free(k1); free(k2);
+    return st;
 }
+
+int or_rk3(const or_problem *P, double *u, double dt_in, int nsteps)
+{
+    size_t N = (size_t)P->nvars * P->nc;
+    real *U = to_real(u, N);
+    if (!U) return -1;
+    int st = rk3_real(P, U, (real)dt_in, nsteps);
+    if (!st) to_double(U, u, N);
+    free(U);
+    return st;
+}
+
+#ifdef OR_TANGENT
+/* ------------------------------------------------------------- tangents */
+
+/* Directions per call (the dual number's width). */
+int or_ndir(void) { return OR_NDIR; }
+
+/* The state u (nvars x nc) with ndir directions du (ndir x nvars x nc); the
+ * dual numbers carry ndir derivatives from here on. */
+static real *seed_state(const double *u, const double *du, int ndir, size_t N)
+{
+    or_nd = ndir > 0 ? ndir : 1;
+    real *U = (real *)malloc((N ? N : 1) * sizeof(real));
+    if (U)
+        for (size_t t = 0; t < N; ++t) U[t] = or_seed(u[t], du + t, ndir, N);
+    return U;
+}
+
+static void split_state(const real *U, int ndir, size_t N, double *u, double *du)
+{
+    for (size_t t = 0; t < N; ++t) {
+        u[t] = U[t].v;
+        for (int k = 0; k < ndir; ++k) du[(size_t)k * N + t] = U[t].d[k];
+    }
+}
+
+/* L(u) and its directional derivatives J(u) du_k, k < ndir <= or_ndir(). */
+int or_rhs_tangent(const or_problem *P, const double *u, const double *du, int ndir, double *dudt,
+                   double *ddudt)
+{
+    size_t N = (size_t)P->nvars * P->nc;
+    if (ndir < 0 || ndir > OR_NDIR) return -2;
+    real *U = seed_state(u, du, ndir, N);
+    real *L = (real *)malloc((N ? N : 1) * sizeof(real));
+    int st = -1;
+    if (U && L) st = rhs_real(P, U, L, NULL);
+    if (!st) split_state(L, ndir, N, dudt, ddudt);
+    free(U); free(L);
+    return st;
+}
+
+/* nsteps RK3 steps in place on u, and in place on the directions du:
+ * du_k <- (d u(T) / d u0) du_k, the exact tangent of the trajectory. */
+int or_rk3_tangent(const or_problem *P, double *u, double *du, int ndir, double dt, int nsteps)
+{
+    size_t N = (size_t)P->nvars * P->nc;
+    if (ndir < 0 || ndir > OR_NDIR) return -2;
+    real *U = seed_state(u, du, ndir, N);
+    if (!U) return -1;
+    int st = rk3_real(P, U, (real)dt, nsteps);
+    if (!st) split_state(U, ndir, N, u, du);
+    free(U);
+    return st;
+}
+#endif
+
+#ifdef __cplusplus
+}
+#endif
