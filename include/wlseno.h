@@ -260,6 +260,22 @@ wlseno_status wlseno_batch_step(wlseno_t ctx, double *u_dev, const double *dt_pe
  * n_mesh doubles; 0 for advection).  Synchronises the stream. */
 wlseno_status wlseno_batch_last_alpha(wlseno_t ctx, double *alpha_per_mesh);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * dudt_dev = L(u_dev) as wlseno_rhs, bit for bit, with every scratch buffer
+ * (stage state and result in device order, facet values, Lax-Friedrichs alpha
+ * slots) in one static array of 32 MiB per GPU inside the library, held until
+ * the process ends.  The call allocates nothing and frees nothing; it enqueues
+ * kernels only (the alpha slots are cleared by a kernel).  Limit: a mesh whose
+ * scratch exceeds 32 MiB gives EINVAL (2-D p = 3 scalar: 64 B per cell, about
+ * 520 k cells; 2-D Euler p = 4: 256 B per cell); the balanced refit gives
+ * EUNSUPPORTED.  All contexts on one GPU share the array and each call
+ * overwrites it: calls that overlap on one GPU (several host threads, or
+ * streams not ordered with each other) race and must be serialised by the
+ * caller.  wlseno_last_alpha does not see this call.  Arguments and errors as
+ * wlseno_rhs. */
+wlseno_status wlseno_rhs_noalloc(wlseno_t ctx, const double *u_dev, double *dudt_dev);
+
 /* Adjoint (scalar linear advection on a single mesh; other cases return
  * EUNSUPPORTED).  The right-hand side L(u) is differentiated on its active
  * branch: stencils, pivot order, numerical rank and the facet neighbour that

@@ -20,6 +20,7 @@ EXPORTS = [
     "wlseno_reconstruct", "wlseno_rhs", "wlseno_step", "wlseno_last_alpha", "wlseno_time_kernel",
     "wlseno_batch_add_mesh", "wlseno_batch_step", "wlseno_batch_last_alpha", "wlseno_set_graphs",
     "wlseno_rhs_vjp", "wlseno_step_adjoint", "wlseno_step_record", "wlseno_step_adjoint_recorded",
+    "wlseno_rhs_noalloc",
 ]
 
 
@@ -74,6 +75,7 @@ def load():
     lib.wlseno_get_stencil.argtypes = [vp, ip, ip]
     lib.wlseno_reconstruct.argtypes = [vp, vp, vp, vp, vp]
     lib.wlseno_rhs.argtypes = [vp, vp, vp]
+    lib.wlseno_rhs_noalloc.argtypes = [vp, vp, vp]
     lib.wlseno_step.argtypes = [vp, vp, C.c_double, C.c_int]
     lib.wlseno_last_alpha.argtypes = [vp, dp]
     lib.wlseno_time_kernel.argtypes = [vp, C.c_int, vp, C.c_int, dp]

@@ -18,6 +18,7 @@ using namespace wlseno;
 struct wlseno_ctx {
     int device = -1;
     hipStream_t stream = nullptr;
+    unsigned char *scratch = nullptr;   // this device's static scratch array (wlseno_rhs_noalloc)
     std::string err;
     bool have_mesh = false, have_build = false;
     HostMesh mesh;
@@ -348,9 +349,18 @@ wlseno_status wlseno_create(int device, wlseno_t *out)
         g_create_error = "device must be >= 0, or -1 for a host-only context";
         return WLSENO_EINVAL;
     }
+    void *scr = nullptr;
+    if (device >= 0) {
+        const int e = scratch_address(device, &scr);
+        if (e != 0) {
+            g_create_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString((hipError_t)e);
+            return WLSENO_EDEVICE;
+        }
+    }
     wlseno_ctx *c = new (std::nothrow) wlseno_ctx;
     if (!c) return WLSENO_ENOMEM;
     c->device = device;
+    c->scratch = (unsigned char *)scr;
     *out = c;
     return WLSENO_OK;
 }
@@ -514,6 +524,38 @@ wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev)
     check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
     stage(ctx, ctx->ubuf, nullptr, nullptr, ctx->tbuf, 0.0, 0.0, 1.0, 0, 0, ctx->stream);
     check_launch(launch_permute(ctx->dm, ctx->tbuf, dudt_dev, false, ctx->stream), "permute");
+    API_END(ctx)
+}
+
+wlseno_status wlseno_rhs_noalloc(wlseno_t ctx, const double *u_dev, double *dudt_dev)
+{
+    API_BEGIN(ctx)
+    if (!u_dev || !dudt_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
+    if (u_dev == dudt_dev) throw Error{WLSENO_EINVAL, "dudt_dev must not alias u_dev"};
+    need_device(ctx);
+    if (ctx->dm.balance) throw Error{WLSENO_EUNSUPPORTED, "the balanced refit keeps buffers of its own"};
+    if (!ctx->scratch) throw Error{WLSENO_ESTATE, "no scratch address on this device"};
+    // scratch layout: alpha slots (two parities), state and result in device
+    // order, facet values; each part 256-byte aligned
+    const DevMesh &cm = ctx->dm;
+    auto up256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t a_bytes = up256(2 * (size_t)cm.alpha_slots() * 16 * sizeof(unsigned long long));
+    const size_t u_bytes = up256((size_t)cm.nvars * cm.nc * sizeof(double));
+    const size_t f_bytes = up256((size_t)cm.nvars * cm.nc * cm.nf * cm.nq * sizeof(double));
+    const size_t need = a_bytes + 2 * u_bytes + f_bytes;
+    if (need > scratch_capacity())
+        throw Error{WLSENO_EINVAL, "this mesh needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                                       std::to_string(scratch_capacity()) + " of the allocation-free entry point"};
+    DevMesh dm = cm;
+    dm.alpha = (unsigned long long *)ctx->scratch;
+    double *ub = (double *)(ctx->scratch + a_bytes);
+    double *tb = (double *)(ctx->scratch + a_bytes + u_bytes);
+    dm.fv = (double *)(ctx->scratch + a_bytes + 2 * u_bytes);
+    check_launch(launch_permute(dm, u_dev, ub, true, ctx->stream), "permute");
+    check_launch(launch_clear_alpha(dm, ctx->stream), "clear");
+    check_launch(launch_reconstruct(dm, ub, 0, nullptr, nullptr, nullptr, ctx->stream), "reconstruct");
+    check_launch(launch_update(dm, nullptr, nullptr, tb, 0.0, 0.0, 1.0, 0, 0, ctx->stream), "update");
+    check_launch(launch_permute(dm, tb, dudt_dev, false, ctx->stream), "permute");
     API_END(ctx)
 }
 

@@ -158,6 +158,10 @@ int launch_adjoint_gather(const DevMesh &dm, const int64_t *tptr, const double *
 // its place (-1: padding or a boundary facet).
 void transpose_tables(const Build &b, int64_t nc, int nf, std::vector<int64_t> &tptr, std::vector<int32_t> &tpos);
 int launch_clear_alpha(const DevMesh &dm, void *stream);
+// Static scratch array of the allocation-free entry point: its size, and its
+// device address on `device` (looked up once per device; hipSuccess or an error).
+size_t scratch_capacity();
+int scratch_address(int device, void **out);
 int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *coef_user,
                        double *fv_user, int32_t *rank_user, void *stream);
 // out = L (mode 0) or A*u0 + B*prev + Cdt*L (mode 1).

@@ -23,6 +23,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -2135,6 +2136,37 @@ int launch_permute(const DevMesh &dm, const double *in, double *out, bool to_dev
     hipLaunchKernelGGL(k_permute, dim3(blocks_for(work, 256)), dim3(256), 0, (hipStream_t)stream, dm.nc,
                        dm.nvars, dm.perm, in, out, to_device_order ? 1 : 0);
     return (int)hipGetLastError();
+}
+
+// Scratch memory of the allocation-free right-hand side (wlseno_rhs_noalloc):
+// one array per GPU in the code object's static device memory, kept until the
+// process ends.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+size_t scratch_capacity() { return kScratchBytes; }
+
+int scratch_address(int device, void **out)
+{
+    static std::mutex mu;
+    static void *addr[kScratchDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kScratchDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int prev = -1;
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        hipError_t e = hipSetDevice(device);
+        void *p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
+        if (e != hipSuccess) return (int)e;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return 0;
 }
 
 int launch_clear_alpha(const DevMesh &dm, void *stream)

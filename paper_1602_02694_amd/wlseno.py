@@ -161,6 +161,15 @@ class WLSENO:
         self._check(self._lib.wlseno_rhs(self._h, _ptr(u), _ptr(out)))
         return out
 
+    def rhs_noalloc(self, u, out):
+        """rhs() through the allocation-free entry point (scratch in the
+        library's static per-GPU array); out must be preallocated."""
+        u = self._field(u)
+        out = self._field(out)
+        self._sync_stream()
+        self._check(self._lib.wlseno_rhs_noalloc(self._h, _ptr(u), _ptr(out)))
+        return out
+
     def step(self, u, dt, n_steps):
         """Advance u in place by n_steps TVD RK3 steps of size dt."""
         u = self._field(u)

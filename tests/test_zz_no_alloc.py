@@ -1,0 +1,64 @@
+"""GPU check of the allocation-free right-hand side (wlseno_rhs_noalloc).
+
+It runs the same kernels as wlseno_rhs with every scratch buffer in the
+library's static per-GPU array, so its result must equal wlseno_rhs's bit for
+bit: here on two contexts in a row, the second with a smaller mesh (the array
+keeps the first call's contents), then the first again, and a mesh whose
+scratch would exceed the array is refused before any kernel runs.
+"""
+
+import numpy as np
+import pytest
+
+from workloads import fields, jittered_square
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _ctx(mesh, **kw):
+    from paper_1602_02694_amd import WLSENO
+
+    w = WLSENO(device=0)
+    w.mesh_upload(2, mesh.verts, mesh.cells)
+    w.stencil_build(**kw)
+    return w
+
+
+def test_rhs_noalloc_equals_rhs():
+    torch = _torch()
+    big = jittered_square(60, 0.3, 7301)
+    small = jittered_square(17, 0.3, 7302)
+    print(f"[case] noalloc: {big.n_cell} Burgers cells, then {small.n_cell} Euler cells", flush=True)
+    w1 = _ctx(big, p=3, n_lo=12, n_hi=20, flux="burgers")
+    w2 = _ctx(small, p=4, n_lo=20, n_hi=36, flux="euler")
+    u1 = torch.tensor(fields.cell_averages(big, fields.gaussian_bump_with_step_2d), device="cuda")
+    u2 = torch.tensor(fields.cell_averages(small, fields.euler_quadrants(7303)).reshape(-1), device="cuda")
+    for w, u in ((w1, u1), (w2, u2), (w1, u1)):
+        ref = w.rhs(u)
+        out = torch.full_like(u, float("nan"))
+        w.rhs_noalloc(u, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        assert bool(torch.isfinite(out).all())
+
+
+def test_rhs_noalloc_refuses_oversized_scratch():
+    from paper_1602_02694_amd import WLSENOError
+
+    torch = _torch()
+    # 2-D Euler at p = 5: 352 bytes of scratch per cell, above 32 MiB here
+    mesh = jittered_square(240, 0.3, 7304)
+    w = _ctx(mesh, p=5, n_lo=24, n_hi=30, flux="euler")
+    u = torch.zeros(4 * mesh.n_cell, dtype=torch.float64, device="cuda")
+    out = torch.zeros_like(u)
+    with pytest.raises(WLSENOError) as e:
+        w.rhs_noalloc(u, out)
+    assert e.value.status == 1 and "scratch" in str(e.value)
