@@ -255,6 +255,115 @@ def run_batch(args, torch, WLSENO):
     }
 
 
+def parity_stats(g, o, tol=1e-12):
+    """GPU values g against oracle values o: per entry |g - o| / max(|o|,
+    1e-2 max|o|) (the floor keeps zeros of a field from making a relative
+    error ill-posed) -- its maximum, 99.9th percentile and count above tol --
+    and the norm-wise relative error."""
+    g = np.asarray(g, dtype=np.float64).reshape(-1)
+    o = np.asarray(o, dtype=np.float64).reshape(-1)
+    scale = np.maximum(np.abs(o), 1e-2 * np.max(np.abs(o)))
+    r = np.abs(g - o) / scale
+    return {"max_rel_err_vs_oracle": float(r.max()), "p99_9_rel_err": float(np.percentile(r, 99.9)),
+            "count_above_tolerance": int((r > tol).sum()), "entries": int(r.size),
+            "normwise_rel_err": float(np.linalg.norm(g - o) / np.linalg.norm(o)), "tolerance": tol,
+            "pass": bool(r.max() <= tol)}
+
+
+def run_line(torch, WLSENO):
+    """1-D periodic line of 200 cells (widths +-20%), p = 3, linear advection
+    of the sine + square wave, 100 TVD RK3 steps at CFL 0.5: GPU time, the
+    FP64 oracle's time on the same steps, and their parity."""
+    import oracle
+    from workloads import configs
+
+    wl = configs.line_advection(200, 1001)
+    s = wl.settings
+    kw = dict(p=s["p"], n_lo=s["n_lo"], n_hi=s["n_hi"], flux="advection", velocity=s["velocity"])
+    w = WLSENO(device=0)
+    w.mesh_upload(1, wl.mesh.verts, wl.mesh.cells, True)
+    w.stencil_build(**kw)
+    dt = s["cfl"] * w.info()["min_insphere"]
+    u0 = torch.tensor(wl.u0, device="cuda")
+    u = u0.clone()
+    w.step(u, dt, s["steps"])
+    torch.cuda.synchronize()
+    u = u0.clone()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    w.step(u, dt, s["steps"])
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - ts
+    o = oracle.Oracle(1, wl.mesh.verts, wl.mesh.cells, True, **kw)
+    ts = time.perf_counter()
+    uo = o.step(wl.u0, dt, s["steps"])[0]
+    t_cpu = time.perf_counter() - ts
+    nc = wl.mesh.n_cell
+    rec = {"workload": f"{wl.name}, {s['steps']} steps", "value": nc * s["steps"] / t_gpu,
+           "unit": "cell-updates/s", "ms_per_step": t_gpu * 1e3 / s["steps"],
+           "cpu_baseline": {"value": nc * s["steps"] / t_cpu, "cores": oracle.core.num_threads(), "kind": "oracle"},
+           "parity": parity_stats(u.cpu().numpy(), uo)}
+    log(f"[bench] line200: {rec['value']:.3g} cell-updates/s (launch-bound), oracle {rec['cpu_baseline']['value']:.3g}; "
+        f"parity after {s['steps']} steps {rec['parity']['max_rel_err_vs_oracle']:.2e}")
+    return rec
+
+
+# compulsory HBM bytes per cell-stage of the 2-D p = 3 scalar path: averages
+# in, state and stage buffers, stencil ids, geometry and moments, facet records
+B_MIN_2D_P3 = 280.0
+
+
+def run_square_large(torch, WLSENO, steps=20):
+    """The 1000 x 1000-point companion of the benchmark mesh (~2.0 M
+    triangles, same data and settings), where the working set far exceeds the
+    256 MB last-level cache: throughput, event-timed kernels, their roofline
+    fractions and the stage's algorithmic HBM fraction (cell-stages/s x 280 B
+    compulsory bytes / 8 TB/s)."""
+    t0 = time.time()
+    wl = make_workload("square-large")
+    cfg, mesh = wl.settings, wl.mesh
+    w = WLSENO(device=0)
+    w.mesh_upload(2, mesh.verts, mesh.cells)
+    w.stencil_build(p=cfg["p"], n_lo=cfg["n_lo"], n_hi=cfg["n_hi"], flux=cfg["flux"])
+    info = w.info()
+    rp, _ = w.stencil()
+    nsz = np.diff(rp)
+    dt = 0.5 * info["min_insphere"] / (np.sqrt(2.0) * float(np.max(np.abs(wl.u0))))
+    u0 = torch.tensor(wl.u0, device="cuda")
+    u = u0.clone()
+    w.step(u, dt, 4)
+    u = u0.clone()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    w.step(u, dt, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - ts
+    nc = mesh.n_cell
+    k1 = w.time_kernel(0, u0, 30)
+    k2 = w.time_kernel(1, u0, 30)
+    F, Q, m = info["faces_per_cell"], info["points_per_face"], info["m"]
+    flops = float(np.sum(recon_flops(nsz, m, 2, F, Q)))
+    ub = update_bytes(nc, 2, F, Q)
+    stage_s = el / steps / 3.0
+    alg = nc * B_MIN_2D_P3 / stage_s / 1e9
+    rec = {"workload": f"{wl.name}, {steps} steps", "n_cell": nc, "value": nc * steps / el,
+           "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
+           "stage_hbm_algorithmic": {"bytes_per_cell_stage": B_MIN_2D_P3, "achieved_GBs": alg,
+                                     "peak_GBs": HBM_PEAK_GBS, "frac": alg / HBM_PEAK_GBS},
+           "k_reconstruct": {"avg_launch_us": k1 * 1e3, "achieved_TFLOPs": flops / (k1 * 1e-3) / 1e12,
+                             "frac_fp64_peak": flops / (k1 * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                             "traffic": traffic_record("k_reconstruct", "square-large")},
+           "k_update": {"avg_launch_us": k2 * 1e3, "algorithmic_bytes": ub,
+                        "achieved_GBs": ub / (k2 * 1e-3) / 1e9, "frac_hbm_peak": ub / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "traffic": traffic_record("k_update", "square-large")},
+           "seconds": time.time() - t0}
+    log(f"[bench] square-large: {nc} cells, {rec['value']:.4g} cell-updates/s, stage HBM fraction (algorithmic) "
+        f"{rec['stage_hbm_algorithmic']['frac']:.3f}; k_reconstruct {k1 * 1e3:.1f} us "
+        f"({rec['k_reconstruct']['frac_fp64_peak']:.3f} of FP64), k_update {k2 * 1e3:.1f} us "
+        f"({rec['k_update']['frac_hbm_peak']:.3f} of HBM); {rec['seconds']:.0f}s")
+    return rec
+
+
 def exact_tangent_check(torch, w, wl, dt, steps, ckpt, rng, ndir=8):
     """The adjoint against the oracle's exact tangent (its own code on dual
     numbers, exact on the active branch), step by step along the GPU's own
@@ -294,7 +403,9 @@ def exact_tangent_check(torch, w, wl, dt, steps, ckpt, rng, ndir=8):
     worst = float(np.max(rels))
     norms = [float(torch.linalg.norm(g[k])) for k in range(steps, -1, -10)]
     o = oracle.Oracle(2, mesh.verts, mesh.cells, **kw)
+    tf = time.perf_counter()
     uo = o.step(wl.u0, dt, steps)[0]
+    tf = time.perf_counter() - tf
     drift = float(np.max(np.abs(states[-1].cpu().numpy() - uo)) / np.max(np.abs(uo)))
     secs = time.perf_counter() - t0
     log(f"[bench] adjoint vs the oracle's exact tangent, {steps} one-step segments x {ndir} directions: max rel "
@@ -305,7 +416,30 @@ def exact_tangent_check(torch, w, wl, dt, steps, ckpt, rng, ndir=8):
             "the GPU trajectory", "max_rel_err": worst, "median_rel_err": float(np.median(rels)), "tolerance": 1e-6,
             "pass": worst <= 1e-6 and composed, "one_step_adjoints_compose_to_full_call": composed,
             "gradient_norm_every_10_steps_from_T": norms, "trajectory_drift_gpu_vs_oracle": drift,
+            "oracle_forward": {"value": mesh.n_cell * steps / tf, "unit": "cell-updates/s",
+                               "cores": oracle.core.num_threads(), "kind": "oracle"},
             "seconds": secs}
+
+
+def short_tangent_check(torch, w, wl, dt, steps, rng, ndir=8):
+    """Over a horizon short enough for the GPU's and the oracle's trajectories
+    to stay together, the whole gradient at once: <g_0, d> from the GPU's
+    adjoint over `steps` steps against <g_T, J d> with J d the oracle's exact
+    tangent of its own trajectory from u_0."""
+    import oracle
+
+    mesh, s = wl.mesh, wl.settings
+    kw = dict(p=s["p"], n_lo=s["n_lo"], n_hi=s["n_hi"], flux="advection", velocity=s["velocity"], bc=s["bc"])
+    ot = oracle.Oracle(2, mesh.verts, mesh.cells, tangent=True, **kw)
+    D = rng.standard_normal((ndir, mesh.n_cell))
+    uT, JD = ot.step_tangent(wl.u0, D, dt, steps)
+    gT = uT[0] - s["target"]
+    g0 = w.step_adjoint(torch.tensor(wl.u0, device="cuda"), dt, steps, torch.tensor(gT, device="cuda"), 10)
+    g0 = g0.cpu().numpy()
+    rels = [abs(float(g0 @ D[j]) - float(gT @ JD[j])) / abs(float(gT @ JD[j])) for j in range(ndir)]
+    log(f"[bench] adjoint vs the oracle's exact tangent over {steps} steps from u0: max rel err {max(rels):.3e}")
+    return {"steps": steps, "directions": ndir, "max_rel_err": float(max(rels)), "tolerance": 1e-6,
+            "pass": max(rels) <= 1e-6}
 
 
 def run_adjoint(torch, WLSENO, steps=100, ckpt=10, directions=32):
@@ -314,8 +448,8 @@ def run_adjoint(torch, WLSENO, steps=100, ckpt=10, directions=32):
     loss 1/2 ||u(T) - u_target||^2 after `steps` RK3 steps; the gradient with
     respect to u0 from the checkpointed adjoint and its time against the
     forward run's.  Checks: the oracle's exact tangent step by step along the
-    trajectory (exact_tangent_check); Richardson-extrapolated central
-    differences over 2 steps; central differences over all steps in the
+    trajectory (exact_tangent_check) and, over the first 10 steps, as a whole
+    (short_tangent_check); central differences over all steps in the
     equal-weight limit (unit weights: a linear scheme, so differences are
     exact up to rounding).  Over 100 steps the WLS-ENO map amplifies
     perturbations ~10^12-fold, so no difference quotient resolves it there."""
@@ -374,33 +508,7 @@ def run_adjoint(torch, WLSENO, steps=100, ckpt=10, directions=32):
         rng = np.random.default_rng(5003)
         if weight_mode == 0:
             out[f"exact_tangent_{steps}_steps"] = exact_tangent_check(torch, w, wl, dt, steps, ckpt, rng)
-            # a horizon that differences resolve: the same check over 2 steps
-            n2 = 2
-
-            def forward2(x):
-                y = x.clone()
-                w.step(y, dt, n2)
-                return y
-
-            gT2 = forward2(u0) - tg
-            g02 = w.step_adjoint(u0, dt, n2, gT2, ckpt)
-            worst2 = 0.0
-            # the weights vary on the scale sqrt(eps h^2), so plain central
-            # differences carry an O(h^2) error of ~1e-5 at h = 1e-6; Richardson
-            # extrapolation of steps h and h/2 removes that term
-            for _ in range(directions):
-                d = torch.tensor(rng.standard_normal(mesh.n_cell), device="cuda")
-                h = 2e-7 * float(u0.abs().max()) / float(d.abs().max())
-                cd = [float(torch.dot(gT2, (forward2(u0 + k * d) - forward2(u0 - k * d)) / (2 * k)))
-                      for k in (h, 0.5 * h)]
-                fd = (4.0 * cd[1] - cd[0]) / 3.0
-                ad = float(torch.dot(g02, d))
-                worst2 = max(worst2, abs(fd - ad) / max(abs(ad), 1e-300))
-            log(f"[bench] {tag}: adjoint vs Richardson-extrapolated central differences over {n2} steps: "
-                f"max rel err {worst2:.3e}")
-            out[f"fd_{tag}_{n2}_steps"] = {"steps": n2, "directions": directions, "max_rel_err": worst2,
-                                           "tolerance": 1e-6, "pass": worst2 <= 1e-6,
-                                           "max_abs_gradient": float(g02.abs().max())}
+            out["exact_tangent_10_steps_from_u0"] = short_tangent_check(torch, w, wl, dt, 10, rng)
         else:
             worst = 0.0
             for _ in range(directions):
@@ -438,6 +546,10 @@ def main():
                     help="skip the adjoint/forward measurement of the default workload")
     ap.add_argument("--adjoint-fd", type=int, default=32,
                     help="random directions of the adjoint's finite-difference check")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further timed runs of the same K steps (median, min, max reported)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2 M-triangle companion record of the default workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs a mesh, or a "
@@ -488,6 +600,18 @@ def main():
     nc = mesh.n_cell
     value = nc * args.steps / elapsed
     log(f"[bench] {args.steps} steps in {elapsed * 1e3:.2f} ms -> {value:.4g} cell-updates/s")
+    # the same K timed steps again, for the spread
+    rep = []
+    for _ in range(args.repeats):
+        u = u_init.clone()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        w.step(u, dt, args.steps)
+        torch.cuda.synchronize()
+        rep.append(nc * args.steps / (time.perf_counter() - ts))
+    if rep:
+        log(f"[bench] {len(rep)} more runs of {args.steps} steps: median {np.median(rep):.4g}, "
+            f"min {min(rep):.4g}, max {max(rep):.4g} cell-updates/s")
 
     # a plain device copy of known size, so that hardware traffic counters of a
     # profiled run can be calibrated (bytes read and written = 2 x 512 MiB)
@@ -563,6 +687,9 @@ def main():
         "roofline": roofline,
         "roofline_update": roofline_update,
     }
+    if rep:
+        out["repeat_timing"] = {"runs": len(rep), "steps_each": args.steps, "median_value": float(np.median(rep)),
+                                "min_value": float(min(rep)), "max_value": float(max(rep))}
 
     if args.cpu_seconds > 0 and args.workload == "square":
         import oracle
@@ -581,17 +708,30 @@ def main():
         w.step(ug, dt, S)
         torch.cuda.synchronize()
         g = ug.cpu().numpy()
-        scale = np.maximum(np.abs(uo), 1e-2 * np.max(np.abs(uo)))
-        err = float(np.max(np.abs(g - uo) / scale))
+        # the same oracle on one thread, over a shorter sample
+        S1 = int(max(2, min(S, 0.5 * args.cpu_seconds / max(one * nthreads, 1e-6))))
+        prev = oracle.core.set_num_threads(1)
+        tt = time.perf_counter()
+        o.step(u0, dt, S1)
+        cpu1 = time.perf_counter() - tt
+        oracle.core.set_num_threads(prev)
         out["cpu_baseline"] = {
             "value": nc * S / cpu_t,
             "unit": "cell-updates/s",
             "cores": nthreads,
             "kind": "oracle",
             "sample": f"{S} TVD RK3 steps of the same workload from the same initial data",
+            "one_core": {"value": nc * S1 / cpu1, "cores": 1, "sample": f"{S1} TVD RK3 steps"},
+            "host_cpu_count": os.cpu_count(),
         }
-        out["parity"] = {"steps": S, "max_rel_err_vs_oracle": err, "tolerance": 1e-12, "pass": err <= 1e-12}
-        log(f"[bench] oracle {nc * S / cpu_t:.4g} cell-updates/s; GPU vs oracle after {S} steps: {err:.3e}")
+        out["parity"] = dict(steps=S, **parity_stats(g, uo))
+        log(f"[bench] oracle {nc * S / cpu_t:.4g} cell-updates/s on {nthreads} threads, {nc * S1 / cpu1:.4g} on one; "
+            f"GPU vs oracle after {S} steps: max {out['parity']['max_rel_err_vs_oracle']:.3e}, "
+            f"99.9% {out['parity']['p99_9_rel_err']:.3e}, norm-wise {out['parity']['normwise_rel_err']:.3e}")
+    if args.workload == "square" and args.cpu_seconds > 0:
+        out["line200"] = run_line(torch, WLSENO)
+    if args.workload == "square" and not args.no_large:
+        out["square_large"] = run_square_large(torch, WLSENO)
     if args.workload == "square" and not args.no_adjoint:
         out["adjoint"] = run_adjoint(torch, WLSENO, directions=args.adjoint_fd)
     print(json.dumps(out), flush=True)

@@ -77,6 +77,7 @@ def lib(extended: bool = False, tangent: bool = False):
         _lib.or_rhs.argtypes = [pp, dp, dp, dp]
         _lib.or_rk3.argtypes = [pp, dp, C.c_double, C.c_int]
         _lib.or_num_threads.argtypes = []
+        _lib.or_set_num_threads.argtypes = [C.c_int]
         if tangent:
             _lib.or_ndir.argtypes = []
             _lib.or_rhs_tangent.argtypes = [pp, dp, dp, C.c_int, dp, dp]
@@ -86,6 +87,11 @@ def lib(extended: bool = False, tangent: bool = False):
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> int:
+    """Threads of the FP64 build's per-cell loops from now on; returns the previous count."""
+    return int(lib().or_set_num_threads(int(n)))
 
 
 class _Problem(C.Structure):

@@ -107,6 +107,17 @@ int or_num_threads(void)
 #endif
 }
 
+/* Use n threads in later per-cell loops (timing on one core); returns the
+ * previous count. */
+int or_set_num_threads(int n)
+{
+    int prev = or_num_threads();
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#endif
+    return prev;
+}
+
 /* ------------------------------------------------------------------ basis */
 
 static greal factorial(int k)

@@ -181,6 +181,29 @@ def test_step_adjoint_against_oracle_reference(n, h_rel, tol, bc):
         assert abs(got - ref) <= tol * abs(ref), (trial, got, ref)
 
 
+@pytest.mark.parametrize("n,p,bc,torus", [(2, 3, 0, False), (30, 3, 0, False), (30, 3, 1, False), (30, 3, 0, True),
+                                          (12, 4, 0, False)])
+def test_step_adjoint_against_oracle_tangent(n, p, bc, torus):
+    """The gradient of the whole trajectory against the oracle's exact tangent
+    (its own code on dual numbers, same active branch) along 8 seeded
+    directions: <g_0, d> = <g_T, J d>."""
+    import oracle
+
+    torch = _torch()
+    mesh, w, kw, u0, target = _setup(p=p, bc=bc, torus=torus)
+    _say(f"[case] adjoint vs oracle tangent: n={n} p={p} bc={bc} torus={torus} n_cell={mesh.n_cell}")
+    ot = oracle.Oracle(2, mesh.verts, mesh.cells, mesh.periodic, tangent=True, **kw)
+    dt = 0.5 * w.info()["min_insphere"] / float(np.hypot(1.0, 0.5))
+    D = np.random.default_rng(5404).standard_normal((8, mesh.n_cell))
+    uT, JD = ot.step_tangent(u0, D, dt, n)
+    gT = uT[0] - target
+    g0 = w.step_adjoint(torch.tensor(u0, device="cuda"), dt, n, torch.tensor(gT, device="cuda"), 7)
+    g0 = g0.cpu().numpy()
+    for j in range(D.shape[0]):
+        a, b = float(g0 @ D[j]), float(gT @ JD[j])
+        assert abs(a - b) <= 1e-9 * abs(b), (j, a, b)
+
+
 def test_step_adjoint_checkpoints_and_autograd():
     torch = _torch()
     from paper_1602_02694_amd.autograd import trajectory
