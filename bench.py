@@ -270,6 +270,46 @@ def parity_stats(g, o, tol=1e-12):
             "pass": bool(r.max() <= tol)}
 
 
+def sampled_parity(torch, w, wl, u_dev, kw, n_random=24, n_boundary=8, R=3, seed=9105):
+    """Parity of a mesh too large for the whole-mesh oracle: seeded random and
+    boundary cells against the FP64 oracle on the sub-mesh of every cell
+    within R vertex rings of them (the oracle helpers of the test suite; on
+    small meshes that sub-mesh oracle equals the whole-mesh one bit for bit at
+    the sampled cells): stencils, facet values and right-hand sides, and the
+    oracle's time for one RK3 step of the sub-mesh."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from submesh import SubOracle, sample_cells
+    import oracle
+
+    t0 = time.perf_counter()
+    mesh = wl.mesh
+    sample = sample_cells(mesh, n_random, n_boundary, seed)
+    sub = SubOracle(mesh, wl.u0, sample, R, **kw)
+    rp, col = w.stencil()
+    same = all(np.array_equal(col[rp[i]:rp[i + 1]], r) for i, r in zip(sample, sub.stencil_rows()))
+    idx = torch.tensor(sample, device=u_dev.device)
+    fv = w.reconstruct(u_dev)["fval"][:, idx].cpu().numpy()
+    L = w.rhs(u_dev)
+    L = L.reshape(sub.u.shape[0], -1)[:, idx].cpu().numpy()
+    ref = sub.o.reconstruct(sub.u)["fval"][:, sub.loc]
+    Lo, _ = sub.o.rhs(sub.u)
+    Lo = Lo.reshape(sub.u.shape[0], -1)[:, sub.loc]
+    tt = time.perf_counter()
+    sub.o.step(sub.u, 1e-4, 1)
+    t_step = time.perf_counter() - tt
+    rec = {"sampled_cells": int(len(sample)), "submesh_cells": int(len(sub.keep)), "stencils_equal": bool(same),
+           "facet_values": parity_stats(fv, ref), "rhs": parity_stats(L, Lo),
+           "cpu_baseline": {"value": len(sub.keep) / t_step, "unit": "cell-updates/s",
+                            "cores": oracle.core.num_threads(), "kind": "oracle",
+                            "sample": f"one TVD RK3 step of the {len(sub.keep)}-cell sub-mesh"},
+           "seconds": time.perf_counter() - t0}
+    log(f"[bench] sampled parity, {len(sample)} cells (sub-mesh {len(sub.keep)}): stencils equal {same}; facet "
+        f"values max {rec['facet_values']['max_rel_err_vs_oracle']:.2e}, rhs max "
+        f"{rec['rhs']['max_rel_err_vs_oracle']:.2e} (norm-wise {rec['rhs']['normwise_rel_err']:.2e}); oracle "
+        f"{rec['cpu_baseline']['value']:.3g} cell-updates/s")
+    return rec
+
+
 def run_line(torch, WLSENO):
     """1-D periodic line of 200 cells (widths +-20%), p = 3, linear advection
     of the sine + square wave, 100 TVD RK3 steps at CFL 0.5: GPU time, the
@@ -728,6 +768,12 @@ def main():
         log(f"[bench] oracle {nc * S / cpu_t:.4g} cell-updates/s on {nthreads} threads, {nc * S1 / cpu1:.4g} on one; "
             f"GPU vs oracle after {S} steps: max {out['parity']['max_rel_err_vs_oracle']:.3e}, "
             f"99.9% {out['parity']['p99_9_rel_err']:.3e}, norm-wise {out['parity']['normwise_rel_err']:.3e}")
+    if args.workload in ("cube", "square-large") and args.cpu_seconds > 0 and not args.balance:
+        kwp = dict(p=cfg["p"], n_lo=cfg["n_lo"], n_hi=cfg["n_hi"], flux=cfg["flux"], velocity=cfg["velocity"])
+        if cfg["flux"] == "burgers":
+            kwp["lf_alpha"] = 1       # the global alpha needs every cell; the local one is checked
+            w.stencil_build(**kwp)
+        out["sampled_parity"] = sampled_parity(torch, w, wl, u_init, kwp, R=3 if dim == 3 else 4)
     if args.workload == "square" and args.cpu_seconds > 0:
         out["line200"] = run_line(torch, WLSENO)
     if args.workload == "square" and not args.no_large:

@@ -135,6 +135,28 @@ def test_cube_advection_sampled():
     _check_sample(w, u, sub, "cube40")
 
 
+def test_cube_full_size_sampled():
+    """The 3-D benchmark mesh itself: a Delaunay tetrahedralisation of the
+    jittered 74^3 lattice (2,681,294 tetrahedra), advection p = 3, 30-50 cell
+    stencils, sine plus sphere data; 32 sampled cells (random and on the
+    boundary) against the sub-mesh oracle.  Generating the mesh takes the
+    host about two minutes."""
+    import time
+
+    torch = _torch()
+    t = time.time()
+    wl = configs.cube_advection(74, 4001)
+    mesh, u0, s = wl.mesh, wl.u0, wl.settings
+    _say(f"[case] cube74 advection: n_cell={mesh.n_cell} (mesh and averages in {time.time() - t:.0f}s)")
+    kw = dict(p=s["p"], n_lo=s["n_lo"], n_hi=s["n_hi"], flux=s["flux"], velocity=s["velocity"])
+    sample = sample_cells(mesh, 24, 8, 9105)
+    u = torch.tensor(u0, device="cuda")
+    w = _gpu(mesh, **kw)
+    _say(f"[case] cube74: library set up at {time.time() - t:.0f}s")
+    sub = SubOracle(mesh, u0, sample, 3, **kw)
+    _check_sample(w, u, sub, "cube74")
+
+
 def test_adjoint_workload_sampled():
     """The adjoint workload's 200 k triangles (advection p = 3, zero outside
     state): sampled facet values and rhs, and <J(u)^T x, d> with x on the
