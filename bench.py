@@ -158,6 +158,9 @@ def run_batch(args, torch, WLSENO):
     log(f"[bench] batch setup {time.time() - t:.1f}s")
     u0 = np.concatenate([w.u0 for w in wls], axis=1)
     u_init = torch.tensor(u0.reshape(-1), device="cuda")
+    tune = wb.autotune(u_init)
+    log(f"[bench] autotuned reconstruction: {tune['chosen']} lanes per cell "
+        f"({', '.join(f'{k}: {v:.1f} us' for k, v in tune['timings_us'].items())})")
     wb.rhs(u_init)
     alphas = wb.batch_last_alpha()
     dts = np.array([0.5 * insphere_diameters(w.mesh).min() / a for w, a in zip(wls, alphas)])
@@ -180,7 +183,9 @@ def run_batch(args, torch, WLSENO):
         c = WLSENO(device=0)
         c.mesh_upload(2, w.mesh.verts, w.mesh.cells)
         c.stencil_build(**kw)
-        singles.append((c, torch.tensor(w.u0.reshape(-1), device="cuda"), dt))
+        ui = torch.tensor(w.u0.reshape(-1), device="cuda")
+        c.autotune(ui)
+        singles.append((c, ui, dt))
     for c, ui, dt in singles:
         c.step(ui.clone(), dt, args.warmup)
     torch.cuda.synchronize()
@@ -242,6 +247,7 @@ def run_batch(args, torch, WLSENO):
             "flux": "2-D Euler (gamma 1.4), per-mesh global Lax-Friedrichs alpha, quadrant Riemann data",
             "time_integrator": "TVD RK3, per-mesh dt, HIP-graph replay",
         },
+        "autotune": tune,
         "per_mesh_loop": {"value": nc * args.steps / el_loop, "ms_per_step": el_loop * 1e3 / args.steps,
                           "batch_speedup": el_loop / elapsed, "bitwise_equal_to_batch": same},
         "roofline": {"bound": "alu", "kernel": "k_reconstruct", "achieved": achieved,
@@ -255,14 +261,16 @@ def run_batch(args, torch, WLSENO):
     }
 
 
-def parity_stats(g, o, tol=1e-12):
+def parity_stats(g, o, tol=1e-12, scale=None):
     """GPU values g against oracle values o: per entry |g - o| / max(|o|,
     1e-2 max|o|) (the floor keeps zeros of a field from making a relative
-    error ill-posed) -- its maximum, 99.9th percentile and count above tol --
-    and the norm-wise relative error."""
+    error ill-posed; `scale`, if given, raises it further) -- its maximum,
+    99.9th percentile and count above tol -- and the norm-wise relative
+    error."""
     g = np.asarray(g, dtype=np.float64).reshape(-1)
     o = np.asarray(o, dtype=np.float64).reshape(-1)
-    scale = np.maximum(np.abs(o), 1e-2 * np.max(np.abs(o)))
+    scale0 = np.maximum(np.abs(o), 1e-2 * np.max(np.abs(o)))
+    scale = scale0 if scale is None else np.maximum(scale0, np.asarray(scale, dtype=np.float64).reshape(-1))
     r = np.abs(g - o) / scale
     return {"max_rel_err_vs_oracle": float(r.max()), "p99_9_rel_err": float(np.percentile(r, 99.9)),
             "count_above_tolerance": int((r > tol).sum()), "entries": int(r.size),
@@ -291,14 +299,20 @@ def sampled_parity(torch, w, wl, u_dev, kw, n_random=24, n_boundary=8, R=3, seed
     fv = w.reconstruct(u_dev)["fval"][:, idx].cpu().numpy()
     L = w.rhs(u_dev)
     L = L.reshape(sub.u.shape[0], -1)[:, idx].cpu().numpy()
-    ref = sub.o.reconstruct(sub.u)["fval"][:, sub.loc]
-    Lo, _ = sub.o.rhs(sub.u)
+    from parity import flux_scale
+
+    rec_o = sub.o.reconstruct(sub.u)
+    ref = rec_o["fval"][:, sub.loc]
+    Lo, alpha_o = sub.o.rhs(sub.u)
     Lo = Lo.reshape(sub.u.shape[0], -1)[:, sub.loc]
+    # L_i differences fluxes: its rounding is relative to the flux sum S_i
+    S = np.asarray(flux_scale(sub.o, rec_o["fval"], alpha_o)).reshape(sub.u.shape[0], -1)[:, sub.loc]
     tt = time.perf_counter()
     sub.o.step(sub.u, 1e-4, 1)
     t_step = time.perf_counter() - tt
     rec = {"sampled_cells": int(len(sample)), "submesh_cells": int(len(sub.keep)), "stencils_equal": bool(same),
-           "facet_values": parity_stats(fv, ref), "rhs": parity_stats(L, Lo),
+           "facet_values": parity_stats(fv, ref), "rhs": parity_stats(L, Lo, scale=S),
+           "rhs_against_own_magnitude": parity_stats(L, Lo),
            "cpu_baseline": {"value": len(sub.keep) / t_step, "unit": "cell-updates/s",
                             "cores": oracle.core.num_threads(), "kind": "oracle",
                             "sample": f"one TVD RK3 step of the {len(sub.keep)}-cell sub-mesh"},
@@ -370,6 +384,7 @@ def run_square_large(torch, WLSENO, steps=20):
     nsz = np.diff(rp)
     dt = 0.5 * info["min_insphere"] / (np.sqrt(2.0) * float(np.max(np.abs(wl.u0))))
     u0 = torch.tensor(wl.u0, device="cuda")
+    tune = w.autotune(u0)
     u = u0.clone()
     w.step(u, dt, 4)
     u = u0.clone()
@@ -388,6 +403,7 @@ def run_square_large(torch, WLSENO, steps=20):
     alg = nc * B_MIN_2D_P3 / stage_s / 1e9
     rec = {"workload": f"{wl.name}, {steps} steps", "n_cell": nc, "value": nc * steps / el,
            "unit": "cell-updates/s", "ms_per_step": el * 1e3 / steps,
+           "autotune": tune,
            "stage_hbm_algorithmic": {"bytes_per_cell_stage": B_MIN_2D_P3, "achieved_GBs": alg,
                                      "peak_GBs": HBM_PEAK_GBS, "frac": alg / HBM_PEAK_GBS},
            "k_reconstruct": {"avg_launch_us": k1 * 1e3, "achieved_TFLOPs": flops / (k1 * 1e-3) / 1e12,
@@ -624,6 +640,9 @@ def main():
         speed = float(np.linalg.norm(cfg["velocity"][:dim]))
     dt = 0.5 * info["min_insphere"] / speed
     u_init = torch.tensor(u0, device="cuda")
+    tune = w.autotune(u_init)
+    log(f"[bench] autotuned reconstruction: {tune['chosen']} lanes per cell "
+        f"({', '.join(f'{k}: {v:.2f} us' for k, v in tune['timings_us'].items())})")
 
     # warm-up
     u = u_init.clone()
@@ -726,6 +745,7 @@ def main():
         },
         "roofline": roofline,
         "roofline_update": roofline_update,
+        "autotune": tune,
     }
     if rep:
         out["repeat_timing"] = {"runs": len(rep), "steps_each": args.steps, "median_value": float(np.median(rep)),

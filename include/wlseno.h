@@ -237,6 +237,19 @@ wlseno_status wlseno_last_alpha(wlseno_t ctx, double *alpha);
  * are identical either way.  The default is enabled. */
 wlseno_status wlseno_set_graphs(wlseno_t ctx, int enable);
 
+/* How wlseno_step and wlseno_batch_step launch their stages: 0 = two kernels
+ * per stage, launched directly; 1 (the default) = the same kernels replayed
+ * from HIP graphs as described for wlseno_set_graphs; 2 = all steps in one
+ * cooperative launch of a persistent kernel whose workgroups (as many as fit
+ * on the device at once) run every stage's reconstruction and update phases
+ * with a device-wide barrier after each.  Results are identical in every
+ * mode.  Mode 2 is compiled for 2-D p = 3 advection and Burgers with 2 lanes
+ * per cell and no balanced refit (else the stepping call returns
+ * EUNSUPPORTED); its barrier waits are bounded, and wlseno_step then waits for
+ * the device and returns EDEVICE if a barrier timed out.  EINVAL for another
+ * mode.  wlseno_set_graphs(ctx, e) is wlseno_set_step_mode(ctx, e ? 1 : 0). */
+wlseno_status wlseno_set_step_mode(wlseno_t ctx, int mode);
+
 /* Batches of independent meshes (several meshes stepped by one set of
  * launches).  Each call appends one mesh (host arrays, copied; no flags) and
  * returns its index in *mesh_id (nullable).  The meshes must share dim.  The
@@ -306,6 +319,31 @@ wlseno_status wlseno_step_adjoint(wlseno_t ctx, const double *u0_dev, double dt,
  * record (ESTATE until the next record).  Arguments as wlseno_step_adjoint. */
 wlseno_status wlseno_step_record(wlseno_t ctx, double *u_dev, double dt, int n_steps, int ckpt_every);
 wlseno_status wlseno_step_adjoint_recorded(wlseno_t ctx, const double *gT_dev, double *g0_dev);
+
+/* Result of wlseno_autotune. */
+typedef struct {
+    int32_t n;          /* lane counts timed (at most 4) */
+    int32_t lanes[4];   /* each lane count per cell timed */
+    double us[4];       /* its average reconstruction launch, microseconds */
+    int32_t chosen;     /* the fastest: the context uses it from now on */
+    int32_t cached;     /* 1 when taken, without timing, from this process's earlier result for the
+                           same device, kernel build and workload class */
+} wlseno_tune;
+
+/* Launch-shape autotuner of the reconstruction kernel: times every lane count
+ * per cell compiled for this build (2-D p = 3: 2, 4, 8, 16; p = 4: 4, 8, 16;
+ * p = 5 and 3-D p = 3: 8, 16; otherwise one) on this mesh, back-to-back launches
+ * between HIP events (~20 ms each), and keeps the fastest for this context
+ * (captured step graphs are dropped and recaptured).  Fewer lanes per cell
+ * hold more stencil rows per lane (more registers, fewer resident waves);
+ * more lanes add exchanges per column.  The choice is cached in the process
+ * per device, kernel build and workload class (dim, p, flux variant,
+ * components, smallest and largest stencil, share of cells per stencil-size
+ * bucket in tenths, cell count to the next power of two).  u_dev: the state
+ * to time on (double[n_vars * n_cell], user order), or NULL for a smooth
+ * synthetic state.  A rebuild (wlseno_stencil_build) returns to
+ * wlseno_params.lanes.  Synchronises the stream. */
+wlseno_status wlseno_autotune(wlseno_t ctx, const double *u_dev, wlseno_tune *out);
 
 /* Kernel timing for measurement.  Reconstructs u_dev (user order, n_cell
  * doubles on the device, not modified) once, then records a HIP event on the

@@ -20,7 +20,7 @@ EXPORTS = [
     "wlseno_reconstruct", "wlseno_rhs", "wlseno_step", "wlseno_last_alpha", "wlseno_time_kernel",
     "wlseno_batch_add_mesh", "wlseno_batch_step", "wlseno_batch_last_alpha", "wlseno_set_graphs",
     "wlseno_rhs_vjp", "wlseno_step_adjoint", "wlseno_step_record", "wlseno_step_adjoint_recorded",
-    "wlseno_rhs_noalloc",
+    "wlseno_rhs_noalloc", "wlseno_set_step_mode", "wlseno_autotune",
 ]
 
 
@@ -39,6 +39,13 @@ class Info(C.Structure):
         ("points_per_face", C.c_int32), ("min_stencil", C.c_int32), ("max_stencil", C.c_int32),
         ("n_mesh", C.c_int32), ("n_cell", C.c_int64), ("nnz", C.c_int64), ("h", C.c_double),
         ("min_insphere", C.c_double),
+    ]
+
+
+class Tune(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("lanes", C.c_int32 * 4), ("us", C.c_double * 4), ("chosen", C.c_int32),
+        ("cached", C.c_int32),
     ]
 
 
@@ -83,6 +90,8 @@ def load():
     lib.wlseno_batch_step.argtypes = [vp, vp, dp, C.c_int]
     lib.wlseno_batch_last_alpha.argtypes = [vp, dp]
     lib.wlseno_set_graphs.argtypes = [vp, C.c_int]
+    lib.wlseno_set_step_mode.argtypes = [vp, C.c_int]
+    lib.wlseno_autotune.argtypes = [vp, vp, C.POINTER(Tune)]
     lib.wlseno_rhs_vjp.argtypes = [vp, vp, vp, vp]
     lib.wlseno_step_adjoint.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, vp, vp]
     lib.wlseno_step_record.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int]

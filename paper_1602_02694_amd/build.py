@@ -10,6 +10,7 @@ arithmetic fix the stencil order).
 
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -49,8 +50,12 @@ def build(verbose: bool = False) -> str:
     _run([cxx] + CXX_FLAGS + ["-ffp-contract=off", "-fopenmp"] + inc +
          ["-c", os.path.join(CSRC, "setup.cpp"), "-o", o], verbose)
     objs.append(o)
+    # the autotuner caches results per kernel build: a digest of the device sources
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "grid_sync.hpp", "internal.hpp"):
+        h.update(open(os.path.join(CSRC, name), "rb").read())
     o = os.path.join(BUILD, "api.o")
-    _run([cxx] + CXX_FLAGS + ["-D__HIP_PLATFORM_AMD__"] + inc +
+    _run([cxx] + CXX_FLAGS + ["-D__HIP_PLATFORM_AMD__", '-DWLSENO_BUILD_ID="%s"' % h.hexdigest()[:16]] + inc +
          ["-c", os.path.join(CSRC, "api.cpp"), "-o", o], verbose)
     objs.append(o)
     tmp = LIB + ".tmp"

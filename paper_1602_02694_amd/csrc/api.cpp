@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -35,11 +37,15 @@ struct wlseno_ctx {
     std::vector<Part> parts;
     std::vector<double> batch_xyz;
     std::vector<int32_t> batch_cells;
+    std::vector<double> batch_h;   // each mesh's mean edge length
+    bool batch_pending = false;    // meshes added since the union was last set up
     std::vector<double> dt_host;   // per-mesh time steps last sent to the device
     // RK3 steps replayed from captured HIP graphs of kGraphSteps[g] steps (an
     // even number: stage parities 0,1,0,1,... start and end alike), captured
     // on a private stream for one stage scale
     bool use_graphs = true;
+    int step_mode = 1;            // 0 direct launches, 1 graph replay, 2 one persistent launch
+    unsigned *sync = nullptr;     // persistent launch: barrier counter and failure flag
     hipStream_t cap = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     double graph_h[2] = {0.0, 0.0};
@@ -95,6 +101,7 @@ void free_device(wlseno_ctx *c)
     c->allocs.clear();
     c->dm = DevMesh{};
     c->ubuf = c->kbuf = c->tbuf = nullptr;
+    c->sync = nullptr;
     c->adj_ready = false;
     c->tptr = nullptr;
     c->tpos = nullptr;
@@ -282,6 +289,8 @@ hipGraphExec_t steps_graph(wlseno_ctx *c, double h, int g)
     return ex;
 }
 
+double time_launches(wlseno_ctx *ctx, int kernel, int launches);
+
 }  // namespace
 
 #define API_BEGIN(ctx)                                                   \
@@ -378,6 +387,17 @@ wlseno_status wlseno_set_graphs(wlseno_t ctx, int enable)
 {
     API_BEGIN(ctx)
     ctx->use_graphs = enable != 0;
+    ctx->step_mode = enable ? 1 : 0;
+    if (!ctx->use_graphs) drop_graph(ctx);
+    API_END(ctx)
+}
+
+wlseno_status wlseno_set_step_mode(wlseno_t ctx, int mode)
+{
+    API_BEGIN(ctx)
+    if (mode < 0 || mode > 2) throw Error{WLSENO_EINVAL, "step mode must be 0, 1 or 2"};
+    ctx->step_mode = mode;
+    ctx->use_graphs = mode == 1;
     if (!ctx->use_graphs) drop_graph(ctx);
     API_END(ctx)
 }
@@ -410,6 +430,8 @@ wlseno_status wlseno_mesh_upload(wlseno_t ctx, int dim, int64_t n_vert, const do
     ctx->parts.clear();
     ctx->batch_xyz.clear();
     ctx->batch_cells.clear();
+    ctx->batch_h.clear();
+    ctx->batch_pending = false;
     API_END(ctx)
 }
 
@@ -432,22 +454,15 @@ wlseno_status wlseno_batch_add_mesh(wlseno_t ctx, int dim, int64_t n_vert, const
     ctx->batch_xyz.insert(ctx->batch_xyz.end(), xyz, xyz + n_vert * dim);
     for (int64_t t = 0; t < n_cell * (dim + 1); ++t) ctx->batch_cells.push_back((int32_t)(cells[t] + nv0));
     ctx->parts.push_back({n_vert, n_cell});
-    // the union of the meshes so far (disjoint, so stencils stay within a mesh)
-    HostMesh m;
-    mesh_setup(m, dim, nv0 + n_vert, ctx->batch_xyz.data(), nc0 + n_cell, ctx->batch_cells.data(), 0);
-    m.nmesh = (int)ctx->parts.size();
-    m.mesh_of.resize(m.nc);
-    m.mesh_h = ctx->mesh.mesh_h;
-    if (ctx->parts.size() == 1) m.mesh_h.clear();
-    m.mesh_h.push_back(one.h);
-    int64_t at = 0;
-    for (int k = 0; k < m.nmesh; ++k)
-        for (int64_t i = 0; i < ctx->parts[k].nc; ++i) m.mesh_of[at++] = k;
+    ctx->batch_h.push_back(one.h);
+    // the union (disjoint meshes, so stencils stay within a mesh) is set up
+    // once, by the next stencil build: adding n meshes stays linear in size
     free_device(ctx);
-    ctx->mesh = std::move(m);
+    ctx->mesh = HostMesh{};
     ctx->have_mesh = true;
     ctx->have_build = false;
     ctx->build = Build{};
+    ctx->batch_pending = true;
     if (mesh_id) *mesh_id = (int32_t)ctx->parts.size() - 1;
     API_END(ctx)
 }
@@ -457,6 +472,25 @@ wlseno_status wlseno_stencil_build(wlseno_t ctx, const wlseno_params *params)
     API_BEGIN(ctx)
     if (!params) throw Error{WLSENO_EINVAL, "params is NULL"};
     if (!ctx->have_mesh) throw Error{WLSENO_ESTATE, "call wlseno_mesh_upload first"};
+    if (ctx->batch_pending) {
+        int64_t nv = 0, nc = 0;
+        for (const auto &pt : ctx->parts) {
+            nv += pt.nv;
+            nc += pt.nc;
+        }
+        HostMesh m;
+        mesh_setup(m, ctx->batch_dim, nv, ctx->batch_xyz.data(), nc, ctx->batch_cells.data(), 0);
+        m.nmesh = (int)ctx->parts.size();
+        if (m.nmesh > 1) {
+            m.mesh_h = ctx->batch_h;
+            m.mesh_of.resize(m.nc);
+            int64_t at = 0;
+            for (int k = 0; k < m.nmesh; ++k)
+                for (int64_t i = 0; i < ctx->parts[k].nc; ++i) m.mesh_of[at++] = k;
+        }
+        ctx->mesh = std::move(m);
+        ctx->batch_pending = false;
+    }
     ctx->have_build = false;
     Build b;
     build_setup(ctx->mesh, *params, b);
@@ -733,8 +767,22 @@ void run_steps(wlseno_ctx *ctx, double *u_dev, double dt, const double *dt_mesh,
     }
     // stage coefficients c dt; for a batch the kernel multiplies c by the mesh's dt
     const double h = batch ? 1.0 : dt;
+    if (ctx->step_mode == 2 && !steps_supported(ctx->dm))
+        throw Error{WLSENO_EUNSUPPORTED, "the persistent step kernel is compiled for 2-D p = 3 scalar fluxes with "
+                                         "2 lanes per cell and no balanced refit"};
     check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
     check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
+    if (ctx->step_mode == 2) {
+        if (!ctx->sync) ctx->sync = (unsigned *)dev_alloc(ctx, 64 * sizeof(unsigned));
+        check_launch(launch_steps(ctx->dm, ctx->ubuf, ctx->kbuf, h, n_steps, ctx->sync, ctx->stream), "steps");
+        check_launch(launch_permute(ctx->dm, ctx->ubuf, u_dev, false, ctx->stream), "permute");
+        ctx->last_parity = (3 * n_steps - 1) & 1;
+        unsigned failed = 0;
+        check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        check_hip(hipMemcpy(&failed, ctx->sync + 32, sizeof failed, hipMemcpyDeviceToHost), "hipMemcpy");
+        if (failed) throw Error{WLSENO_EDEVICE, "persistent step kernel: a device-wide barrier timed out"};
+        return;
+    }
     int s = 0;
     if (ctx->use_graphs) {
         for (int g = 0; g < 2; ++g) {
@@ -832,6 +880,20 @@ wlseno_status wlseno_time_kernel(wlseno_t ctx, int kernel, const double *u_dev, 
     need_device(ctx);
     // state in device order, facet values and alpha of one reconstruction
     check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
+    *avg_ms = time_launches(ctx, kernel, launches);
+    API_END(ctx)
+}
+
+}  // extern "C"
+
+namespace {
+
+// Average duration of `launches` back-to-back launches of one stage kernel
+// (0 reconstruction, 1 flux/update) on the device-order state in ubuf,
+// between two HIP events on the context's stream, after one untimed
+// reconstruction (facet values and alpha).
+double time_launches(wlseno_ctx *ctx, int kernel, int launches)
+{
     check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
     check_launch(launch_reconstruct(ctx->dm, ctx->ubuf, 0, nullptr, nullptr, nullptr, ctx->stream), "reconstruct");
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -856,7 +918,128 @@ wlseno_status wlseno_time_kernel(wlseno_t ctx, int kernel, const double *u_dev, 
     check_launch(le, kernel == 0 ? "reconstruct" : "update");
     check_hip(he, "kernel timing events");
     ctx->last_parity = 0;
-    *avg_ms = (double)ms / launches;
+    return (double)ms / launches;
+}
+
+// A smooth, physical state in device order for timing (the solve's cost does
+// not depend on the values beyond rare pivot exchanges): scalars
+// 0.5 + 0.25 sin(2 pi x) cos(2 pi y) + 0.1 z; Euler rho = 1 + 0.2 sin(2 pi x),
+// velocity (0.3, -0.2), p = 1 + 0.1 cos(2 pi y).
+void synthetic_state(wlseno_ctx *ctx)
+{
+    const Build &b = ctx->build;
+    const int64_t nc = ctx->dm.nc;
+    const int dim = ctx->dm.dim;
+    const double tp = 6.283185307179586;
+    std::vector<double> u((size_t)b.nvars * nc);
+    for (int64_t i = 0; i < nc; ++i) {
+        const double *c = &b.geo[(size_t)i * b.gs];
+        const double x = c[0], y = dim > 1 ? c[1] : 0.0, z = dim > 2 ? c[2] : 0.0;
+        if (b.nvars == 1) {
+            u[i] = 0.5 + 0.25 * std::sin(tp * x) * std::cos(tp * y) + 0.1 * z;
+        } else {
+            const double rho = 1.0 + 0.2 * std::sin(tp * x), vx = 0.3, vy = -0.2, pr = 1.0 + 0.1 * std::cos(tp * y);
+            u[i] = rho;
+            u[nc + i] = rho * vx;
+            u[2 * nc + i] = rho * vy;
+            u[3 * nc + i] = pr / (b.prm.gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy);
+        }
+    }
+    check_hip(hipMemcpyAsync(ctx->ubuf, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream),
+              "hipMemcpyAsync");
+    check_hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+}
+
+#ifndef WLSENO_BUILD_ID
+#define WLSENO_BUILD_ID "unversioned"
+#endif
+
+// Autotuning results of this process, per device, kernel build and workload
+// class: dim, order, flux variant, components, stencil sizes and the share of
+// cells per stencil-size bucket (tenths), cell count (power of two).
+struct TuneEntry {
+    wlseno_tune result;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune_cache;
+
+std::string tune_key(wlseno_ctx *ctx)
+{
+    hipDeviceProp_t prop;
+    check_hip(hipGetDeviceProperties(&prop, ctx->device), "hipGetDeviceProperties");
+    const DevMesh &dm = ctx->dm;
+    std::string k = std::string(prop.gcnArchName) + "/" + std::to_string(prop.pciBusID) + "/" + WLSENO_BUILD_ID;
+    k += "/d" + std::to_string(dm.dim) + "p" + std::to_string(dm.p) + "f" + std::to_string(dm.flux) + "c" +
+         std::to_string(dm.characteristic) + "v" + std::to_string(dm.nvars) + "b" + std::to_string(dm.balance) +
+         "s" + std::to_string(ctx->build.min_stencil) + "-" + std::to_string(dm.max_stencil);
+    for (int t = 0; t < dm.nbuckets; ++t) {
+        const double share = dm.nc ? (double)(dm.bucket_cell0[t + 1] - dm.bucket_cell0[t]) / dm.nc : 0.0;
+        k += "/" + std::to_string((int)std::lround(10.0 * share));
+    }
+    int lg = 0;
+    while ((int64_t(1) << lg) < dm.nc) ++lg;
+    return k + "/n" + std::to_string(lg);
+}
+
+}  // namespace
+
+extern "C" {
+
+wlseno_status wlseno_autotune(wlseno_t ctx, const double *u_dev, wlseno_tune *out)
+{
+    API_BEGIN(ctx)
+    if (!out) throw Error{WLSENO_EINVAL, "out is NULL"};
+    need_device(ctx);
+    std::memset(out, 0, sizeof(*out));
+    const std::string key = tune_key(ctx);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second.result;
+            out->cached = 1;
+            if (ctx->dm.lanes != out->chosen) drop_graph(ctx);
+            ctx->dm.lanes = out->chosen;
+            ctx->build.prm.lanes = out->chosen;
+            return WLSENO_OK;
+        }
+    }
+    if (u_dev)
+        check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
+    else
+        synthetic_state(ctx);
+    const std::vector<int> cand = lane_choices(ctx->dm);
+    const int keep = ctx->dm.lanes;
+    int best = -1;
+    double best_us = 0.0;
+    try {
+        for (int lanes : cand) {
+            if (out->n >= 4) break;
+            ctx->dm.lanes = lanes;
+            // about 20 ms of launches, at least 3 and at most 200
+            const double one = time_launches(ctx, 0, 1);
+            int n = (int)(20.0 / (one > 1e-3 ? one : 1e-3));
+            n = n < 3 ? 3 : (n > 200 ? 200 : n);
+            const double us = 1e3 * time_launches(ctx, 0, n);
+            out->lanes[out->n] = lanes;
+            out->us[out->n] = us;
+            out->n += 1;
+            if (best < 0 || us < best_us) {
+                best = lanes;
+                best_us = us;
+            }
+        }
+    } catch (...) {
+        ctx->dm.lanes = keep;
+        throw;
+    }
+    out->chosen = best;
+    out->cached = 0;
+    if (keep != best) drop_graph(ctx);
+    ctx->dm.lanes = best;
+    ctx->build.prm.lanes = best;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[key] = TuneEntry{*out};
     API_END(ctx)
 }
 

@@ -141,6 +141,9 @@ constexpr int kAlphaSlotsBatch = 8;   // slots per mesh of a batch
 // Returns hipSuccess (0) or an error code; `supported` tells whether the
 // (dim, p, stencil size) combination has a compiled variant.
 bool reconstruct_supported(const DevMesh &dm);
+// Lane counts per cell compiled for the reconstruction of this build (the
+// automatic choice first is not implied; the autotuner times them all).
+std::vector<int> lane_choices(const DevMesh &dm);
 int launch_permute(const DevMesh &dm, const double *in, double *out, bool to_device_order, void *stream);
 // Transposed Jacobian of the advection right-hand side: per-cell
 // contributions written into each receiving cell's segment of contrib
@@ -158,6 +161,13 @@ int launch_adjoint_gather(const DevMesh &dm, const int64_t *tptr, const double *
 // its place (-1: padding or a boundary facet).
 void transpose_tables(const Build &b, int64_t nc, int nf, std::vector<int64_t> &tptr, std::vector<int32_t> &tpos);
 int launch_clear_alpha(const DevMesh &dm, void *stream);
+// n TVD RK3 steps of the device-order state u (stage buffer k) in one
+// cooperative launch with device-wide barriers between phases; sync: 64
+// unsigned words of device memory (arrival counter, failure flag at [32],
+// nonzero after the launch if a barrier timed out).  Compiled for 2-D p = 3
+// scalar fluxes with 2 lanes per cell.
+bool steps_supported(const DevMesh &dm);
+int launch_steps(const DevMesh &dm, double *u, double *k, double h, int nsteps, unsigned *sync, void *stream);
 // Static scratch array of the allocation-free entry point: its size, and its
 // device address on `device` (looked up once per device; hipSuccess or an error).
 size_t scratch_capacity();

@@ -28,6 +28,9 @@
 
 #include "internal.hpp"
 
+#define WLSENO_HD __device__
+#include "grid_sync.hpp"
+
 namespace wlseno {
 namespace {
 
@@ -967,15 +970,22 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     }
 }
 
-// One workgroup = 256/G cells of one stencil-size bucket, G lanes per cell.
+// LDS of a reconstruction workgroup: per cell M coefficients; for the Euler
+// system also its facet values [V][F][Q].
+template <int DIM, int P, int FLUX, int G>
+constexpr int recon_lds()
+{
+    return (recon_block(DIM) / G) *
+           (Basis<DIM, P>::M +
+            (FLUX == kFluxEuler || FLUX == kFluxEulerChar ? (DIM + 2) * (DIM + 1) * num_q<DIM, P>() : 0));
+}
+
+// Logical workgroup L of the reconstruction: 256/G (3-D) or 64/G (1-D, 2-D)
+// cells of one stencil-size bucket, G lanes per cell.
 template <int DIM, int P, int FLUX, int G, int R0, int R1, int R2, bool BAL = false>
-__global__ void __launch_bounds__(recon_block(DIM)) k_reconstruct(RArgs a)
+__device__ __forceinline__ void reconstruct_block(const RArgs &a, int L, double *lds)
 {
     constexpr int CPB = recon_block(DIM) / G;   // cells per workgroup
-    // per cell: M coefficients; for the Euler system also its facet values [V][F][Q]
-    __shared__ double lds[CPB * (Basis<DIM, P>::M +
-                                 (FLUX == kFluxEuler || FLUX == kFluxEulerChar ? (DIM + 2) * (DIM + 1) * num_q<DIM, P>() : 0))];
-    const int L = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int g = (int)(threadIdx.x % G);
     const int slot = (int)(threadIdx.x / G);
     if (L < a.blk0[1]) {
@@ -991,6 +1001,13 @@ __global__ void __launch_bounds__(recon_block(DIM)) k_reconstruct(RArgs a)
         reconstruct_cell<DIM, P, G, R2, FLUX, BAL>(a, cell, a.cell0[2], a.cell0[3], a.spad + a.spad_off[2], a.stride[2], g,
                                               lds, slot);
     }
+}
+
+template <int DIM, int P, int FLUX, int G, int R0, int R1, int R2, bool BAL = false>
+__global__ void __launch_bounds__(recon_block(DIM)) k_reconstruct(RArgs a)
+{
+    __shared__ double lds[recon_lds<DIM, P, FLUX, G>()];
+    reconstruct_block<DIM, P, FLUX, G, R0, R1, R2, BAL>(a, xcd_block((int)blockIdx.x, (int)gridDim.x), lds);
 }
 
 // Balanced-stencil refit (end of Sec. 3.2) of the cells listed by
@@ -1610,18 +1627,19 @@ __device__ __forceinline__ double point_alpha(const double (&ua)[V], const doubl
     }
 }
 
+// Logical workgroup lb of the flux/update: cells lb BS .. lb BS + BS - 1.
 template <int DIM, int Q, int FLUX, int BS>
-__global__ void __launch_bounds__(BS) k_update(UArgs a)
+__device__ __forceinline__ void update_block(const UArgs &a, int lb)
 {
     constexpr int F = DIM + 1;
     constexpr int V = FLUX == kFluxEuler ? DIM + 2 : 1;
     // 64-bit cell indices: [V][F][N][Q] offsets pass 2^32 well within 288 GB
     const int64_t N = a.nc;
-    const int64_t c0 = (int64_t)xcd_block((int)blockIdx.x, (int)gridDim.x) * BS + threadIdx.x;
+    const int64_t c0 = (int64_t)lb * BS + threadIdx.x;
     const bool live = c0 < N;
     const int64_t c = live ? c0 : N - 1;   // lanes past the end work on the last cell, store nothing
     if constexpr (FLUX != kFluxAdv) {
-        if (blockIdx.x == 0)
+        if (lb == 0)
             for (int t = (int)threadIdx.x; t < a.nslot; t += BS) a.alpha_clr[t * 16] = 0ull;
     }
     // every load is issued up front (indices clamped into this cell's own
@@ -1764,7 +1782,114 @@ __global__ void __launch_bounds__(BS) k_update(UArgs a)
     }
 }
 
+template <int DIM, int Q, int FLUX, int BS>
+__global__ void __launch_bounds__(BS) k_update(UArgs a)
+{
+    update_block<DIM, Q, FLUX, BS>(a, xcd_block((int)blockIdx.x, (int)gridDim.x));
+}
+
+// ---------------------------------------------------- persistent steps
+// n TVD RK3 steps in one cooperative launch: every stage is a reconstruction
+// phase, a device-wide barrier, a flux/update phase and another barrier, with
+// the same logical workgroups, coefficients and alpha-slot parities as the
+// stage launches (so the results are the same bits).  Physical workgroup b
+// runs on XCD b % 8; each phase's logical workgroups are split into 8
+// contiguous ranges, one per XCD, dealt out round robin among that XCD's
+// workgroups, as xcd_block does for a plain launch.
+
+struct DevSyncOps {
+    static __device__ void add_release(unsigned *p, unsigned v)
+    {
+        __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    static __device__ void acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+    static __device__ unsigned load_relaxed(unsigned *p)
+    {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    static __device__ void store_relaxed(unsigned *p, unsigned v)
+    {
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    static __device__ void pause() { __builtin_amdgcn_s_sleep(2); }
+};
+
+struct SArgs {
+    RArgs r;                      // reconstruction (state and alpha parity set per stage)
+    UArgs up;                     // flux/update (buffers and coefficients set per stage)
+    double *u, *k;                // state and stage buffer, device order
+    unsigned long long *alpha;    // both parities of alpha slots
+    double h;                     // stage scale (the time step; 1 for batches)
+    int nsteps, nb_rec, nb_upd;
+    unsigned *count, *err;        // barrier arrivals, failure flag (separate 128-byte lines)
+    unsigned max_polls;
+};
+
+// Logical workgroups [lo, hi) of XCD x when n are split into 8 contiguous ranges.
+__device__ __forceinline__ void xcd_range(int n, int x, int &lo, int &hi)
+{
+    const int per = n >> 3, rem = n & 7;
+    lo = x * per + (x < rem ? x : rem);
+    hi = lo + per + (x < rem ? 1 : 0);
+}
+
+// One wavefront per workgroup: lane 0 arrives for it; false if the barrier failed.
+__device__ __forceinline__ bool grid_barrier(const SArgs &a, unsigned epoch)
+{
+    __syncthreads();
+    int ok = 1;
+    if (threadIdx.x == 0) ok = arrive_and_wait<DevSyncOps>(a.count, a.err, gridDim.x, epoch, a.max_polls) ? 1 : 0;
+    ok = __shfl(ok, 0);
+    // lane 0 acquired; the workgroup barrier orders the other lanes after it
+    __syncthreads();
+    return ok != 0;
+}
+
+template <int DIM, int P, int FLUX, int G, int R0, int R1, int R2>
+__global__ void __launch_bounds__(64) k_steps(SArgs a)
+{
+    static_assert(recon_block(DIM) == 64, "one-wavefront reconstruction workgroups");
+    constexpr int Q = num_q<DIM, P>();
+    __shared__ double lds[recon_lds<DIM, P, FLUX, G>()];
+    const int x = (int)(blockIdx.x & 7u), i0 = (int)(blockIdx.x >> 3), nx = (int)(gridDim.x >> 3);
+    const int64_t nsl = (int64_t)a.up.nslot * 16;
+    unsigned epoch = 0;
+    int par = 0;
+    for (int s = 0; s < a.nsteps; ++s) {
+        for (int st = 0; st < 3; ++st) {
+            RArgs r = a.r;
+            r.u = st == 0 ? a.u : a.k;
+            r.alpha_acc = a.alpha + par * nsl;
+            int lo, hi;
+            xcd_range(a.nb_rec, x, lo, hi);
+            for (int L = lo + i0; L < hi; L += nx) reconstruct_block<DIM, P, FLUX, G, R0, R1, R2>(r, L, lds);
+            if (!grid_barrier(a, ++epoch)) return;
+            // k1 = u + h L(u); k2 = 3/4 u + 1/4 k1 + 1/4 h L(k1); u = 1/3 u + 2/3 k2 + 2/3 h L(k2)
+            UArgs up = a.up;
+            up.u0 = a.u;
+            up.prev = st == 0 ? a.u : a.k;
+            up.out = st == 2 ? a.u : a.k;
+            up.A = st == 0 ? 1.0 : (st == 1 ? 0.75 : 1.0 / 3.0);
+            up.B = st == 0 ? 0.0 : (st == 1 ? 0.25 : 2.0 / 3.0);
+            up.Cdt = st == 0 ? a.h : (st == 1 ? 0.25 * a.h : 2.0 / 3.0 * a.h);
+            up.mode = 1;
+            up.alpha_rd = a.alpha + par * nsl;
+            up.alpha_clr = a.alpha + (par ^ 1) * nsl;
+            xcd_range(a.nb_upd, x, lo, hi);
+            for (int L = lo + i0; L < hi; L += nx) update_block<DIM, Q, FLUX, 64>(up, L);
+            if (!grid_barrier(a, ++epoch)) return;
+            par ^= 1;
+        }
+    }
+}
+
 // ------------------------------------------------------------- helpers
+__global__ void k_clear_u32(unsigned *p, int n)
+{
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t < n) p[t] = 0u;
+}
+
 __global__ void k_permute(int64_t nc, int nvars, const int32_t *perm, const double *in, double *out,
                           int to_device)
 {
@@ -1921,6 +2046,17 @@ std::vector<int> stencil_capacities(int dim, int p)
     return {};
 }
 
+std::vector<int> lane_choices(const DevMesh &dm)
+{
+    if (dm.balance) return {dm.dim == 3 ? 8 : 2};
+    if (dm.dim == 2 && dm.flux == kFluxEuler && dm.characteristic) return {char_lanes(dm.p)};
+    if (dm.dim == 2 && dm.p == 3) return {2, 4, 8, 16};
+    if (dm.dim == 2 && dm.p == 4) return {4, 8, 16};
+    if (dm.dim == 2 && dm.p == 5) return {8, 16};
+    if (dm.dim == 3 && dm.p == 3) return {8, 16};
+    return {4};
+}
+
 bool reconstruct_supported(const DevMesh &dm)
 {
     const std::vector<int> v = stencil_capacities(dm.dim, dm.p);
@@ -1930,8 +2066,8 @@ bool reconstruct_supported(const DevMesh &dm)
     return dm.max_stencil <= v.back();
 }
 
-int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *coef_user, double *fv_user,
-                       int32_t *rank_user, void *stream)
+RArgs fill_rargs(const DevMesh &dm, const double *u, int parity, double *coef_user, double *fv_user,
+                 int32_t *rank_user)
 {
     RArgs a;
     a.nc = dm.nc;
@@ -1967,6 +2103,13 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
         a.spad_off[b] = dm.spad_off[b];
         if (b < kMaxBuckets) a.stride[b] = b < dm.nbuckets ? dm.bucket_cap[b] : 0;
     }
+    return a;
+}
+
+int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *coef_user, double *fv_user,
+                       int32_t *rank_user, void *stream)
+{
+    RArgs a = fill_rargs(dm, u, parity, coef_user, fv_user, rank_user);
     hipStream_t st = (hipStream_t)stream;
     // rows per lane = ceil(capacity / lanes).  Measured fastest: 2 lanes per
     // cell for 2-D p=3 (6 coefficients), 8 in 3-D (10 coefficients, stencils
@@ -2025,8 +2168,8 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     return (int)hipErrorInvalidValue;
 }
 
-int launch_update(const DevMesh &dm, const double *u0, const double *prev, double *out, double A, double B,
-                  double Cdt, int mode, int parity, void *stream)
+UArgs fill_uargs(const DevMesh &dm, const double *u0, const double *prev, double *out, double A, double B,
+                 double Cdt, int mode, int parity)
 {
     UArgs a;
     a.nc = dm.nc;
@@ -2055,6 +2198,13 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
     a.bc = dm.bc;
     for (int v = 0; v < 5; ++v) a.far[v] = dm.far[v];
     a.local_alpha = dm.lf_alpha;
+    return a;
+}
+
+int launch_update(const DevMesh &dm, const double *u0, const double *prev, double *out, double A, double B,
+                  double Cdt, int mode, int parity, void *stream)
+{
+    UArgs a = fill_uargs(dm, u0, prev, out, A, B, Cdt, mode, parity);
     hipStream_t st = (hipStream_t)stream;
     if (dm.dim == 1) return launch_k23<1, 1>(dm, a, st);
     if (dm.dim == 2) {
@@ -2064,6 +2214,69 @@ int launch_update(const DevMesh &dm, const double *u0, const double *prev, doubl
     }
     if (dm.dim == 3 && dm.nq == 3) return launch_k23<3, 3>(dm, a, st);
     return (int)hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------- persistent steps
+namespace {
+
+template <int DIM, int P, int FLUX, int G, int R0, int R1, int R2>
+int launch_steps_t(const DevMesh &dm, double *u, double *k, double h, int nsteps, unsigned *sync, hipStream_t st)
+{
+    SArgs a;
+    a.r = fill_rargs(dm, u, 0, nullptr, nullptr, nullptr);
+    constexpr int CPB = recon_block(DIM) / G;
+    int nb = 0;
+    for (int b = 0; b < kMaxBuckets; ++b) {
+        a.r.blk0[b] = nb;
+        nb += blocks_for(a.r.cell0[b + 1] - a.r.cell0[b], CPB);
+    }
+    a.r.blk0[kMaxBuckets] = nb;
+    a.up = fill_uargs(dm, u, u, k, 1.0, 0.0, h, 1, 0);
+    a.u = u;
+    a.k = k;
+    a.alpha = dm.alpha;
+    a.h = h;
+    a.nsteps = nsteps;
+    a.nb_rec = nb;
+    a.nb_upd = blocks_for(dm.nc, 64);
+    a.count = sync;
+    a.err = sync + 32;
+    // a legitimate wait lasts one phase (microseconds to milliseconds); ~2^22
+    // polls of ~64 cycles are a quarter of a second
+    a.max_polls = 1u << 22;
+    const void *fn = reinterpret_cast<const void *>(&k_steps<DIM, P, FLUX, G, R0, R1, R2>);
+    int per_cu = 0, dev = 0, ncu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, 0);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return (int)e;
+    const int resident = per_cu * ncu;
+    int grid = nb > a.nb_upd ? nb : a.nb_upd;
+    grid = grid < resident ? grid : resident;
+    grid &= ~7;   // whole XCD rounds
+    if (grid < 8) return (int)hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, sync, 64);
+    void *args[] = {&a};
+    e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(64), args, 0, st);
+    if (e != hipSuccess) return (int)e;
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+bool steps_supported(const DevMesh &dm)
+{
+    const int lanes = dm.lanes ? dm.lanes : 2;
+    return dm.dim == 2 && dm.p == 3 && lanes == 2 && !dm.balance && !dm.characteristic &&
+           (dm.flux == kFluxAdv || dm.flux == kFluxBurgers) && reconstruct_supported(dm);
+}
+
+int launch_steps(const DevMesh &dm, double *u, double *k, double h, int nsteps, unsigned *sync, void *stream)
+{
+    if (!steps_supported(dm)) return (int)hipErrorInvalidValue;
+    hipStream_t st = (hipStream_t)stream;
+    if (dm.flux == kFluxBurgers) return launch_steps_t<2, 3, kFluxBurgers, 2, 6, 8, 10>(dm, u, k, h, nsteps, sync, st);
+    return launch_steps_t<2, 3, kFluxAdv, 2, 6, 8, 10>(dm, u, k, h, nsteps, sync, st);
 }
 
 bool adjoint_supported(const DevMesh &dm)

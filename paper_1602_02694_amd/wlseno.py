@@ -181,6 +181,24 @@ class WLSENO:
         """Replay RK3 step pairs from a captured HIP graph (default) or launch directly."""
         self._check(self._lib.wlseno_set_graphs(self._h, 1 if enable else 0))
 
+    def autotune(self, u=None) -> dict:
+        """Time every compiled lane count of the reconstruction on this mesh
+        (on u, or a synthetic smooth state) and keep the fastest."""
+        t = N.Tune()
+        if u is not None:
+            u = self._field(u)
+        self._sync_stream()
+        self._check(self._lib.wlseno_autotune(self._h, _ptr(u) if u is not None else None, C.byref(t)))
+        return {"chosen": t.chosen, "cached": bool(t.cached),
+                "timings_us": {int(t.lanes[i]): float(t.us[i]) for i in range(t.n)}}
+
+    STEP_MODES = {"direct": 0, "graphs": 1, "persistent": 2}
+
+    def set_step_mode(self, mode):
+        """'direct', 'graphs' (default) or 'persistent' (one cooperative launch for all steps)."""
+        m = self.STEP_MODES[mode] if isinstance(mode, str) else int(mode)
+        self._check(self._lib.wlseno_set_step_mode(self._h, m))
+
     def batch_step(self, u, dts, n_steps):
         """Advance a batch in place by n_steps TVD RK3 steps, mesh k with dts[k]."""
         u = self._field(u)

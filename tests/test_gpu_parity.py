@@ -470,6 +470,78 @@ def test_balanced_refit_short_list():
     _compare_all(mesh, u0, 2, None, "balance-short-list", balance=True, **kw)
 
 
+@pytest.mark.parametrize("flux", ["burgers", "advection"])
+def test_persistent_steps_equal_stage_launches(flux):
+    """One cooperative launch for all steps (device-wide barriers between the
+    phases) gives the bits of graph replay and of direct launches, and the same
+    Lax-Friedrichs alpha; odd and even step counts."""
+    torch = _torch()
+    mesh = jittered_square(30, 0.3, 3131)
+    u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+    kw = dict(p=3, n_lo=12, n_hi=20, flux=flux, velocity=(1.0, 0.5, 0.0))
+    _say(f"[case] persistent steps {flux}: n_cell={mesh.n_cell}")
+    w = _gpu(mesh, **kw)
+    dt = 0.5 * w.info()["min_insphere"] / (np.sqrt(2.0) * np.max(np.abs(u0)))
+    for n in (1, 6, 7):
+        res = {}
+        for mode in ("direct", "graphs", "persistent"):
+            w.set_step_mode(mode)
+            u = torch.tensor(u0, device="cuda")
+            w.step(u, dt, n)
+            torch.cuda.synchronize()
+            res[mode] = (u.cpu().numpy(), w.last_alpha() if flux == "burgers" else 0.0)
+        for mode in ("direct", "graphs"):
+            assert np.array_equal(res["persistent"][0], res[mode][0]), (n, mode)
+            assert res["persistent"][1] == res[mode][1]
+
+
+def test_persistent_steps_unsupported():
+    from paper_1602_02694_amd import WLSENOError
+
+    torch = _torch()
+    mesh = jittered_square(12, 0.3, 3132)
+    w = _gpu(mesh, p=4, n_lo=20, n_hi=36, flux="burgers")
+    w.set_step_mode("persistent")
+    u = torch.ones(mesh.n_cell, dtype=torch.float64, device="cuda")
+    with pytest.raises(WLSENOError) as e:
+        w.step(u, 1e-3, 2)
+    assert e.value.status == 5
+    with pytest.raises(WLSENOError):
+        w.set_step_mode(3)
+
+
+@pytest.mark.parametrize("case", ["square-p3", "square-p4-euler", "cube-p3"])
+def test_autotune(case):
+    """The autotuner times every compiled lane count, keeps the fastest (a
+    second call on the same workload class comes from the cache), and the
+    tuned context still meets the oracle."""
+    from workloads import jittered_cube
+
+    torch = _torch()
+    if case == "square-p3":
+        mesh = jittered_square(40, 0.3, 3141)
+        u0 = fields.cell_averages(mesh, fields.gaussian_bump_with_step_2d)
+        kw, cand = dict(p=3, n_lo=12, n_hi=20, flux="burgers"), {2, 4, 8, 16}
+    elif case == "square-p4-euler":
+        mesh = jittered_square(20, 0.3, 3142)
+        u0 = fields.cell_averages(mesh, fields.euler_quadrants(3142))
+        kw, cand = dict(p=4, n_lo=20, n_hi=36, flux="euler"), {4, 8, 16}
+    else:
+        mesh = jittered_cube(8, 0.15, 3143)
+        u0 = fields.cell_averages(mesh, fields.sine_with_sphere_3d)
+        kw, cand = dict(p=3, n_lo=30, n_hi=50, flux="advection", velocity=(1.0, 0.5, 0.25)), {8, 16}
+    w = _gpu(mesh, **kw)
+    u = torch.tensor(np.asarray(u0).reshape(-1), device="cuda")
+    t = w.autotune(u)
+    _say(f"[case] autotune {case}: {t}")
+    assert set(t["timings_us"]) == cand and t["chosen"] in cand and not t["cached"]
+    assert t["timings_us"][t["chosen"]] == min(t["timings_us"].values())
+    w2 = _gpu(mesh, **kw)
+    t2 = w2.autotune()
+    assert t2["cached"] and t2["chosen"] == t["chosen"]
+    _compare_all(mesh, u0, 2, None, f"autotuned-{case}", lanes=t["chosen"], **kw)
+
+
 def test_torus_burgers():
     """Doubly periodic mesh: facet neighbours and stencils wrap around."""
     mesh = jittered_square_periodic(16, 0.3, 3121)
