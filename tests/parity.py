@@ -23,6 +23,9 @@ rel = 1e-12.  Measured on the 19,602-triangle Burgers workload, GPU and FP64
 oracle errors against the extended run stay below 3.2 kappa 2^-53.
 """
 
+import json
+import os
+
 import numpy as np
 
 REL = 1e-12
@@ -105,6 +108,27 @@ def cell_noise(o, x, floor=FLOOR, scale=None, cell_axes=None):
     return e
 
 
+def report(what, err, tol, rel=REL, err_plain=None):
+    """Print (and, with WLSENO_PARITY_LOG set, append as a JSON line to that
+    file) how the comparison passed: entries, largest error, how many entries
+    exceed the plain 1e-12 bar measured against their own magnitude but pass
+    through the flux scale S_i, how many pass only through the kappa/nu floor,
+    and the largest effective tolerance any entry needed."""
+    above = err > rel
+    rec = {"what": what, "entries": int(err.size), "max_err": float(err.max()) if err.size else 0.0,
+           "floor_only": int(np.sum(above & (err <= tol))),
+           "scale_only": int(np.sum((err_plain > rel) & ~above)) if err_plain is not None else 0,
+           "largest_tol_needed": float(np.max(tol[above])) if above.any() else rel}
+    print(f"[parity] {what}: {rec['entries']} entries, max err {rec['max_err']:.2e}; {rec['scale_only']} pass only "
+          f"through the flux scale, {rec['floor_only']} only through the kappa/nu floor (largest tolerance needed "
+          f"{rec['largest_tol_needed']:.2e})", flush=True)
+    path = os.environ.get("WLSENO_PARITY_LOG")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps(rec) + "\n")
+    return rec
+
+
 def assert_parity(g, o, what="", rel=REL, floor=FLOOR, scale=None, noise=None, tol_floor=None):
     g = np.asarray(g)
     o = np.asarray(o)
@@ -119,6 +143,7 @@ def assert_parity(g, o, what="", rel=REL, floor=FLOOR, scale=None, noise=None, t
     if tol_floor is not None:
         tol = np.maximum(tol, np.broadcast_to(np.asarray(tol_floor, dtype=np.float64), err.shape))
     worst = float(err.max())
+    report(what, err, tol, rel, rel_errors(g, o, floor) if scale is not None else None)
     bad = err > tol
     nbad = int(bad.sum())
     if nbad:
@@ -166,6 +191,7 @@ def assert_poly_parity(gcoef, ocoef, o, u, what="", rel=REL, floor=FLOOR, xcoef=
         tol = np.maximum(tol, np.broadcast_to(np.asarray(tol_floor, dtype=np.float64), err.shape))
     if xcoef is not None:
         tol = np.maximum(tol, K_FLOOR * poly_dev(ocoef, xcoef, o, u, floor))
+    report(what, err, tol, rel)
     bad = err > tol
     if bad.any():
         idx = np.unravel_index(int(np.argmax(err - tol)), err.shape)
