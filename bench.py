@@ -252,7 +252,7 @@ def run_batch(args, torch, WLSENO):
                           "batch_speedup": el_loop / elapsed, "bitwise_equal_to_batch": same},
         "roofline": {"bound": "alu", "kernel": "k_reconstruct", "achieved": achieved,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic_record("k_reconstruct", wkey), "avg_launch_us": k1 * 1e3,
+                     "traffic": traffic_record(f"k_reconstruct/{tune['chosen']}", wkey), "avg_launch_us": k1 * 1e3,
                      "flops_per_launch": flops},
         "roofline_update": {"bound": "hbm", "kernel": "k_update", "achieved": ach_u, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": ach_u / HBM_PEAK_GBS,
@@ -408,7 +408,7 @@ def run_square_large(torch, WLSENO, steps=20):
                                      "peak_GBs": HBM_PEAK_GBS, "frac": alg / HBM_PEAK_GBS},
            "k_reconstruct": {"avg_launch_us": k1 * 1e3, "achieved_TFLOPs": flops / (k1 * 1e-3) / 1e12,
                              "frac_fp64_peak": flops / (k1 * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
-                             "traffic": traffic_record("k_reconstruct", "square-large")},
+                             "traffic": traffic_record(f"k_reconstruct/{tune['chosen']}", "square-large")},
            "k_update": {"avg_launch_us": k2 * 1e3, "algorithmic_bytes": ub,
                         "achieved_GBs": ub / (k2 * 1e-3) / 1e9, "frac_hbm_peak": ub / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                         "traffic": traffic_record("k_update", "square-large")},
@@ -604,6 +604,8 @@ def main():
                     help="random directions of the adjoint's finite-difference check")
     ap.add_argument("--repeats", type=int, default=5,
                     help="further timed runs of the same K steps (median, min, max reported)")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="lanes per cell of the reconstruction (0: autotune); profiling runs pin it")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 2 M-triangle companion record of the default workload")
     args = ap.parse_args()
@@ -628,7 +630,7 @@ def main():
     t1 = time.time()
     w.mesh_upload(dim, mesh.verts, mesh.cells)
     w.stencil_build(p=cfg["p"], n_lo=cfg["n_lo"], n_hi=cfg["n_hi"], flux=cfg["flux"], velocity=cfg["velocity"],
-                    balance=args.balance)
+                    balance=args.balance, lanes=args.lanes)
     info = w.info()
     rp, _ = w.stencil()
     nsz = np.diff(rp)
@@ -640,9 +642,12 @@ def main():
         speed = float(np.linalg.norm(cfg["velocity"][:dim]))
     dt = 0.5 * info["min_insphere"] / speed
     u_init = torch.tensor(u0, device="cuda")
-    tune = w.autotune(u_init)
-    log(f"[bench] autotuned reconstruction: {tune['chosen']} lanes per cell "
-        f"({', '.join(f'{k}: {v:.2f} us' for k, v in tune['timings_us'].items())})")
+    if args.lanes:
+        tune = {"chosen": args.lanes, "cached": False, "timings_us": {}, "pinned": True}
+    else:
+        tune = w.autotune(u_init)
+        log(f"[bench] autotuned reconstruction: {tune['chosen']} lanes per cell "
+            f"({', '.join(f'{k}: {v:.2f} us' for k, v in tune['timings_us'].items())})")
 
     # warm-up
     u = u_init.clone()
@@ -691,7 +696,7 @@ def main():
     log(f"[bench] k_reconstruct avg {k1_avg * 1e3:.2f} us ({k1_n} launches), "
         f"k_update avg {k2_avg * 1e3:.2f} us ({k2_n} launches); {flops / nc:.0f} flop/cell")
     tkey = args.workload + ("-balance" if args.balance else "")
-    traffic = traffic_record("k_reconstruct", tkey)
+    traffic = traffic_record(f"k_reconstruct/{tune['chosen']}", tkey)
     roofline = {
         "bound": "alu",
         "kernel": "k_reconstruct",

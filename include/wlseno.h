@@ -250,18 +250,39 @@ wlseno_status wlseno_set_graphs(wlseno_t ctx, int enable);
  * mode.  wlseno_set_graphs(ctx, e) is wlseno_set_step_mode(ctx, e ? 1 : 0). */
 wlseno_status wlseno_set_step_mode(wlseno_t ctx, int mode);
 
-/* Batches of independent meshes (several meshes stepped by one set of
- * launches).  Each call appends one mesh (host arrays, copied; no flags) and
- * returns its index in *mesh_id (nullable).  The meshes must share dim.  The
+/* Batches of independent meshes (many meshes stepped by one set of launches
+ * per stage).  Each call appends one mesh (host arrays, copied; no flags) and
+ * returns its index in *mesh_id (nullable); adding costs time in proportion
+ * to the mesh alone (the batch is assembled by the next stencil build).  The
  * batch replaces any mesh given by wlseno_mesh_upload, and wlseno_mesh_upload
  * replaces the batch.  After wlseno_stencil_build every call works on the
- * concatenation: cells of mesh 0 first, then mesh 1, ...; fields are
- * double[n_vars][sum of n_cell].  Stencils never cross meshes (they share no
- * vertex); each mesh uses its own eps h^2 and its own Lax-Friedrichs alpha
- * (Burgers, Euler).  Sizes: the total must fit 32-bit cell indices, as for a
- * single mesh.  EINVAL for a bad mesh or a dim that differs from the first. */
+ * concatenation in add order: cells of mesh 0 first, then mesh 1, ...; fields
+ * are double[n_vars][sum of n_cell].  Stencils never cross meshes (they share
+ * no vertex); each mesh uses its own eps h^2 and its own Lax-Friedrichs alpha
+ * (Burgers, Euler).
+ *
+ * Meshes of different dims may share a batch: the meshes of each dim form a
+ * group with its own stencils, order p and compiled kernels (parameters per
+ * dim from wlseno_batch_params), and every stage runs the groups' kernels
+ * concurrently on streams forked from the context's (joined back into it
+ * before the call's work ends).  All groups need the same n_vars; the caller's
+ * arrays stay in add order.  Such a batch supports stencil build, get_info
+ * (per-dim sizes m, faces and points are 0 there; dim is 0), get_stencil,
+ * rhs, rhs_noalloc, step, batch_step, last_alpha, batch_last_alpha,
+ * set_graphs, set_step_mode and autotune (each group tuned; out describes the
+ * first); reconstruct and time_kernel give EUNSUPPORTED, as do the adjoint
+ * calls for any batch.
+ *
+ * Sizes: the total must fit 32-bit cell indices, as for a single mesh.  EINVAL
+ * for a bad mesh. */
 wlseno_status wlseno_batch_add_mesh(wlseno_t ctx, int dim, int64_t n_vert, const double *xyz, int64_t n_cell,
                                     const int32_t *cells, int32_t *mesh_id);
+
+/* Parameters for the batch's meshes of one dim (1, 2 or 3): the next
+ * wlseno_stencil_build uses *params for them instead of its own argument (for
+ * instance p and the stencil sizes n_lo, n_hi differ between 2-D and 3-D
+ * meshes).  params = NULL drops the setting.  EINVAL for another dim. */
+wlseno_status wlseno_batch_params(wlseno_t ctx, int dim, const wlseno_params *params);
 
 /* n_steps TVD RK3 steps of the whole batch in place, mesh k with time step
  * dt_per_mesh[k] (host array of n_mesh finite doubles).  wlseno_step on a
@@ -334,6 +355,8 @@ typedef struct {
  * per cell compiled for this build (2-D p = 3: 2, 4, 8, 16; p = 4: 4, 8, 16;
  * p = 5 and 3-D p = 3: 8, 16; otherwise one) on this mesh, back-to-back launches
  * between HIP events (~20 ms each), and keeps the fastest for this context
+ * (the automatic choice of wlseno_params.lanes = 0 unless another is faster
+ * by 2% or more)
  * (captured step graphs are dropped and recaptured).  Fewer lanes per cell
  * hold more stencil rows per lane (more registers, fewer resident waves);
  * more lanes add exchanges per column.  The choice is cached in the process

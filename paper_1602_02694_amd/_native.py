@@ -20,7 +20,7 @@ EXPORTS = [
     "wlseno_reconstruct", "wlseno_rhs", "wlseno_step", "wlseno_last_alpha", "wlseno_time_kernel",
     "wlseno_batch_add_mesh", "wlseno_batch_step", "wlseno_batch_last_alpha", "wlseno_set_graphs",
     "wlseno_rhs_vjp", "wlseno_step_adjoint", "wlseno_step_record", "wlseno_step_adjoint_recorded",
-    "wlseno_rhs_noalloc", "wlseno_set_step_mode", "wlseno_autotune",
+    "wlseno_rhs_noalloc", "wlseno_set_step_mode", "wlseno_autotune", "wlseno_batch_params",
 ]
 
 
@@ -92,6 +92,7 @@ def load():
     lib.wlseno_set_graphs.argtypes = [vp, C.c_int]
     lib.wlseno_set_step_mode.argtypes = [vp, C.c_int]
     lib.wlseno_autotune.argtypes = [vp, vp, C.POINTER(Tune)]
+    lib.wlseno_batch_params.argtypes = [vp, C.c_int, C.POINTER(Params)]
     lib.wlseno_rhs_vjp.argtypes = [vp, vp, vp, vp]
     lib.wlseno_step_adjoint.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, vp, vp]
     lib.wlseno_step_record.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int]

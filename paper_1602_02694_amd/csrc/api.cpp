@@ -39,6 +39,22 @@ struct wlseno_ctx {
     std::vector<int32_t> batch_cells;
     std::vector<double> batch_h;   // each mesh's mean edge length
     bool batch_pending = false;    // meshes added since the union was last set up
+    // parameters given per dim for batches (wlseno_batch_params), index dim
+    bool has_dim_prm[4] = {false, false, false, false};
+    wlseno_params dim_prm[4];
+    // a batch whose meshes have several dims: one group per dim (in order of
+    // first appearance), each an internal single-dim batch context whose
+    // permutation maps its device cells straight to the caller's cells
+    struct Group {
+        int dim = 0;
+        wlseno_ctx *c = nullptr;
+        std::vector<int32_t> meshes;   // batch mesh ids of the group, ascending
+        hipStream_t st = nullptr;      // the group's stream (forked from ours)
+        hipEvent_t done = nullptr;
+    };
+    std::vector<Group> groups;         // empty unless the batch has several dims
+    std::vector<int32_t> mesh_group;   // group of each batch mesh
+    hipEvent_t fork = nullptr;
     std::vector<double> dt_host;   // per-mesh time steps last sent to the device
     // RK3 steps replayed from captured HIP graphs of kGraphSteps[g] steps (an
     // even number: stage parities 0,1,0,1,... start and end alike), captured
@@ -313,6 +329,118 @@ double time_launches(wlseno_ctx *ctx, int kernel, int launches);
     }                                                                    \
     return WLSENO_OK;
 
+namespace {
+
+// ---------------------------------------------------------- batch groups
+
+bool mixed(const wlseno_ctx *c) { return !c->groups.empty(); }
+
+void check_child(wlseno_ctx *g, wlseno_status st, int dim)
+{
+    if (st != WLSENO_OK) throw Error{st, std::to_string(dim) + "-D meshes of the batch: " + g->err};
+}
+
+void drop_groups(wlseno_ctx *c)
+{
+    for (auto &g : c->groups) {
+        if (g.c) (void)wlseno_destroy(g.c);
+        if (g.st) (void)hipStreamDestroy(g.st);
+        if (g.done) (void)hipEventDestroy(g.done);
+    }
+    c->groups.clear();
+    c->mesh_group.clear();
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    c->fork = nullptr;
+}
+
+// Append batch mesh `id` (host arrays) to the group of its dim, opening the
+// group (an internal context on our device, with a stream of its own) if new.
+void group_add(wlseno_ctx *c, int dim, int64_t nv, const double *xyz, int64_t nc, const int32_t *cells, int32_t id)
+{
+    size_t gi = 0;
+    while (gi < c->groups.size() && c->groups[gi].dim != dim) ++gi;
+    if (gi == c->groups.size()) {
+        wlseno_ctx::Group g;
+        g.dim = dim;
+        if (wlseno_create(c->device, &g.c) != WLSENO_OK) throw Error{WLSENO_EDEVICE, wlseno_last_error(nullptr)};
+        c->groups.push_back(g);
+        wlseno_ctx::Group &gr = c->groups.back();
+        gr.c->step_mode = c->step_mode;
+        gr.c->use_graphs = c->use_graphs;
+        if (c->device >= 0) {
+            check_hip(hipSetDevice(c->device), "hipSetDevice");
+            check_hip(hipStreamCreateWithFlags(&gr.st, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+            check_hip(hipEventCreateWithFlags(&gr.done, hipEventDisableTiming), "hipEventCreateWithFlags");
+            check_child(gr.c, wlseno_set_stream(gr.c, gr.st), dim);
+        }
+    }
+    wlseno_ctx::Group &g = c->groups[gi];
+    check_child(g.c, wlseno_batch_add_mesh(g.c, dim, nv, xyz, nc, cells, nullptr), dim);
+    g.meshes.push_back(id);
+    c->mesh_group.push_back((int32_t)gi);
+}
+
+// The meshes added so far (one dim) become the first group.
+void enter_mixed(wlseno_ctx *c)
+{
+    const int d = c->batch_dim;
+    int64_t nv0 = 0, nc0 = 0;
+    for (size_t k = 0; k < c->parts.size(); ++k) {
+        const auto &pt = c->parts[k];
+        std::vector<int32_t> cl((size_t)pt.nc * (d + 1));
+        for (size_t t = 0; t < cl.size(); ++t) cl[t] = c->batch_cells[(size_t)nc0 * (d + 1) + t] - (int32_t)nv0;
+        group_add(c, d, pt.nv, c->batch_xyz.data() + (size_t)nv0 * d, pt.nc, cl.data(), (int32_t)k);
+        nv0 += pt.nv;
+        nc0 += pt.nc;
+    }
+    c->batch_xyz.clear();
+    c->batch_cells.clear();
+    c->batch_h.clear();
+}
+
+// First cell of each batch mesh in the caller's arrays (add order), and the total.
+std::vector<int64_t> mesh_cell0(const wlseno_ctx *c)
+{
+    std::vector<int64_t> c0(c->parts.size() + 1, 0);
+    for (size_t k = 0; k < c->parts.size(); ++k) c0[k + 1] = c0[k] + c->parts[k].nc;
+    return c0;
+}
+
+// For group g: the caller's cell index of each of its user cells (its meshes
+// concatenated in add order).
+std::vector<int64_t> group_to_caller(const wlseno_ctx *c, const wlseno_ctx::Group &g)
+{
+    const std::vector<int64_t> c0 = mesh_cell0(c);
+    std::vector<int64_t> out;
+    for (int32_t k : g.meshes)
+        for (int64_t i = c0[k]; i < c0[k + 1]; ++i) out.push_back(i);
+    return out;
+}
+
+// Work of every group on its own stream, ordered after the caller's stream
+// and joined back into it.
+void fork_groups(wlseno_ctx *c)
+{
+    if (!c->fork) check_hip(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming), "hipEventCreateWithFlags");
+    check_hip(hipEventRecord(c->fork, c->stream), "hipEventRecord");
+    for (auto &g : c->groups) check_hip(hipStreamWaitEvent(g.st, c->fork, 0), "hipStreamWaitEvent");
+}
+
+void join_groups(wlseno_ctx *c)
+{
+    for (auto &g : c->groups) {
+        check_hip(hipEventRecord(g.done, g.st), "hipEventRecord");
+        check_hip(hipStreamWaitEvent(c->stream, g.done, 0), "hipStreamWaitEvent");
+    }
+}
+
+void need_single_dim(const wlseno_ctx *c, const char *what)
+{
+    if (mixed(c)) throw Error{WLSENO_EUNSUPPORTED, std::string(what) + " works on batches of one dim only"};
+}
+
+}  // namespace
+
 extern "C" {
 
 void wlseno_params_default(wlseno_params *out)
@@ -377,6 +505,7 @@ wlseno_status wlseno_create(int device, wlseno_t *out)
 wlseno_status wlseno_destroy(wlseno_t ctx)
 {
     if (!ctx) return WLSENO_OK;
+    drop_groups(ctx);
     free_device(ctx);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
@@ -389,6 +518,7 @@ wlseno_status wlseno_set_graphs(wlseno_t ctx, int enable)
     ctx->use_graphs = enable != 0;
     ctx->step_mode = enable ? 1 : 0;
     if (!ctx->use_graphs) drop_graph(ctx);
+    for (auto &g : ctx->groups) check_child(g.c, wlseno_set_graphs(g.c, enable), g.dim);
     API_END(ctx)
 }
 
@@ -399,6 +529,7 @@ wlseno_status wlseno_set_step_mode(wlseno_t ctx, int mode)
     ctx->step_mode = mode;
     ctx->use_graphs = mode == 1;
     if (!ctx->use_graphs) drop_graph(ctx);
+    for (auto &g : ctx->groups) check_child(g.c, wlseno_set_step_mode(g.c, mode), g.dim);
     API_END(ctx)
 }
 
@@ -422,6 +553,7 @@ wlseno_status wlseno_mesh_upload(wlseno_t ctx, int dim, int64_t n_vert, const do
     API_BEGIN(ctx)
     HostMesh m;
     mesh_setup(m, dim, n_vert, xyz, n_cell, cells, flags);
+    drop_groups(ctx);
     free_device(ctx);
     ctx->mesh = std::move(m);
     ctx->have_mesh = true;
@@ -442,7 +574,6 @@ wlseno_status wlseno_batch_add_mesh(wlseno_t ctx, int dim, int64_t n_vert, const
     // validates the mesh on its own and gives its mean edge length
     HostMesh one;
     mesh_setup(one, dim, n_vert, xyz, n_cell, cells, 0);
-    if (!ctx->parts.empty() && dim != ctx->batch_dim) throw Error{WLSENO_EINVAL, "all meshes of a batch share dim"};
     int64_t nv0 = 0, nc0 = 0;
     for (const auto &pt : ctx->parts) {
         nv0 += pt.nv;
@@ -450,6 +581,19 @@ wlseno_status wlseno_batch_add_mesh(wlseno_t ctx, int dim, int64_t n_vert, const
     }
     if (nc0 + n_cell > (int64_t)(INT32_MAX / 8) || nv0 + n_vert > (int64_t)INT32_MAX)
         throw Error{WLSENO_EINVAL, "batch too large for 32-bit indices"};
+    if (!ctx->parts.empty() && dim != ctx->batch_dim && !mixed(ctx)) enter_mixed(ctx);
+    if (mixed(ctx)) {
+        group_add(ctx, dim, n_vert, xyz, n_cell, cells, (int32_t)ctx->parts.size());
+        ctx->parts.push_back({n_vert, n_cell});
+        free_device(ctx);
+        ctx->mesh = HostMesh{};
+        ctx->have_mesh = true;
+        ctx->have_build = false;
+        ctx->build = Build{};
+        ctx->batch_pending = false;
+        if (mesh_id) *mesh_id = (int32_t)ctx->parts.size() - 1;
+        return WLSENO_OK;
+    }
     ctx->batch_dim = dim;
     ctx->batch_xyz.insert(ctx->batch_xyz.end(), xyz, xyz + n_vert * dim);
     for (int64_t t = 0; t < n_cell * (dim + 1); ++t) ctx->batch_cells.push_back((int32_t)(cells[t] + nv0));
@@ -467,11 +611,50 @@ wlseno_status wlseno_batch_add_mesh(wlseno_t ctx, int dim, int64_t n_vert, const
     API_END(ctx)
 }
 
+wlseno_status wlseno_batch_params(wlseno_t ctx, int dim, const wlseno_params *params)
+{
+    API_BEGIN(ctx)
+    if (dim < 1 || dim > 3) throw Error{WLSENO_EINVAL, "dim must be 1, 2 or 3"};
+    ctx->has_dim_prm[dim] = params != nullptr;
+    if (params) ctx->dim_prm[dim] = *params;
+    ctx->have_build = false;
+    API_END(ctx)
+}
+
 wlseno_status wlseno_stencil_build(wlseno_t ctx, const wlseno_params *params)
 {
     API_BEGIN(ctx)
     if (!params) throw Error{WLSENO_EINVAL, "params is NULL"};
     if (!ctx->have_mesh) throw Error{WLSENO_ESTATE, "call wlseno_mesh_upload first"};
+    if (mixed(ctx)) {
+        ctx->have_build = false;
+        int nvars = -1;
+        for (auto &g : ctx->groups) {
+            const wlseno_params &prm = ctx->has_dim_prm[g.dim] ? ctx->dim_prm[g.dim] : *params;
+            check_child(g.c, wlseno_stencil_build(g.c, &prm), g.dim);
+            if (nvars >= 0 && g.c->build.nvars != nvars)
+                throw Error{WLSENO_EINVAL, "the meshes of a batch need the same number of field components"};
+            nvars = g.c->build.nvars;
+        }
+        if (ctx->device >= 0) {
+            // each group's device cells map straight to the caller's cells
+            const int64_t total = mesh_cell0(ctx).back();
+            for (auto &g : ctx->groups) {
+                const std::vector<int64_t> to = group_to_caller(ctx, g);
+                std::vector<int32_t> gp(g.c->build.perm.size());
+                for (size_t d = 0; d < gp.size(); ++d) gp[d] = (int32_t)to[g.c->build.perm[d]];
+                g.c->dm.perm = upload(g.c, gp);
+                g.c->dm.user_stride = total;
+            }
+        }
+        ctx->build = Build{};
+        ctx->build.prm = *params;
+        ctx->build.nvars = nvars;
+        ctx->have_build = true;
+        return WLSENO_OK;
+    }
+    const bool per_dim = !ctx->parts.empty() && ctx->has_dim_prm[ctx->batch_dim];
+    if (per_dim) params = &ctx->dim_prm[ctx->batch_dim];
     if (ctx->batch_pending) {
         int64_t nv = 0, nc = 0;
         for (const auto &pt : ctx->parts) {
@@ -506,6 +689,22 @@ wlseno_status wlseno_get_info(wlseno_t ctx, wlseno_info *out)
     if (!out) throw Error{WLSENO_EINVAL, "out is NULL"};
     if (!ctx->have_build) throw Error{WLSENO_ESTATE, "call wlseno_stencil_build first"};
     std::memset(out, 0, sizeof(*out));
+    if (mixed(ctx)) {
+        // several dims: totals and extremes over the groups; per-dim sizes are 0
+        out->min_stencil = INT32_MAX;
+        out->min_insphere = INFINITY;
+        for (auto &g : ctx->groups) {
+            const Build &gb = g.c->build;
+            out->n_vars = gb.nvars;
+            out->min_stencil = std::min(out->min_stencil, gb.min_stencil);
+            out->max_stencil = std::max(out->max_stencil, gb.max_stencil);
+            out->n_cell += g.c->mesh.nc;
+            out->nnz += (int64_t)gb.col.size();
+            out->min_insphere = std::min(out->min_insphere, gb.min_insphere);
+        }
+        out->n_mesh = (int32_t)ctx->parts.size();
+        return WLSENO_OK;
+    }
     const Build &b = ctx->build;
     out->dim = ctx->mesh.dim;
     out->m = b.m;
@@ -527,6 +726,35 @@ wlseno_status wlseno_get_stencil(wlseno_t ctx, int32_t *row_ptr, int32_t *col)
     API_BEGIN(ctx)
     if (!row_ptr || !col) throw Error{WLSENO_EINVAL, "null output array"};
     if (!ctx->have_build) throw Error{WLSENO_ESTATE, "call wlseno_stencil_build first"};
+    if (mixed(ctx)) {
+        // the caller's cell order and ids: each mesh's rows from its group
+        const std::vector<int64_t> c0 = mesh_cell0(ctx);
+        std::vector<std::vector<int64_t>> to(ctx->groups.size());
+        std::vector<std::vector<int64_t>> first(ctx->groups.size());   // group user index of each mesh's first cell
+        for (size_t gi = 0; gi < ctx->groups.size(); ++gi) {
+            to[gi] = group_to_caller(ctx, ctx->groups[gi]);
+            int64_t at = 0;
+            for (int32_t k : ctx->groups[gi].meshes) {
+                first[gi].push_back(at);
+                at += c0[k + 1] - c0[k];
+            }
+        }
+        std::vector<int32_t> pos(ctx->parts.size());   // position of each mesh within its group
+        for (size_t gi = 0; gi < ctx->groups.size(); ++gi)
+            for (size_t t = 0; t < ctx->groups[gi].meshes.size(); ++t) pos[ctx->groups[gi].meshes[t]] = (int32_t)t;
+        int64_t w = 0;
+        row_ptr[0] = 0;
+        for (size_t k = 0; k < ctx->parts.size(); ++k) {
+            const int gi = ctx->mesh_group[k];
+            const Build &gb = ctx->groups[gi].c->build;
+            for (int64_t i = c0[k]; i < c0[k + 1]; ++i) {
+                const int64_t ui = first[gi][pos[k]] + (i - c0[k]);
+                for (int32_t t = gb.row_ptr[ui]; t < gb.row_ptr[ui + 1]; ++t) col[w++] = (int32_t)to[gi][gb.col[t]];
+                row_ptr[i + 1] = (int32_t)w;
+            }
+        }
+        return WLSENO_OK;
+    }
     std::memcpy(row_ptr, ctx->build.row_ptr.data(), ctx->build.row_ptr.size() * sizeof(int32_t));
     std::memcpy(col, ctx->build.col.data(), ctx->build.col.size() * sizeof(int32_t));
     API_END(ctx)
@@ -537,6 +765,7 @@ wlseno_status wlseno_reconstruct(wlseno_t ctx, const double *u_dev, double *coef
 {
     API_BEGIN(ctx)
     if (!u_dev) throw Error{WLSENO_EINVAL, "u_dev is NULL"};
+    need_single_dim(ctx, "wlseno_reconstruct (per-dim coefficient and facet layouts)");
     if (coef_dev && ctx->have_build && ctx->build.prm.characteristic)
         throw Error{WLSENO_EINVAL, "no coefficient output with characteristic fields (one fit per facet)"};
     need_device(ctx);
@@ -554,6 +783,12 @@ wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev)
     if (!u_dev || !dudt_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
     if (u_dev == dudt_dev) throw Error{WLSENO_EINVAL, "dudt_dev must not alias u_dev"};
     need_device(ctx);
+    if (mixed(ctx)) {
+        fork_groups(ctx);
+        for (auto &g : ctx->groups) check_child(g.c, wlseno_rhs(g.c, u_dev, dudt_dev), g.dim);
+        join_groups(ctx);
+        return WLSENO_OK;
+    }
     check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
     check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
     stage(ctx, ctx->ubuf, nullptr, nullptr, ctx->tbuf, 0.0, 0.0, 1.0, 0, 0, ctx->stream);
@@ -567,6 +802,16 @@ wlseno_status wlseno_rhs_noalloc(wlseno_t ctx, const double *u_dev, double *dudt
     if (!u_dev || !dudt_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
     if (u_dev == dudt_dev) throw Error{WLSENO_EINVAL, "dudt_dev must not alias u_dev"};
     need_device(ctx);
+    if (mixed(ctx)) {
+        // the groups share this device's array: one after another, on our stream
+        for (auto &g : ctx->groups) {
+            check_child(g.c, wlseno_set_stream(g.c, ctx->stream), g.dim);
+            const wlseno_status st = wlseno_rhs_noalloc(g.c, u_dev, dudt_dev);
+            (void)wlseno_set_stream(g.c, g.st);
+            check_child(g.c, st, g.dim);
+        }
+        return WLSENO_OK;
+    }
     if (ctx->dm.balance) throw Error{WLSENO_EUNSUPPORTED, "the balanced refit keeps buffers of its own"};
     if (!ctx->scratch) throw Error{WLSENO_ESTATE, "no scratch address on this device"};
     // scratch layout: alpha slots (two parities), state and result in device
@@ -806,6 +1051,12 @@ wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps)
     if (!std::isfinite(dt) || n_steps < 0) throw Error{WLSENO_EINVAL, "dt must be finite and n_steps >= 0"};
     need_device(ctx);
     if (n_steps == 0) return WLSENO_OK;
+    if (mixed(ctx)) {
+        fork_groups(ctx);
+        for (auto &g : ctx->groups) check_child(g.c, wlseno_step(g.c, u_dev, dt, n_steps), g.dim);
+        join_groups(ctx);
+        return WLSENO_OK;
+    }
     run_steps(ctx, u_dev, dt, nullptr, n_steps);
     API_END(ctx)
 }
@@ -816,6 +1067,19 @@ wlseno_status wlseno_batch_step(wlseno_t ctx, double *u_dev, const double *dt_pe
     if (!u_dev || !dt_per_mesh) throw Error{WLSENO_EINVAL, "null pointer"};
     if (n_steps < 0) throw Error{WLSENO_EINVAL, "n_steps >= 0 required"};
     need_device(ctx);
+    if (mixed(ctx)) {
+        for (size_t k = 0; k < ctx->parts.size(); ++k)
+            if (!std::isfinite(dt_per_mesh[k])) throw Error{WLSENO_EINVAL, "time steps must be finite"};
+        if (n_steps == 0) return WLSENO_OK;
+        fork_groups(ctx);
+        for (auto &g : ctx->groups) {
+            std::vector<double> dts;
+            for (int32_t k : g.meshes) dts.push_back(dt_per_mesh[k]);
+            check_child(g.c, wlseno_batch_step(g.c, u_dev, dts.data(), n_steps), g.dim);
+        }
+        join_groups(ctx);
+        return WLSENO_OK;
+    }
     for (int k = 0; k < ctx->mesh.nmesh; ++k)
         if (!std::isfinite(dt_per_mesh[k])) throw Error{WLSENO_EINVAL, "time steps must be finite"};
     if (n_steps == 0) return WLSENO_OK;
@@ -855,6 +1119,16 @@ wlseno_status wlseno_last_alpha(wlseno_t ctx, double *alpha)
     API_BEGIN(ctx)
     if (!alpha) throw Error{WLSENO_EINVAL, "alpha is NULL"};
     need_device(ctx);
+    if (mixed(ctx)) {
+        double a = 0.0;
+        for (auto &g : ctx->groups) {
+            double ag = 0.0;
+            check_child(g.c, wlseno_last_alpha(g.c, &ag), g.dim);
+            a = ag > a ? ag : a;
+        }
+        *alpha = a;
+        return WLSENO_OK;
+    }
     double a = 0.0;
     for (double v : read_alpha(ctx)) a = v > a ? v : a;
     *alpha = a;
@@ -866,6 +1140,14 @@ wlseno_status wlseno_batch_last_alpha(wlseno_t ctx, double *alpha_per_mesh)
     API_BEGIN(ctx)
     if (!alpha_per_mesh) throw Error{WLSENO_EINVAL, "alpha_per_mesh is NULL"};
     need_device(ctx);
+    if (mixed(ctx)) {
+        for (auto &g : ctx->groups) {
+            std::vector<double> ag(g.meshes.size());
+            check_child(g.c, wlseno_batch_last_alpha(g.c, ag.data()), g.dim);
+            for (size_t t = 0; t < ag.size(); ++t) alpha_per_mesh[g.meshes[t]] = ag[t];
+        }
+        return WLSENO_OK;
+    }
     const std::vector<double> a = read_alpha(ctx);
     for (size_t k = 0; k < a.size(); ++k) alpha_per_mesh[k] = a[k];
     API_END(ctx)
@@ -878,6 +1160,7 @@ wlseno_status wlseno_time_kernel(wlseno_t ctx, int kernel, const double *u_dev, 
     if (kernel != 0 && kernel != 1) throw Error{WLSENO_EINVAL, "kernel must be 0 or 1"};
     if (launches < 1) throw Error{WLSENO_EINVAL, "launches must be >= 1"};
     need_device(ctx);
+    need_single_dim(ctx, "wlseno_time_kernel");
     // state in device order, facet values and alpha of one reconstruction
     check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
     *avg_ms = time_launches(ctx, kernel, launches);
@@ -991,6 +1274,16 @@ wlseno_status wlseno_autotune(wlseno_t ctx, const double *u_dev, wlseno_tune *ou
     if (!out) throw Error{WLSENO_EINVAL, "out is NULL"};
     need_device(ctx);
     std::memset(out, 0, sizeof(*out));
+    if (mixed(ctx)) {
+        // every group on its own; out describes the first
+        for (size_t gi = 0; gi < ctx->groups.size(); ++gi) {
+            wlseno_tune t;
+            auto &g = ctx->groups[gi];
+            check_child(g.c, wlseno_autotune(g.c, u_dev, &t), g.dim);
+            if (gi == 0) *out = t;
+        }
+        return WLSENO_OK;
+    }
     const std::string key = tune_key(ctx);
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -1033,6 +1326,11 @@ wlseno_status wlseno_autotune(wlseno_t ctx, const double *u_dev, wlseno_tune *ou
         ctx->dm.lanes = keep;
         throw;
     }
+    // the automatic choice stays unless another is faster by 2% or more:
+    // differences below that are run-to-run noise
+    const int dflt = default_lanes(ctx->dm);
+    for (int t = 0; t < out->n; ++t)
+        if (out->lanes[t] == dflt && !(best_us < 0.98 * out->us[t])) best = dflt;
     out->chosen = best;
     out->cached = 0;
     if (keep != best) drop_graph(ctx);

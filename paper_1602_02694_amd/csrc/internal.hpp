@@ -114,6 +114,7 @@ struct DevMesh {
     unsigned long long *bal_alpha = nullptr;   // scratch alpha slots of the discarded first fits
     int lanes = 0;   // lanes per cell in the reconstruction: 0 = automatic, 4 or 8
     int64_t nc = 0;
+    int64_t user_stride = 0;   // component stride of user-order arrays (0: nc)
     int nbuckets = 0;
     int bucket_cap[kMaxBuckets] = {0, 0, 0};
     int64_t bucket_cell0[kMaxBuckets + 1] = {0, 0, 0, 0};
@@ -144,6 +145,8 @@ bool reconstruct_supported(const DevMesh &dm);
 // Lane counts per cell compiled for the reconstruction of this build (the
 // automatic choice first is not implied; the autotuner times them all).
 std::vector<int> lane_choices(const DevMesh &dm);
+// The automatic lane count (wlseno_params.lanes = 0).
+int default_lanes(const DevMesh &dm);
 int launch_permute(const DevMesh &dm, const double *in, double *out, bool to_device_order, void *stream);
 // Transposed Jacobian of the advection right-hand side: per-cell
 // contributions written into each receiving cell's segment of contrib

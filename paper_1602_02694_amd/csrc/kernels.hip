@@ -1890,17 +1890,19 @@ __global__ void k_clear_u32(unsigned *p, int n)
     if (t < n) p[t] = 0u;
 }
 
+// Device order d <-> user index perm[d]; user arrays have component stride
+// ustride (the user's cell count: all cells of a batch with several dims).
 __global__ void k_permute(int64_t nc, int nvars, const int32_t *perm, const double *in, double *out,
-                          int to_device)
+                          int to_device, int64_t ustride)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nc * nvars) return;
     const int64_t v = t / nc, d = t - v * nc;
     const int64_t u = perm[d];
     if (to_device)
-        out[v * nc + d] = in[v * nc + u];
+        out[v * nc + d] = in[v * ustride + u];
     else
-        out[v * nc + u] = in[v * nc + d];
+        out[v * ustride + u] = in[v * nc + d];
 }
 
 __global__ void k_clear_alpha(unsigned long long *alpha, int nslot)
@@ -2046,6 +2048,11 @@ std::vector<int> stencil_capacities(int dim, int p)
     return {};
 }
 
+int default_lanes(const DevMesh &dm)
+{
+    return dm.dim == 3 ? 8 : (dm.dim == 2 && dm.p == 3 ? 2 : (dm.dim == 2 && dm.p == 5 ? 16 : 4));
+}
+
 std::vector<int> lane_choices(const DevMesh &dm)
 {
     if (dm.balance) return {dm.dim == 3 ? 8 : 2};
@@ -2116,8 +2123,7 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
     // up to 56 rows), 16 for 2-D p=5 (15 coefficients: fewer lanes spill
     // registers), 4 otherwise.  Fewer lanes replicate less of the
     // per-column work (pivot search, exchanges, broadcasts) across a cell.
-    const int lanes = dm.lanes ? dm.lanes
-                               : (dm.dim == 3 ? 8 : (dm.dim == 2 && dm.p == 3 ? 2 : (dm.dim == 2 && dm.p == 5 ? 16 : 4)));
+    const int lanes = dm.lanes ? dm.lanes : default_lanes(dm);
     if (dm.balance) {
         // the refit list of this stage starts empty
         hipLaunchKernelGGL(k_clear_alpha, dim3(1), dim3(64), 0, st, a.bal_count, 1);
@@ -2347,7 +2353,7 @@ int launch_permute(const DevMesh &dm, const double *in, double *out, bool to_dev
 {
     const int64_t work = dm.nc * dm.nvars;
     hipLaunchKernelGGL(k_permute, dim3(blocks_for(work, 256)), dim3(256), 0, (hipStream_t)stream, dm.nc,
-                       dm.nvars, dm.perm, in, out, to_device_order ? 1 : 0);
+                       dm.nvars, dm.perm, in, out, to_device_order ? 1 : 0, dm.user_stride ? dm.user_stride : dm.nc);
     return (int)hipGetLastError();
 }
 

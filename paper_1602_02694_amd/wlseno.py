@@ -83,6 +83,33 @@ class WLSENO:
         self.n_cell = (self.n_cell or 0) + int(c.shape[0]) if mid.value > 0 else int(c.shape[0])
         return mid.value
 
+    @staticmethod
+    def _params(lib, p=3, n_lo=12, n_hi=20, flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2, alpha_w=1.5,
+                rank_tol=1e-12, weight_mode=0, gamma=1.4, lanes=0, bc=0, characteristic=False, far_state=None,
+                balance=False, lf_alpha=0, h_mode=0):
+        prm = N.Params()
+        lib.wlseno_params_default(C.byref(prm))
+        prm.p, prm.n_lo, prm.n_hi = int(p), int(n_lo), int(n_hi)
+        prm.flux = N.FLUX[flux] if isinstance(flux, str) else int(flux)
+        prm.weight_mode = int(weight_mode)
+        prm.lanes = int(lanes)
+        prm.bc = int(bc)
+        prm.characteristic = int(bool(characteristic))
+        prm.balance = int(bool(balance))
+        prm.lf_alpha = int(lf_alpha)
+        prm.h_mode = int(h_mode)
+        for v in range(5):
+            prm.far_state[v] = float(far_state[v]) if far_state is not None and v < len(far_state) else 0.0
+        prm.eps, prm.alpha_w, prm.rank_tol, prm.gamma = float(eps), float(alpha_w), float(rank_tol), float(gamma)
+        for d in range(3):
+            prm.velocity[d] = float(velocity[d]) if d < len(velocity) else 0.0
+        return prm
+
+    def batch_params(self, dim, **kw):
+        """Parameters (as stencil_build's keywords) for the batch's meshes of one dim; none: drop them."""
+        prm = self._params(self._lib, **kw) if kw else None
+        self._check(self._lib.wlseno_batch_params(self._h, int(dim), C.byref(prm) if prm is not None else None))
+
     def stencil_build(self, p=3, n_lo=12, n_hi=20, flux="advection", velocity=(1.0, 0.0, 0.0), eps=1e-2,
                       alpha_w=1.5, rank_tol=1e-12, weight_mode=0, gamma=1.4, lanes=0, bc=0, characteristic=False,
                       far_state=None, balance=False, lf_alpha=0, h_mode=0):

@@ -718,6 +718,58 @@ def test_batch_matches_single_meshes(flux, p, n_lo, n_hi, extra):
         off += n
 
 
+@pytest.mark.parametrize("flux", ["burgers", "advection"])
+def test_batch_of_2d_and_3d_meshes(flux):
+    """Triangle and tetrahedral meshes in one batch (a group per dim, with its
+    own order and stencil sizes, stepped concurrently): bit for bit what each
+    mesh gives alone -- rhs, the allocation-free rhs, per-mesh alpha, steps
+    with a time step per mesh, in graph, direct and 32-step-graph runs."""
+    torch = _torch()
+    from paper_1602_02694_amd import WLSENO
+    from workloads import jittered_cube
+
+    meshes = [(2, jittered_square(9, 0.3, 3311)), (3, jittered_cube(5, 0.15, 3312)),
+              (2, jittered_square(12, 0.3, 3313)), (3, jittered_cube(4, 0.15, 3314))]
+    kw2 = dict(p=3, n_lo=12, n_hi=20, flux=flux, velocity=(1.0, 0.5, 0.25))
+    kw3 = dict(p=3, n_lo=30, n_hi=50, flux=flux, velocity=(1.0, 0.5, 0.25))
+    us = [fields.cell_averages(m, fields.gaussian_bump_with_step_2d if d == 2 else fields.sine_with_sphere_3d)
+          for d, m in meshes]
+    _say(f"[case] mixed-dim batch {flux}: cells {[m.n_cell for _, m in meshes]}")
+    wb = WLSENO(device=0)
+    for k, (d, m) in enumerate(meshes):
+        assert wb.batch_add_mesh(d, m.verts, m.cells) == k
+    wb.batch_params(3, **kw3)
+    wb.stencil_build(**kw2)
+    assert wb.info()["n_mesh"] == 4 and wb.info()["dim"] == 0
+    ub = torch.tensor(np.concatenate(us), device="cuda")
+    Lb = wb.rhs(ub).cpu().numpy()
+    La = torch.full_like(ub, float("nan"))
+    wb.rhs_noalloc(ub, La)
+    assert np.array_equal(La.cpu().numpy(), Lb)
+    ab = wb.batch_last_alpha()
+    singles, off = [], 0
+    for k, (d, m) in enumerate(meshes):
+        w = _gpu(m, **(kw2 if d == 2 else kw3))
+        u = torch.tensor(us[k], device="cuda")
+        assert np.array_equal(w.rhs(u).cpu().numpy(), Lb[off:off + m.n_cell]), f"mesh {k} rhs"
+        assert w.last_alpha() == ab[k]
+        singles.append((w, u))
+        off += m.n_cell
+    speed = [max(a, 1e-30) for a in ab] if flux == "burgers" else [float(np.linalg.norm((1.0, 0.5, 0.25)))] * 4
+    dts = [0.5 * w.info()["min_insphere"] / sp for (w, _), sp in zip(singles, speed)]
+    for mode, n in (("graphs", 3), ("direct", 2), ("graphs", 33)):
+        wb.set_step_mode(mode)
+        wb.batch_step(ub, dts, n)
+        got = ub.cpu().numpy()
+        off = 0
+        for k, (w, u) in enumerate(singles):
+            w.set_step_mode(mode)
+            w.step(u, dts[k], n)
+            c = meshes[k][1].n_cell
+            assert np.array_equal(u.cpu().numpy(), got[off:off + c]), f"mesh {k} steps ({mode}, {n})"
+            off += c
+
+
 def test_batch_errors():
     torch = _torch()
     from paper_1602_02694_amd import WLSENO, WLSENOError

@@ -210,11 +210,28 @@ def test_batch_stencils_are_the_meshes_own(lib):
         assert np.array_equal(np.diff(rp[off:off + m.n_cell + 1]), np.diff(orp))
         assert np.array_equal(col[seg], ocol + off)
         off += m.n_cell
-    # a mesh of another dimension cannot join; a single upload replaces the batch
-    line = periodic_line(20, 0.1, 5)
+    # a mesh of another dimension joins as a group of its own, with its own
+    # parameters; stencils stay each mesh's own, in add order
+    cube = jittered_cube(4, 0.15, 9)
+    assert w.batch_add_mesh(3, cube.verts, cube.cells) == 3
+    w.batch_add_mesh(2, meshes[1].verts, meshes[1].cells)
+    w.batch_params(3, p=2, n_lo=8, n_hi=16)
+    w.stencil_build(p=3, n_lo=12, n_hi=20)
+    inf = w.info()
+    assert inf["n_mesh"] == 5 and inf["dim"] == 0 and inf["m"] == 0
+    assert inf["n_cell"] == sum(m.n_cell for m in meshes) + cube.n_cell + meshes[1].n_cell
+    rp, col = w.stencil()
+    off = 0
+    for m, dim, kw in [(x, 2, (3, 12, 20)) for x in meshes] + [(cube, 3, (2, 8, 16)), (meshes[1], 2, (3, 12, 20))]:
+        om = OracleMesh(dim, m.verts, m.cells, p=kw[0])
+        orp, ocol = om.stencils(kw[1], kw[2])
+        assert np.array_equal(np.diff(rp[off:off + m.n_cell + 1]), np.diff(orp))
+        assert np.array_equal(col[rp[off]:rp[off + m.n_cell]], ocol + off)
+        off += m.n_cell
     with pytest.raises(WLSENOError) as e:
-        w.batch_add_mesh(1, line.verts, line.cells)
+        w.batch_params(4, p=3)
     assert e.value.status == 1
+    # a single upload replaces the batch
     w.mesh_upload(2, meshes[0].verts, meshes[0].cells)
     w.stencil_build(p=3, n_lo=12, n_hi=20)
     assert w.info()["n_mesh"] == 1 and w.info()["n_cell"] == meshes[0].n_cell
