@@ -774,19 +774,33 @@ def test_batch_errors():
     torch = _torch()
     from paper_1602_02694_amd import WLSENO, WLSENOError
 
+    from workloads import jittered_cube
+
     meshes, us = _batch("burgers", 3302)
     wb = WLSENO(device=0)
     for m in meshes:
         wb.batch_add_mesh(2, m.verts, m.cells)
-    line = periodic_line(20, 0.1, 5)
-    with pytest.raises(WLSENOError) as e:
-        wb.batch_add_mesh(1, line.verts, line.cells)
-    assert e.value.status == 1
     wb.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers")
     u = torch.tensor(np.concatenate(us, axis=1).reshape(-1), device="cuda")
     with pytest.raises(WLSENOError) as e:
         wb.batch_step(u, [1e-3, float("nan"), 1e-3], 1)
     assert e.value.status == 1
+    # meshes of several dims: the groups must agree on the field components,
+    # and per-dim layouts have no batch-wide reconstruction or kernel timing
+    cube = jittered_cube(4, 0.15, 3303)
+    wb.batch_add_mesh(3, cube.verts, cube.cells)
+    wb.batch_params(3, p=2, n_lo=8, n_hi=16, flux="burgers")
+    with pytest.raises(WLSENOError) as e:
+        wb.stencil_build(p=3, n_lo=12, n_hi=20, flux="euler")
+    assert e.value.status == 1 and "field components" in str(e.value)
+    wb.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers")
+    u = torch.zeros(wb.info()["n_cell"], dtype=torch.float64, device="cuda")
+    with pytest.raises(WLSENOError) as e:
+        wb.reconstruct(u)
+    assert e.value.status == 5
+    with pytest.raises(WLSENOError) as e:
+        wb.time_kernel(0, u, 2)
+    assert e.value.status == 5
 
 
 @pytest.mark.parametrize("case", ["single", "batch", "balance", "characteristic", "cube-local-alpha"])
