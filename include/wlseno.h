@@ -55,7 +55,8 @@ typedef enum {
     WLSENO_EDEVICE = 3,      /* a HIP runtime call failed */
     WLSENO_ESTATE = 4,       /* call out of order (e.g. rhs before stencil_build),
                                 or a device call on a host-only context */
-    WLSENO_EUNSUPPORTED = 5  /* valid request outside the compiled variants */
+    WLSENO_EUNSUPPORTED = 5, /* valid request outside the compiled variants */
+    WLSENO_ENUMERIC = 6      /* non-finite output (only with wlseno_set_numeric_check) */
 } wlseno_status;
 
 /* flux functions */
@@ -156,10 +157,12 @@ typedef struct wlseno_ctx *wlseno_t;
  * advection with a = (1,0,0), gamma = 1.4). */
 void wlseno_params_default(wlseno_params *out);
 
-/* Create a context on HIP device `device` (its default stream is used until
- * wlseno_set_stream).  device = -1 creates a host-only context: mesh upload,
- * stencil build and the query functions work, device calls return ESTATE. */
-wlseno_status wlseno_create(int device, wlseno_t *out);
+/* Create a context on HIP device `device` whose device work goes to
+ * `hip_stream` (a hipStream_t; NULL = the device's null stream; see also
+ * wlseno_set_stream).  device = -1 creates a host-only context (hip_stream must
+ * be NULL): mesh upload, stencil build and the query functions work, device
+ * calls return ESTATE. */
+wlseno_status wlseno_create(int device, void *hip_stream, wlseno_t *out);
 
 /* Free everything the context owns (host and device).  NULL is accepted. */
 wlseno_status wlseno_destroy(wlseno_t ctx);
@@ -171,6 +174,17 @@ const char *wlseno_last_error(wlseno_t ctx);
 /* Enqueue all later device work on `hip_stream` (a hipStream_t; NULL = the
  * device's null stream). */
 wlseno_status wlseno_set_stream(wlseno_t ctx, void *hip_stream);
+
+/* enable != 0: wlseno_reconstruct, wlseno_rhs, wlseno_rhs_noalloc,
+ * wlseno_step and wlseno_batch_step scan their input averages for NaN or
+ * infinity before any work, and their outputs after it (a small kernel and a
+ * stream synchronisation per scan), and return ENUMERIC naming the first such
+ * entry (component and cell, user order) in wlseno_last_error.  A bad input
+ * leaves the outputs untouched; a bad output is written as computed.  (The
+ * solve does not pass a NaN average on: a NaN row makes the cell's rank 0 and
+ * its polynomial zero, so the input scan is what catches it.)  Default: off.
+ * A device context allocates 8 bytes of device memory the first time. */
+wlseno_status wlseno_set_numeric_check(wlseno_t ctx, int enable);
 
 /* Upload a simplex mesh (host arrays, copied).
  *   xyz   : double[n_vert * dim] vertex coordinates
@@ -204,7 +218,11 @@ wlseno_status wlseno_get_info(wlseno_t ctx, wlseno_info *out);
  * row_ptr int32[n_cell+1], col int32[nnz]; rows as described above. */
 wlseno_status wlseno_get_stencil(wlseno_t ctx, int32_t *row_ptr, int32_t *col);
 
-/* Reconstruct every cell from u_dev (double[n_vars * n_cell]).
+/* Reconstruct every cell from u_dev (double[n_vars * n_cell]): gather the
+ * stencil's averages (Sec. 3.1.1, 3.2), weight the rows by the
+ * non-smoothness indicators (Sec. 3.1.2), solve the column-scaled weighted
+ * least-squares system by QR with column pivoting (Sec. 3.3.2) and evaluate
+ * the polynomial at the facet quadrature points (Sec. 1, 3.3.1).
  *   coef_dev     : nullable, double[n_vars * n_cell * m] Taylor coefficients
  *   facevals_dev : nullable, double[n_vars * n_cell * (dim+1) * Q] values of the
  *                  reconstruction at each cell's own facet points
@@ -219,8 +237,9 @@ wlseno_status wlseno_reconstruct(wlseno_t ctx, const double *u_dev, double *coef
  * selects.  dudt_dev must not alias u_dev. */
 wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev);
 
-/* Advance u_dev in place by n_steps steps of size dt of third-order TVD
- * Runge-Kutta (three right-hand sides per step). */
+/* Advance u_dev in place by n_steps steps of size dt of the third-order TVD
+ * Runge-Kutta scheme (Sec. 4.2.1; three right-hand sides per step, each as
+ * wlseno_rhs). */
 wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps);
 
 /* The global Lax-Friedrichs alpha of the last rhs stage: the largest normal

@@ -8,7 +8,8 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwlseno.so")
 
 WLSENO_OK = 0
-STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EUNSUPPORTED"}
+WLSENO_ENUMERIC = 6
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EUNSUPPORTED", 6: "ENUMERIC"}
 FLUX = {"advection": 0, "burgers": 1, "euler": 2}
 MESH_PERIODIC_1D = 1
 MESH_PERIODIC_2D = 2
@@ -21,6 +22,7 @@ EXPORTS = [
     "wlseno_batch_add_mesh", "wlseno_batch_step", "wlseno_batch_last_alpha", "wlseno_set_graphs",
     "wlseno_rhs_vjp", "wlseno_step_adjoint", "wlseno_step_record", "wlseno_step_adjoint_recorded",
     "wlseno_rhs_noalloc", "wlseno_set_step_mode", "wlseno_autotune", "wlseno_batch_params",
+    "wlseno_set_numeric_check",
 ]
 
 
@@ -71,7 +73,8 @@ def load():
     ip = C.POINTER(C.c_int32)
     lib.wlseno_params_default.argtypes = [C.POINTER(Params)]
     lib.wlseno_params_default.restype = None
-    lib.wlseno_create.argtypes = [C.c_int, C.POINTER(vp)]
+    lib.wlseno_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+    lib.wlseno_set_numeric_check.argtypes = [vp, C.c_int]
     lib.wlseno_destroy.argtypes = [vp]
     lib.wlseno_last_error.argtypes = [vp]
     lib.wlseno_last_error.restype = C.c_char_p

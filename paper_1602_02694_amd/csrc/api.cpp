@@ -21,6 +21,8 @@ struct wlseno_ctx {
     int device = -1;
     hipStream_t stream = nullptr;
     unsigned char *scratch = nullptr;   // this device's static scratch array (wlseno_rhs_noalloc)
+    bool check_numeric = false;         // wlseno_set_numeric_check
+    unsigned long long *nf_first = nullptr;   // its device word (first non-finite entry)
     std::string err;
     bool have_mesh = false, have_build = false;
     HostMesh mesh;
@@ -307,6 +309,30 @@ hipGraphExec_t steps_graph(wlseno_ctx *c, double h, int g)
 
 double time_launches(wlseno_ctx *ctx, int kernel, int launches);
 
+// With the numeric check on: ENUMERIC if p[0, n) (an output in user order,
+// `per` entries per component and cell, components of `stride` cells) holds a
+// NaN or infinity, naming the first.
+void numeric_check(wlseno_ctx *ctx, const double *p, int64_t n, int64_t stride, int per, const char *what)
+{
+    if (!ctx->check_numeric || !p || n <= 0) return;
+    unsigned long long first = 0;
+    check_launch(first_nonfinite(p, n, ctx->nf_first, &first, ctx->stream), "numeric check");
+    if (first == ~0ull) return;
+    const int64_t i = (int64_t)first, cell = (i / per) % stride, comp = (i / per) / stride;
+    throw Error{WLSENO_ENUMERIC, std::string("non-finite ") + what + " at entry " + std::to_string(i) + " (component " +
+                                     std::to_string(comp) + ", cell " + std::to_string(cell) + ")"};
+}
+
+// Cells and components of the caller's arrays: the whole batch for a mixed one.
+int64_t user_cells(const wlseno_ctx *ctx)
+{
+    if (ctx->groups.empty()) return ctx->dm.nc;
+    int64_t n = 0;
+    for (const auto &pt : ctx->parts) n += pt.nc;
+    return n;
+}
+int user_vars(const wlseno_ctx *ctx) { return ctx->groups.empty() ? ctx->dm.nvars : ctx->groups[0].c->dm.nvars; }
+
 }  // namespace
 
 #define API_BEGIN(ctx)                                                   \
@@ -362,7 +388,8 @@ void group_add(wlseno_ctx *c, int dim, int64_t nv, const double *xyz, int64_t nc
     if (gi == c->groups.size()) {
         wlseno_ctx::Group g;
         g.dim = dim;
-        if (wlseno_create(c->device, &g.c) != WLSENO_OK) throw Error{WLSENO_EDEVICE, wlseno_last_error(nullptr)};
+        if (wlseno_create(c->device, nullptr, &g.c) != WLSENO_OK)
+            throw Error{WLSENO_EDEVICE, wlseno_last_error(nullptr)};
         c->groups.push_back(g);
         wlseno_ctx::Group &gr = c->groups.back();
         gr.c->step_mode = c->step_mode;
@@ -465,11 +492,15 @@ void wlseno_params_default(wlseno_params *out)
     for (int v = 0; v < 5; ++v) out->far_state[v] = 0.0;
 }
 
-wlseno_status wlseno_create(int device, wlseno_t *out)
+wlseno_status wlseno_create(int device, void *hip_stream, wlseno_t *out)
 {
     if (!out) return WLSENO_EINVAL;
     *out = nullptr;
     g_create_error.clear();
+    if (device == -1 && hip_stream) {
+        g_create_error = "a host-only context takes no stream";
+        return WLSENO_EINVAL;
+    }
     if (device >= 0) {
         int n = 0;
         hipError_t e = hipGetDeviceCount(&n);
@@ -497,6 +528,7 @@ wlseno_status wlseno_create(int device, wlseno_t *out)
     wlseno_ctx *c = new (std::nothrow) wlseno_ctx;
     if (!c) return WLSENO_ENOMEM;
     c->device = device;
+    c->stream = (hipStream_t)hip_stream;
     c->scratch = (unsigned char *)scr;
     *out = c;
     return WLSENO_OK;
@@ -508,8 +540,23 @@ wlseno_status wlseno_destroy(wlseno_t ctx)
     drop_groups(ctx);
     free_device(ctx);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+    if (ctx->nf_first) (void)hipFree(ctx->nf_first);
     delete ctx;
     return WLSENO_OK;
+}
+
+wlseno_status wlseno_set_numeric_check(wlseno_t ctx, int enable)
+{
+    API_BEGIN(ctx)
+    if (enable && ctx->device >= 0 && !ctx->nf_first) {
+        check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+        void *p = nullptr;
+        if (hipMalloc(&p, sizeof(unsigned long long)) != hipSuccess)
+            throw Error{WLSENO_ENOMEM, "device allocation failed (numeric check word)"};
+        ctx->nf_first = (unsigned long long *)p;
+    }
+    ctx->check_numeric = enable != 0;
+    API_END(ctx)
 }
 
 wlseno_status wlseno_set_graphs(wlseno_t ctx, int enable)
@@ -769,11 +816,18 @@ wlseno_status wlseno_reconstruct(wlseno_t ctx, const double *u_dev, double *coef
     if (coef_dev && ctx->have_build && ctx->build.prm.characteristic)
         throw Error{WLSENO_EINVAL, "no coefficient output with characteristic fields (one fit per facet)"};
     need_device(ctx);
+    numeric_check(ctx, u_dev, (int64_t)ctx->dm.nvars * ctx->dm.nc, ctx->dm.nc, 1, "input average");
     check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
     check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
     check_launch(launch_reconstruct(ctx->dm, ctx->ubuf, 0, coef_dev, facevals_dev, rank_dev, ctx->stream),
                  "reconstruct");
     ctx->last_parity = 0;
+    {
+        const DevMesh &d = ctx->dm;
+        const int per_f = d.nf * d.nq;
+        numeric_check(ctx, facevals_dev, (int64_t)d.nvars * d.nc * per_f, d.nc, per_f, "facet value");
+        numeric_check(ctx, coef_dev, (int64_t)d.nvars * d.nc * d.m, d.nc, d.m, "coefficient");
+    }
     API_END(ctx)
 }
 
@@ -783,16 +837,18 @@ wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev)
     if (!u_dev || !dudt_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
     if (u_dev == dudt_dev) throw Error{WLSENO_EINVAL, "dudt_dev must not alias u_dev"};
     need_device(ctx);
+    numeric_check(ctx, u_dev, user_vars(ctx) * user_cells(ctx), user_cells(ctx), 1, "input average");
     if (mixed(ctx)) {
         fork_groups(ctx);
         for (auto &g : ctx->groups) check_child(g.c, wlseno_rhs(g.c, u_dev, dudt_dev), g.dim);
         join_groups(ctx);
-        return WLSENO_OK;
+    } else {
+        check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
+        check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
+        stage(ctx, ctx->ubuf, nullptr, nullptr, ctx->tbuf, 0.0, 0.0, 1.0, 0, 0, ctx->stream);
+        check_launch(launch_permute(ctx->dm, ctx->tbuf, dudt_dev, false, ctx->stream), "permute");
     }
-    check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
-    check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
-    stage(ctx, ctx->ubuf, nullptr, nullptr, ctx->tbuf, 0.0, 0.0, 1.0, 0, 0, ctx->stream);
-    check_launch(launch_permute(ctx->dm, ctx->tbuf, dudt_dev, false, ctx->stream), "permute");
+    numeric_check(ctx, dudt_dev, user_vars(ctx) * user_cells(ctx), user_cells(ctx), 1, "right-hand side");
     API_END(ctx)
 }
 
@@ -802,6 +858,7 @@ wlseno_status wlseno_rhs_noalloc(wlseno_t ctx, const double *u_dev, double *dudt
     if (!u_dev || !dudt_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
     if (u_dev == dudt_dev) throw Error{WLSENO_EINVAL, "dudt_dev must not alias u_dev"};
     need_device(ctx);
+    numeric_check(ctx, u_dev, user_vars(ctx) * user_cells(ctx), user_cells(ctx), 1, "input average");
     if (mixed(ctx)) {
         // the groups share this device's array: one after another, on our stream
         for (auto &g : ctx->groups) {
@@ -810,6 +867,7 @@ wlseno_status wlseno_rhs_noalloc(wlseno_t ctx, const double *u_dev, double *dudt
             (void)wlseno_set_stream(g.c, g.st);
             check_child(g.c, st, g.dim);
         }
+        numeric_check(ctx, dudt_dev, user_vars(ctx) * user_cells(ctx), user_cells(ctx), 1, "right-hand side");
         return WLSENO_OK;
     }
     if (ctx->dm.balance) throw Error{WLSENO_EUNSUPPORTED, "the balanced refit keeps buffers of its own"};
@@ -835,6 +893,7 @@ wlseno_status wlseno_rhs_noalloc(wlseno_t ctx, const double *u_dev, double *dudt
     check_launch(launch_reconstruct(dm, ub, 0, nullptr, nullptr, nullptr, ctx->stream), "reconstruct");
     check_launch(launch_update(dm, nullptr, nullptr, tb, 0.0, 0.0, 1.0, 0, 0, ctx->stream), "update");
     check_launch(launch_permute(dm, tb, dudt_dev, false, ctx->stream), "permute");
+    numeric_check(ctx, dudt_dev, user_vars(ctx) * user_cells(ctx), user_cells(ctx), 1, "right-hand side");
     API_END(ctx)
 }
 
@@ -1051,13 +1110,15 @@ wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps)
     if (!std::isfinite(dt) || n_steps < 0) throw Error{WLSENO_EINVAL, "dt must be finite and n_steps >= 0"};
     need_device(ctx);
     if (n_steps == 0) return WLSENO_OK;
+    numeric_check(ctx, u_dev, user_vars(ctx) * user_cells(ctx), user_cells(ctx), 1, "input average");
     if (mixed(ctx)) {
         fork_groups(ctx);
         for (auto &g : ctx->groups) check_child(g.c, wlseno_step(g.c, u_dev, dt, n_steps), g.dim);
         join_groups(ctx);
-        return WLSENO_OK;
+    } else {
+        run_steps(ctx, u_dev, dt, nullptr, n_steps);
     }
-    run_steps(ctx, u_dev, dt, nullptr, n_steps);
+    numeric_check(ctx, u_dev, user_vars(ctx) * user_cells(ctx), user_cells(ctx), 1, "state");
     API_END(ctx)
 }
 
@@ -1067,6 +1128,7 @@ wlseno_status wlseno_batch_step(wlseno_t ctx, double *u_dev, const double *dt_pe
     if (!u_dev || !dt_per_mesh) throw Error{WLSENO_EINVAL, "null pointer"};
     if (n_steps < 0) throw Error{WLSENO_EINVAL, "n_steps >= 0 required"};
     need_device(ctx);
+    if (n_steps > 0) numeric_check(ctx, u_dev, user_vars(ctx) * user_cells(ctx), user_cells(ctx), 1, "input average");
     if (mixed(ctx)) {
         for (size_t k = 0; k < ctx->parts.size(); ++k)
             if (!std::isfinite(dt_per_mesh[k])) throw Error{WLSENO_EINVAL, "time steps must be finite"};
@@ -1078,15 +1140,16 @@ wlseno_status wlseno_batch_step(wlseno_t ctx, double *u_dev, const double *dt_pe
             check_child(g.c, wlseno_batch_step(g.c, u_dev, dts.data(), n_steps), g.dim);
         }
         join_groups(ctx);
-        return WLSENO_OK;
+    } else {
+        for (int k = 0; k < ctx->mesh.nmesh; ++k)
+            if (!std::isfinite(dt_per_mesh[k])) throw Error{WLSENO_EINVAL, "time steps must be finite"};
+        if (n_steps == 0) return WLSENO_OK;
+        if (ctx->dm.nmesh == 1)
+            run_steps(ctx, u_dev, dt_per_mesh[0], nullptr, n_steps);
+        else
+            run_steps(ctx, u_dev, 0.0, dt_per_mesh, n_steps);
     }
-    for (int k = 0; k < ctx->mesh.nmesh; ++k)
-        if (!std::isfinite(dt_per_mesh[k])) throw Error{WLSENO_EINVAL, "time steps must be finite"};
-    if (n_steps == 0) return WLSENO_OK;
-    if (ctx->dm.nmesh == 1)
-        run_steps(ctx, u_dev, dt_per_mesh[0], nullptr, n_steps);
-    else
-        run_steps(ctx, u_dev, 0.0, dt_per_mesh, n_steps);
+    numeric_check(ctx, u_dev, user_vars(ctx) * user_cells(ctx), user_cells(ctx), 1, "state");
     API_END(ctx)
 }
 

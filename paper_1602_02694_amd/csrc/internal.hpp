@@ -164,6 +164,10 @@ int launch_adjoint_gather(const DevMesh &dm, const int64_t *tptr, const double *
 // its place (-1: padding or a boundary facet).
 void transpose_tables(const Build &b, int64_t nc, int nf, std::vector<int64_t> &tptr, std::vector<int32_t> &tpos);
 int launch_clear_alpha(const DevMesh &dm, void *stream);
+// Smallest index i < n with p[i] not finite into *first_host (all ones if
+// none); first_dev: 8 bytes of device memory.  Synchronises the stream.
+int first_nonfinite(const double *p, int64_t n, unsigned long long *first_dev, unsigned long long *first_host,
+                    void *stream);
 // n TVD RK3 steps of the device-order state u (stage buffer k) in one
 // cooperative launch with device-wide barriers between phases; sync: 64
 // unsigned words of device memory (arrival counter, failure flag at [32],

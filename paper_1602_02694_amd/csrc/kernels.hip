@@ -736,6 +736,25 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
     }
     bmin = bmin < 0.0 ? eh2 : bmin;
 
+    // centroid offsets in place of the centroids; on a periodic mesh, to the
+    // nearest image (a branch the whole wave takes or skips)
+#pragma unroll
+    for (int s = 0; s < RPL; ++s)
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) gx[s][d] -= xc[d];
+    if constexpr (DIM <= 2) {
+        if (a.period > 0.0 || a.period_y > 0.0) {
+#pragma unroll
+            for (int s = 0; s < RPL; ++s)
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) {
+                    const double L = d == 0 ? a.period : a.period_y;
+                    const double x = gx[s][d];
+                    if (L > 0.0) gx[s][d] = x > 0.5 * L ? x - L : (x < -0.5 * L ? x + L : x);
+                }
+        }
+    }
+
     // weighted rows  W A  and  W u
     double A[RPL][M], bv[RPL];
 #pragma unroll
@@ -743,7 +762,8 @@ __device__ __forceinline__ void reconstruct_cell(const RArgs &a, int64_t cell, i
         const int r = s * G + g;
         const bool valid = jrow[s] >= 0;
         double dl[DIM];
-        centroid_offset<DIM>(gx[s], xc, a.period, a.period_y, dl);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) dl[d] = gx[s][d];
         const double uj = ug[s];
         double row[M];
         taylor_row<DIM, P>(dl, gx[s] + DIM, row);
@@ -1905,6 +1925,16 @@ __global__ void k_permute(int64_t nc, int nvars, const int32_t *perm, const doub
         out[v * ustride + u] = in[v * nc + d];
 }
 
+// Smallest index of a non-finite entry of p[0, n) into *first (left at its
+// initial all-ones value if there is none).
+__global__ void k_first_nonfinite(int64_t n, const double *p, unsigned long long *first)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(p[i])) atomicMin(first, (unsigned long long)i);
+}
+
+__global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v; }
+
 __global__ void k_clear_alpha(unsigned long long *alpha, int nslot)
 {
     const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -2393,6 +2423,22 @@ int launch_clear_alpha(const DevMesh &dm, void *stream)
     const int n = (int)(2 * dm.alpha_slots());
     hipLaunchKernelGGL(k_clear_alpha, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, dm.alpha, n);
     return (int)hipGetLastError();
+}
+
+int first_nonfinite(const double *p, int64_t n, unsigned long long *first_dev, unsigned long long *first_host,
+                    void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    k_set_u64<<<1, 1, 0, st>>>(first_dev, ~0ull);
+    if (n > 0) {
+        const int64_t want = (n + 255) / 256;
+        k_first_nonfinite<<<(int)(want < 4096 ? want : 4096), 256, 0, st>>>(n, p, first_dev);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    e = hipMemcpyAsync(first_host, first_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return (int)e;
+    return (int)hipStreamSynchronize(st);
 }
 
 }  // namespace wlseno

@@ -30,7 +30,7 @@ class WLSENO:
     def __init__(self, device: int = 0):
         self._lib = N.load()
         h = C.c_void_p()
-        st = self._lib.wlseno_create(int(device), C.byref(h))
+        st = self._lib.wlseno_create(int(device), None, C.byref(h))
         if st != N.WLSENO_OK:
             raise WLSENOError(st, self._lib.wlseno_last_error(None).decode())
         self._h = h
@@ -59,6 +59,11 @@ class WLSENO:
 
             s = torch.cuda.current_stream(self.device).cuda_stream
             self._check(self._lib.wlseno_set_stream(self._h, C.c_void_p(s)))
+
+    def set_numeric_check(self, enable: bool = True):
+        """Scan every later output for NaN/infinity; such an output raises
+        WLSENOError with status ENUMERIC naming the first entry."""
+        self._check(self._lib.wlseno_set_numeric_check(self._h, int(bool(enable))))
 
     # ------------------------------------------------------------ setup
     def mesh_upload(self, dim, verts, cells, periodic=False):

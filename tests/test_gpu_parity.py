@@ -803,6 +803,53 @@ def test_batch_errors():
     assert e.value.status == 5
 
 
+def test_numeric_check():
+    """wlseno_set_numeric_check: finite data pass; a NaN average makes rhs,
+    step and reconstruct return ENUMERIC (also in a batch of 2-D and 3-D
+    meshes, naming a cell of the mesh that holds it).  With the check off the
+    same calls succeed: every cell whose stencil holds the NaN gets rank 0."""
+    torch = _torch()
+    from paper_1602_02694_amd import WLSENO, WLSENOError
+
+    m = jittered_square(12, 0.3, 3401)
+    u0 = fields.cell_averages(m, fields.gaussian_bump_with_step_2d)
+    w = _gpu(m, p=3, n_lo=12, n_hi=20, flux="burgers")
+    w.set_numeric_check(True)
+    u = torch.tensor(u0, device="cuda")
+    w.rhs(u)
+    w.reconstruct(u)
+    w.step(u.clone(), 1e-4, 3)
+    bad = u.clone()
+    bad[17] = float("nan")
+    for call in (lambda: w.rhs(bad), lambda: w.step(bad.clone(), 1e-4, 1), lambda: w.reconstruct(bad)):
+        with pytest.raises(WLSENOError) as e:
+            call()
+        assert e.value.status == 6 and "non-finite" in str(e.value)
+    w.set_numeric_check(False)
+    w.rhs(bad)
+    rank = w.reconstruct(bad)["rank"].cpu().numpy().reshape(-1)
+    rp, col = w.stencil()
+    holds = np.array([17 in col[rp[i]:rp[i + 1]] for i in range(m.n_cell)])
+    assert holds.sum() > 1 and np.all(rank[holds] == 0) and np.all(rank[~holds] > 0)
+
+    cube = jittered_cube(4, 0.15, 3402)
+    wb = WLSENO(device=0)
+    wb.batch_add_mesh(2, m.verts, m.cells)
+    wb.batch_add_mesh(3, cube.verts, cube.cells)
+    wb.batch_params(3, p=2, n_lo=8, n_hi=16, flux="burgers")
+    wb.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers")
+    wb.set_numeric_check(True)
+    uc = fields.cell_averages(cube, fields.sine_with_sphere_3d)
+    ub = torch.tensor(np.concatenate([u0, uc]), device="cuda")
+    wb.rhs(ub)
+    ub[m.n_cell + 5] = float("inf")
+    with pytest.raises(WLSENOError) as e:
+        wb.rhs(ub)
+    assert e.value.status == 6
+    cell = int(str(e.value).split("cell ")[1].split(")")[0])
+    assert m.n_cell <= cell < m.n_cell + cube.n_cell
+
+
 @pytest.mark.parametrize("case", ["single", "batch", "balance", "characteristic", "cube-local-alpha"])
 def test_graph_replays_equal_direct_launches(case):
     """Steps replayed from the captured graphs (32-step and 2-step) equal

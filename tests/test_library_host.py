@@ -180,11 +180,32 @@ def test_error_paths(lib):
     assert "more than two" in str(e.value)
 
 
+def test_numeric_check_option_host():
+    """The numeric check is a context option: it can be set on a host-only
+    context (whose device calls still return ESTATE), and ENUMERIC has its
+    own status code."""
+    from paper_1602_02694_amd import WLSENO, WLSENOError, _native
+
+    assert _native.STATUS_NAMES[_native.WLSENO_ENUMERIC] == "ENUMERIC"
+    w = WLSENO(device=-1)
+    w.set_numeric_check(True)
+    w.set_numeric_check(False)
+    m = jittered_square(6, 0.3, 3403)
+    w.mesh_upload(2, m.verts, m.cells)
+    w.stencil_build(p=3, n_lo=12, n_hi=20)
+    # device pointers are never touched on a host-only context
+    assert w._lib.wlseno_rhs(w._h, C.c_void_p(8), C.c_void_p(16)) == 4
+    assert b"host-only" in w._lib.wlseno_last_error(w._h)
+
+
 def test_null_context_and_create_errors(lib):
     assert lib.wlseno_rhs(None, None, None) == 1
     h = C.c_void_p()
-    assert lib.wlseno_create(-5, C.byref(h)) == 1
+    assert lib.wlseno_create(-5, None, C.byref(h)) == 1
     assert b"device" in lib.wlseno_last_error(None)
+    # a host-only context takes no stream
+    assert lib.wlseno_create(-1, C.c_void_p(1), C.byref(h)) == 1
+    assert b"no stream" in lib.wlseno_last_error(None)
     assert lib.wlseno_destroy(None) == 0
 
 
