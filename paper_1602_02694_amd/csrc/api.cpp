@@ -461,6 +461,28 @@ void join_groups(wlseno_ctx *c)
     }
 }
 
+// fork_groups on construction; join_groups on join() or, if a group's call
+// threw first, on destruction, so that the caller's stream is always joined.
+struct GroupRun {
+    wlseno_ctx *c;
+    bool joined = false;
+    explicit GroupRun(wlseno_ctx *ctx) : c(ctx) { fork_groups(c); }
+    void join()
+    {
+        joined = true;
+        join_groups(c);
+    }
+    ~GroupRun()
+    {
+        if (!joined) {
+            try {
+                join_groups(c);
+            } catch (...) {
+            }
+        }
+    }
+};
+
 void need_single_dim(const wlseno_ctx *c, const char *what)
 {
     if (mixed(c)) throw Error{WLSENO_EUNSUPPORTED, std::string(what) + " works on batches of one dim only"};
@@ -839,9 +861,9 @@ wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev)
     need_device(ctx);
     numeric_check(ctx, u_dev, user_vars(ctx) * user_cells(ctx), user_cells(ctx), 1, "input average");
     if (mixed(ctx)) {
-        fork_groups(ctx);
+        GroupRun run(ctx);
         for (auto &g : ctx->groups) check_child(g.c, wlseno_rhs(g.c, u_dev, dudt_dev), g.dim);
-        join_groups(ctx);
+        run.join();
     } else {
         check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
         check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
@@ -1112,9 +1134,9 @@ wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps)
     if (n_steps == 0) return WLSENO_OK;
     numeric_check(ctx, u_dev, user_vars(ctx) * user_cells(ctx), user_cells(ctx), 1, "input average");
     if (mixed(ctx)) {
-        fork_groups(ctx);
+        GroupRun run(ctx);
         for (auto &g : ctx->groups) check_child(g.c, wlseno_step(g.c, u_dev, dt, n_steps), g.dim);
-        join_groups(ctx);
+        run.join();
     } else {
         run_steps(ctx, u_dev, dt, nullptr, n_steps);
     }
@@ -1133,13 +1155,13 @@ wlseno_status wlseno_batch_step(wlseno_t ctx, double *u_dev, const double *dt_pe
         for (size_t k = 0; k < ctx->parts.size(); ++k)
             if (!std::isfinite(dt_per_mesh[k])) throw Error{WLSENO_EINVAL, "time steps must be finite"};
         if (n_steps == 0) return WLSENO_OK;
-        fork_groups(ctx);
+        GroupRun run(ctx);
         for (auto &g : ctx->groups) {
             std::vector<double> dts;
             for (int32_t k : g.meshes) dts.push_back(dt_per_mesh[k]);
             check_child(g.c, wlseno_batch_step(g.c, u_dev, dts.data(), n_steps), g.dim);
         }
-        join_groups(ctx);
+        run.join();
     } else {
         for (int k = 0; k < ctx->mesh.nmesh; ++k)
             if (!std::isfinite(dt_per_mesh[k])) throw Error{WLSENO_EINVAL, "time steps must be finite"};
