@@ -586,10 +586,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    # 40 warm-up steps replay the 32-step graph once and the 2-step graph
-    # four times, so that capturing them (once per context and time step) is
-    # not part of the timed steps; with fewer than 32 the timed region pays
-    # one capture (about 0.5 ms on the 19,602-triangle mesh)
+    # the first stepping call captures the library's graphs (every run
+    # length, once per context and time step), so any warm-up of 2 or more
+    # steps keeps capture out of the timed steps
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--workload", default="square", choices=sorted(WORKLOADS) + ["batch"])
     ap.add_argument("--balance", action="store_true",

@@ -249,10 +249,12 @@ wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps);
  * device (synchronises the stream). */
 wlseno_status wlseno_last_alpha(wlseno_t ctx, double *alpha);
 
-/* wlseno_step and wlseno_batch_step replay runs of 32 RK3 steps, then pairs
- * of steps, from HIP graphs captured on first use (per context and time step;
- * recaptured when the time step or the stencil build changes), and launch an
- * odd last step directly.  enable = 0 launches every kernel directly; results
+/* wlseno_step and wlseno_batch_step replay runs of RK3 steps from HIP graphs
+ * of 32, 16, 8, 4 and 2 steps (32 as often as it fits, then each shorter size
+ * at most once) and launch an odd last step directly.  The five graphs are
+ * captured together the first time a run of 2 or more steps needs them, once
+ * per context and stencil build (time steps are read from device memory, so a
+ * new dt needs no recapture).  enable = 0 launches every kernel directly; results
  * are identical either way.  The default is enabled. */
 wlseno_status wlseno_set_graphs(wlseno_t ctx, int enable);
 

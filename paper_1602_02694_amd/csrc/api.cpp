@@ -65,8 +65,8 @@ struct wlseno_ctx {
     int step_mode = 1;            // 0 direct launches, 1 graph replay, 2 one persistent launch
     unsigned *sync = nullptr;     // persistent launch: barrier counter and failure flag
     hipStream_t cap = nullptr;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
-    double graph_h[2] = {0.0, 0.0};
+    hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double graph_h[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     // adjoint: transposed stencil, contributions, cotangents, checkpoints
     bool adj_ready = false;
     int64_t *tptr = nullptr;
@@ -93,14 +93,18 @@ void check_launch(int e, const char *what)
     if (e != 0) throw Error{WLSENO_EDEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)e)};
 }
 
-// Steps per graph: a long one for long runs (launch overhead spread over
-// more kernels: 1,024 steps of the 19,602-triangle benchmark 6% faster than
-// with pairs alone) and pairs for the rest.
-constexpr int kGraphSteps[2] = {32, 2};
+// Steps per graph: a ladder of powers of two, so that a run of n steps takes
+// floor(n / 32) replays of the longest and at most one of each shorter size
+// (each replay costs ~7 us of launch overhead on the 19,602-triangle
+// benchmark, against 44 us per step), then one direct step if n is odd.
+constexpr int kGraphLadder = 5;
+constexpr int kGraphSteps[kGraphLadder] = {32, 16, 8, 4, 2};
+// Cells up to which newly captured graphs get one replay ahead of use.
+constexpr int64_t kPrereplayCells = int64_t(1) << 18;
 
 void drop_graph(wlseno_ctx *c)
 {
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < kGraphLadder; ++g) {
         if (c->graph[g]) {
             (void)hipSetDevice(c->device);
             (void)hipGraphExecDestroy(c->graph[g]);
@@ -203,9 +207,11 @@ void upload_build(wlseno_ctx *c)
         for (int k = 0; k < m.nmesh; ++k) eh2[k] = b.prm.eps * m.mesh_h[k] * m.mesh_h[k];
         dm.mid = upload(c, b.mid);
         dm.eh2_tab = upload(c, eh2);
-        dm.dt_tab = (double *)dev_alloc(c, m.nmesh * sizeof(double));
-        c->dt_host.assign(m.nmesh, NAN);
     }
+    // time step per mesh in device memory (one mesh: one entry), read by the
+    // stepping kernels so that captured graphs hold no time step
+    dm.dt_tab = (double *)dev_alloc(c, m.nmesh * sizeof(double));
+    c->dt_host.assign(m.nmesh, NAN);
     dm.alpha_w = b.prm.alpha_w;
     dm.rank_tol = b.prm.rank_tol;
     dm.period = m.periodic ? m.period : 0.0;
@@ -257,28 +263,32 @@ void upload_build(wlseno_ctx *c)
 }
 
 // One right-hand-side stage: K1 then K2/K3 (flux, divergence, RK combination).
+// dev_dt (one mesh): Cdt is the stage coefficient and the kernel multiplies it
+// by the time step held in dm.dt_tab[0].
 void stage(wlseno_ctx *c, const double *in, const double *u0, const double *prev, double *out, double A,
-           double B, double Cdt, int mode, int parity, hipStream_t st)
+           double B, double Cdt, int mode, int parity, hipStream_t st, bool dev_dt = false)
 {
     check_launch(launch_reconstruct(c->dm, in, parity, nullptr, nullptr, nullptr, st), "reconstruct");
-    check_launch(launch_update(c->dm, u0, prev, out, A, B, Cdt, mode, parity, st), "update");
+    check_launch(launch_update(c->dm, u0, prev, out, A, B, Cdt, mode, parity, st, dev_dt ? c->dm.dt_tab : nullptr),
+                 "update");
     c->last_parity = parity;
 }
 
 // One TVD RK3 step on the device-order state ubuf, starting at `par`:
 // k1 = u + dt L(u); k2 = 3/4 u + 1/4 k1 + 1/4 dt L(k1); u = 1/3 u + 2/3 k2 + 2/3 dt L(k2)
-int rk3_step(wlseno_ctx *c, double h, int par, hipStream_t st)
+// (h = dt, or h = 1 with the time step in device memory: batches, or dev_dt)
+int rk3_step(wlseno_ctx *c, double h, int par, hipStream_t st, bool dev_dt = false)
 {
     double *u = c->ubuf, *k = c->kbuf;
-    stage(c, u, u, u, k, 1.0, 0.0, h, 1, par, st);
+    stage(c, u, u, u, k, 1.0, 0.0, h, 1, par, st, dev_dt);
     par ^= 1;
-    stage(c, k, u, k, k, 0.75, 0.25, 0.25 * h, 1, par, st);
+    stage(c, k, u, k, k, 0.75, 0.25, 0.25 * h, 1, par, st, dev_dt);
     par ^= 1;
-    stage(c, k, u, k, u, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * h, 1, par, st);
+    stage(c, k, u, k, u, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * h, 1, par, st, dev_dt);
     return par ^ 1;
 }
 
-// The two-step graph for stage scale h, captured on first use.
+// The graph of kGraphSteps[g] steps for stage scale h (captured if missing).
 hipGraphExec_t steps_graph(wlseno_ctx *c, double h, int g)
 {
     if (c->graph[g] && std::memcmp(&c->graph_h[g], &h, sizeof h) == 0) return c->graph[g];
@@ -291,7 +301,7 @@ hipGraphExec_t steps_graph(wlseno_ctx *c, double h, int g)
     hipGraph_t gr = nullptr;
     try {
         int par = 0;
-        for (int t = 0; t < kGraphSteps[g]; ++t) par = rk3_step(c, h, par, c->cap);
+        for (int t = 0; t < kGraphSteps[g]; ++t) par = rk3_step(c, h, par, c->cap, c->dm.nmesh == 1);
     } catch (...) {
         (void)hipStreamEndCapture(c->cap, &gr);
         if (gr) (void)hipGraphDestroy(gr);
@@ -302,6 +312,12 @@ hipGraphExec_t steps_graph(wlseno_ctx *c, double h, int g)
     hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
     (void)hipGraphDestroy(gr);
     check_hip(e, "hipGraphInstantiate");
+    // set up its device-side resources now rather than at its first replay
+    e = hipGraphUpload(ex, c->stream);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(ex);
+        check_hip(e, "hipGraphUpload");
+    }
     c->graph[g] = ex;
     c->graph_h[g] = h;
     return ex;
@@ -1078,7 +1094,10 @@ namespace {
 void run_steps(wlseno_ctx *ctx, double *u_dev, double dt, const double *dt_mesh, int n_steps)
 {
     const bool batch = ctx->dm.nmesh > 1;
-    if (batch) {
+    // the time steps go to device memory (one per mesh), read there by the
+    // stepping kernels so that captured graphs hold none; only the persistent
+    // kernel on one mesh takes its time step as an argument
+    if (batch || ctx->step_mode != 2) {
         bool changed = false;
         for (int k = 0; k < ctx->dm.nmesh; ++k) {
             const double v = dt_mesh ? dt_mesh[k] : dt;
@@ -1091,11 +1110,28 @@ void run_steps(wlseno_ctx *ctx, double *u_dev, double dt, const double *dt_mesh,
                                      hipMemcpyHostToDevice, ctx->stream),
                       "hipMemcpyAsync");
     }
-    // stage coefficients c dt; for a batch the kernel multiplies c by the mesh's dt
-    const double h = batch ? 1.0 : dt;
+    // stage coefficients c (times dt in the kernel), or c dt for the persistent
+    // kernel on one mesh
+    const double h = (batch || ctx->step_mode != 2) ? 1.0 : dt;
     if (ctx->step_mode == 2 && !steps_supported(ctx->dm))
         throw Error{WLSENO_EUNSUPPORTED, "the persistent step kernel is compiled for 2-D p = 3 scalar fluxes with "
                                          "2 lanes per cell and no balanced refit"};
+    if (ctx->use_graphs && ctx->step_mode != 2 && n_steps >= 2) {
+        // the whole ladder is captured together the first time any graph is
+        // needed for this h, so that later runs of other lengths capture
+        // nothing.  On meshes small enough for launch overhead to matter,
+        // each new graph is also replayed once here, on whatever the state
+        // buffers hold (the state is copied in below): a graph's first replay
+        // costs ~35 us more than later ones on the 19,602-triangle benchmark.
+        bool fresh = false;
+        for (int g = 0; g < kGraphLadder; ++g) {
+            fresh = fresh || !ctx->graph[g] || std::memcmp(&ctx->graph_h[g], &h, sizeof h) != 0;
+            (void)steps_graph(ctx, h, g);
+        }
+        if (fresh && ctx->dm.nc <= kPrereplayCells)
+            for (int g = 0; g < kGraphLadder; ++g)
+                check_hip(hipGraphLaunch(ctx->graph[g], ctx->stream), "hipGraphLaunch");
+    }
     check_launch(launch_permute(ctx->dm, u_dev, ctx->ubuf, true, ctx->stream), "permute");
     check_launch(launch_clear_alpha(ctx->dm, ctx->stream), "clear");
     if (ctx->step_mode == 2) {
@@ -1110,16 +1146,14 @@ void run_steps(wlseno_ctx *ctx, double *u_dev, double dt, const double *dt_mesh,
         return;
     }
     int s = 0;
-    if (ctx->use_graphs) {
-        for (int g = 0; g < 2; ++g) {
+    if (ctx->use_graphs && n_steps >= 2) {
+        for (int g = 0; g < kGraphLadder; ++g) {
             const int k = kGraphSteps[g];
-            if (n_steps - s < k) continue;
-            hipGraphExec_t ex = steps_graph(ctx, h, g);
-            for (; s + k <= n_steps; s += k) check_hip(hipGraphLaunch(ex, ctx->stream), "hipGraphLaunch");
-            ctx->last_parity = 1;
+            for (; s + k <= n_steps; s += k) check_hip(hipGraphLaunch(ctx->graph[g], ctx->stream), "hipGraphLaunch");
         }
+        ctx->last_parity = 1;
     }
-    for (; s < n_steps; ++s) rk3_step(ctx, h, s & 1 ? 1 : 0, ctx->stream);
+    for (; s < n_steps; ++s) rk3_step(ctx, h, s & 1 ? 1 : 0, ctx->stream, !batch);
     check_launch(launch_permute(ctx->dm, ctx->ubuf, u_dev, false, ctx->stream), "permute");
 }
 

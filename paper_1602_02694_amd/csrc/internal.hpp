@@ -183,7 +183,9 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
                        double *fv_user, int32_t *rank_user, void *stream);
 // out = L (mode 0) or A*u0 + B*prev + Cdt*L (mode 1).
 // Batches: Cdt is the stage coefficient, multiplied by each mesh's time step.
+// One mesh with dt_one non-null: likewise, by dt_one[0] (device memory), so
+// that captured graphs do not depend on the time step.
 int launch_update(const DevMesh &dm, const double *u0, const double *prev, double *out, double A,
-                  double B, double Cdt, int mode, int parity, void *stream);
+                  double B, double Cdt, int mode, int parity, void *stream, const double *dt_one = nullptr);
 
 }  // namespace wlseno

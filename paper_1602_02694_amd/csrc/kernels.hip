@@ -1551,6 +1551,7 @@ struct UArgs {
     unsigned long long *alpha_clr;        // next stage's parity, cleared by block 0
     const int32_t *mid;                   // batches: mesh of each cell (else null)
     const double *dt_tab;                 // batches: time step per mesh (Cdt is then the coefficient)
+    const double *dt_one;                 // one mesh: its time step, if Cdt is the coefficient (else null)
     int spm, nslot;                       // slots per mesh, slots per parity
     double A, B, Cdt;
     double vel[3];
@@ -1675,6 +1676,7 @@ __device__ __forceinline__ void update_block(const UArgs &a, int lb)
     const double rv = a.rvol[c];
     double alpha = 0.0;
     double cdt = a.Cdt;
+    if (!a.mid && a.dt_one) cdt = a.Cdt * a.dt_one[0];
     if (a.mid) {
         const int32_t mesh = a.mid[c];
         cdt = a.Cdt * a.dt_tab[mesh];
@@ -2205,7 +2207,7 @@ int launch_reconstruct(const DevMesh &dm, const double *u, int parity, double *c
 }
 
 UArgs fill_uargs(const DevMesh &dm, const double *u0, const double *prev, double *out, double A, double B,
-                 double Cdt, int mode, int parity)
+                 double Cdt, int mode, int parity, const double *dt_one = nullptr)
 {
     UArgs a;
     a.nc = dm.nc;
@@ -2221,6 +2223,7 @@ UArgs fill_uargs(const DevMesh &dm, const double *u0, const double *prev, double
     a.alpha_clr = dm.alpha + (size_t)(parity ^ 1) * dm.alpha_slots() * 16;
     a.mid = dm.mid;
     a.dt_tab = dm.dt_tab;
+    a.dt_one = dt_one;
     a.spm = dm.slots_per_mesh;
     a.nslot = (int)dm.alpha_slots();
     a.A = A;
@@ -2238,9 +2241,9 @@ UArgs fill_uargs(const DevMesh &dm, const double *u0, const double *prev, double
 }
 
 int launch_update(const DevMesh &dm, const double *u0, const double *prev, double *out, double A, double B,
-                  double Cdt, int mode, int parity, void *stream)
+                  double Cdt, int mode, int parity, void *stream, const double *dt_one)
 {
-    UArgs a = fill_uargs(dm, u0, prev, out, A, B, Cdt, mode, parity);
+    UArgs a = fill_uargs(dm, u0, prev, out, A, B, Cdt, mode, parity, dt_one);
     hipStream_t st = (hipStream_t)stream;
     if (dm.dim == 1) return launch_k23<1, 1>(dm, a, st);
     if (dm.dim == 2) {
