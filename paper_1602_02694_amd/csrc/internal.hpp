@@ -22,8 +22,19 @@ int num_coeffs(int dim, int p);
 // whose stencils have at most cap[b] rows; its variant keeps ceil(cap[b]/G)
 // rows per lane with G lanes per cell.
 constexpr int kMaxBuckets = 3;
-// Ascending bucket capacities compiled for (dim, p); empty if none.
-std::vector<int> stencil_capacities(int dim, int p);
+// Ascending bucket capacities compiled for (dim, p); empty if none.  They
+// match the rows-per-lane template arguments of the reconstruction kernels.
+inline std::vector<int> stencil_capacities(int dim, int p)
+{
+    if (dim == 1 && p >= 2 && p <= 5) return {8};
+    if (dim == 2 && p == 2) return {8};
+    if (dim == 2 && p == 3) return {12, 16, 20};
+    if (dim == 2 && p == 4) return {20, 28, 36};
+    if (dim == 2 && p == 5) return {24, 32, 40};
+    if (dim == 3 && p == 2) return {16};
+    if (dim == 3 && p == 3) return {32, 40, 56};
+    return {};
+}
 // Facet quadrature points per facet (1-D: 1; 2-D: ceil(p/2); 3-D: 3).
 int points_per_face(int dim, int p);
 

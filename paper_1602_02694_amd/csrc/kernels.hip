@@ -2068,18 +2068,6 @@ int launch_adj(AArgs args, hipStream_t st)
     return (int)hipGetLastError();
 }
 
-std::vector<int> stencil_capacities(int dim, int p)
-{
-    if (dim == 1 && p >= 2 && p <= 5) return {8};
-    if (dim == 2 && p == 2) return {8};
-    if (dim == 2 && p == 3) return {12, 16, 20};
-    if (dim == 2 && p == 4) return {20, 28, 36};
-    if (dim == 2 && p == 5) return {24, 32, 40};
-    if (dim == 3 && p == 2) return {16};
-    if (dim == 3 && p == 3) return {32, 40, 56};
-    return {};
-}
-
 int default_lanes(const DevMesh &dm)
 {
     return dm.dim == 3 ? 8 : (dm.dim == 2 && dm.p == 3 ? 2 : (dm.dim == 2 && dm.p == 5 ? 16 : 4));
