@@ -60,7 +60,8 @@ def build(verbose: bool = False) -> str:
     objs.append(o)
     tmp = LIB + ".tmp"
     _run([cxx, "-shared", "-fopenmp", "-o", tmp] + objs +
-         ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib")], verbose)
+         ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lrocprofiler-sdk-roctx",
+          "-Wl,-rpath," + os.path.join(ROCM, "lib")], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -3,6 +3,7 @@
 // kernels of kernels.hip; this file validates arguments, owns device memory
 // and enqueues the kernels on the context's stream.
 #include <hip/hip_runtime_api.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cmath>
 #include <cstring>
@@ -350,6 +351,15 @@ int64_t user_cells(const wlseno_ctx *ctx)
 int user_vars(const wlseno_ctx *ctx) { return ctx->groups.empty() ? ctx->dm.nvars : ctx->groups[0].c->dm.nvars; }
 
 }  // namespace
+
+// A roctx range around each call that enqueues device work, so that a
+// marker trace shows the C-ABI calls above their kernels (no cost without a tool).
+struct ApiRange {
+    explicit ApiRange(const char *name) { roctxRangePushA(name); }
+    ~ApiRange() { roctxRangePop(); }
+    ApiRange(const ApiRange &) = delete;
+    ApiRange &operator=(const ApiRange &) = delete;
+};
 
 #define API_BEGIN(ctx)                                                   \
     if (!(ctx)) return WLSENO_EINVAL;                                    \
@@ -709,6 +719,7 @@ wlseno_status wlseno_batch_params(wlseno_t ctx, int dim, const wlseno_params *pa
 wlseno_status wlseno_stencil_build(wlseno_t ctx, const wlseno_params *params)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_stencil_build");
     if (!params) throw Error{WLSENO_EINVAL, "params is NULL"};
     if (!ctx->have_mesh) throw Error{WLSENO_ESTATE, "call wlseno_mesh_upload first"};
     if (mixed(ctx)) {
@@ -849,6 +860,7 @@ wlseno_status wlseno_reconstruct(wlseno_t ctx, const double *u_dev, double *coef
                                  int32_t *rank_dev)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_reconstruct");
     if (!u_dev) throw Error{WLSENO_EINVAL, "u_dev is NULL"};
     need_single_dim(ctx, "wlseno_reconstruct (per-dim coefficient and facet layouts)");
     if (coef_dev && ctx->have_build && ctx->build.prm.characteristic)
@@ -872,6 +884,7 @@ wlseno_status wlseno_reconstruct(wlseno_t ctx, const double *u_dev, double *coef
 wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_rhs");
     if (!u_dev || !dudt_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
     if (u_dev == dudt_dev) throw Error{WLSENO_EINVAL, "dudt_dev must not alias u_dev"};
     need_device(ctx);
@@ -893,6 +906,7 @@ wlseno_status wlseno_rhs(wlseno_t ctx, const double *u_dev, double *dudt_dev)
 wlseno_status wlseno_rhs_noalloc(wlseno_t ctx, const double *u_dev, double *dudt_dev)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_rhs_noalloc");
     if (!u_dev || !dudt_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
     if (u_dev == dudt_dev) throw Error{WLSENO_EINVAL, "dudt_dev must not alias u_dev"};
     need_device(ctx);
@@ -969,6 +983,7 @@ void vjp(wlseno_ctx *c, const double *u, const double *v, const double *x, const
 wlseno_status wlseno_rhs_vjp(wlseno_t ctx, const double *u_dev, const double *v_dev, double *out_dev)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_rhs_vjp");
     if (!u_dev || !v_dev || !out_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
     if (out_dev == u_dev || out_dev == v_dev) throw Error{WLSENO_EINVAL, "out_dev must not alias an input"};
     need_device(ctx);
@@ -1050,6 +1065,7 @@ wlseno_status wlseno_step_adjoint(wlseno_t ctx, const double *u0_dev, double dt,
                                   const double *gT_dev, double *g0_dev)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_step_adjoint");
     if (!u0_dev || !gT_dev || !g0_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
     check_adjoint_args(dt, n_steps, ckpt_every);
     need_device(ctx);
@@ -1064,6 +1080,7 @@ wlseno_status wlseno_step_adjoint(wlseno_t ctx, const double *u0_dev, double dt,
 wlseno_status wlseno_step_record(wlseno_t ctx, double *u_dev, double dt, int n_steps, int ckpt_every)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_step_record");
     if (!u_dev) throw Error{WLSENO_EINVAL, "u_dev is NULL"};
     check_adjoint_args(dt, n_steps, ckpt_every);
     need_device(ctx);
@@ -1081,6 +1098,7 @@ wlseno_status wlseno_step_record(wlseno_t ctx, double *u_dev, double dt, int n_s
 wlseno_status wlseno_step_adjoint_recorded(wlseno_t ctx, const double *gT_dev, double *g0_dev)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_step_adjoint_recorded");
     if (!gT_dev || !g0_dev) throw Error{WLSENO_EINVAL, "null device pointer"};
     need_device(ctx);
     if (!ctx->rec_valid) throw Error{WLSENO_ESTATE, "no recorded trajectory (wlseno_step_record first)"};
@@ -1162,6 +1180,7 @@ void run_steps(wlseno_ctx *ctx, double *u_dev, double dt, const double *dt_mesh,
 wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_step");
     if (!u_dev) throw Error{WLSENO_EINVAL, "u_dev is NULL"};
     if (!std::isfinite(dt) || n_steps < 0) throw Error{WLSENO_EINVAL, "dt must be finite and n_steps >= 0"};
     need_device(ctx);
@@ -1181,6 +1200,7 @@ wlseno_status wlseno_step(wlseno_t ctx, double *u_dev, double dt, int n_steps)
 wlseno_status wlseno_batch_step(wlseno_t ctx, double *u_dev, const double *dt_per_mesh, int n_steps)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_batch_step");
     if (!u_dev || !dt_per_mesh) throw Error{WLSENO_EINVAL, "null pointer"};
     if (n_steps < 0) throw Error{WLSENO_EINVAL, "n_steps >= 0 required"};
     need_device(ctx);
@@ -1275,6 +1295,7 @@ wlseno_status wlseno_batch_last_alpha(wlseno_t ctx, double *alpha_per_mesh)
 wlseno_status wlseno_time_kernel(wlseno_t ctx, int kernel, const double *u_dev, int launches, double *avg_ms)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_time_kernel");
     if (!u_dev || !avg_ms) throw Error{WLSENO_EINVAL, "null pointer"};
     if (kernel != 0 && kernel != 1) throw Error{WLSENO_EINVAL, "kernel must be 0 or 1"};
     if (launches < 1) throw Error{WLSENO_EINVAL, "launches must be >= 1"};
@@ -1390,6 +1411,7 @@ extern "C" {
 wlseno_status wlseno_autotune(wlseno_t ctx, const double *u_dev, wlseno_tune *out)
 {
     API_BEGIN(ctx)
+    ApiRange range_("wlseno_autotune");
     if (!out) throw Error{WLSENO_EINVAL, "out is NULL"};
     need_device(ctx);
     std::memset(out, 0, sizeof(*out));
