@@ -101,7 +101,7 @@ void check_launch(int e, const char *what)
 constexpr int kGraphLadder = 5;
 constexpr int kGraphSteps[kGraphLadder] = {32, 16, 8, 4, 2};
 // Cells up to which newly captured graphs get one replay ahead of use.
-constexpr int64_t kPrereplayCells = int64_t(1) << 18;
+constexpr int64_t kPrereplayCells = int64_t(1) << 16;
 
 void drop_graph(wlseno_ctx *c)
 {
