@@ -153,7 +153,7 @@ constexpr int kAlphaSlotsBatch = 8;   // slots per mesh of a batch
 // Returns hipSuccess (0) or an error code; `supported` tells whether the
 // (dim, p, stencil size) combination has a compiled variant.
 bool reconstruct_supported(const DevMesh &dm);
-// Lane counts per cell compiled for the reconstruction of this build (the
+// Lane counts per cell compiled for the reconstruction of this stencil build (the
 // automatic choice first is not implied; the autotuner times them all).
 std::vector<int> lane_choices(const DevMesh &dm);
 // The automatic lane count (wlseno_params.lanes = 0).
