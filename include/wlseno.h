@@ -373,7 +373,7 @@ typedef struct {
 } wlseno_tune;
 
 /* Launch-shape autotuner of the reconstruction kernel: times every lane count
- * per cell compiled for this build (2-D p = 3: 2, 4, 8, 16; p = 4: 4, 8, 16;
+ * per cell compiled for the current stencil build (2-D p = 3: 2, 4, 8, 16; p = 4: 4, 8, 16;
  * p = 5 and 3-D p = 3: 8, 16; otherwise one) on this mesh, back-to-back launches
  * between HIP events (~20 ms each), and keeps the fastest for this context
  * (the automatic choice of wlseno_params.lanes = 0 unless another is faster
