@@ -104,12 +104,15 @@ WORKLOADS = {
 }
 
 
-def make_workload(name):
-    """Mesh and initial cell averages, built in two logged phases."""
+def make_workload(name, side=0):
+    """Mesh and initial cell averages, built in two logged phases (side > 0:
+    that many lattice points per side instead of the workload's own)."""
     from workloads import fields, jittered_cube, jittered_square
     from workloads.configs import Workload
 
-    cfg = WORKLOADS[name]
+    cfg = dict(WORKLOADS[name])
+    if side:
+        cfg["side"] = int(side)
     t = time.time()
     if cfg["dim"] == 2:
         mesh = jittered_square(cfg["side"], 0.3, cfg["seed"])
@@ -610,6 +613,9 @@ def main():
                     help="lanes per cell of the reconstruction (0: autotune); profiling runs pin it")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 2 M-triangle companion record of the default workload")
+    ap.add_argument("--side", type=int, default=0,
+                    help="single-mesh workloads: lattice points per side instead of the workload's own (a size "
+                         "sweep; no stored traffic counters apply then)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs a mesh, or a "
@@ -623,7 +629,7 @@ def main():
     if args.workload == "batch":
         print(json.dumps(run_batch(args, torch, WLSENO)), flush=True)
         return
-    wl = make_workload(args.workload)
+    wl = make_workload(args.workload, args.side)
     cfg = wl.settings
     mesh = wl.mesh
     dim = mesh.dim
@@ -697,7 +703,8 @@ def main():
     achieved = flops / (k1_avg * 1e-3) / 1e12
     log(f"[bench] k_reconstruct avg {k1_avg * 1e3:.2f} us ({k1_n} launches), "
         f"k_update avg {k2_avg * 1e3:.2f} us ({k2_n} launches); {flops / nc:.0f} flop/cell")
-    tkey = args.workload + ("-balance" if args.balance else "")
+    # counters were taken on the workloads' own meshes only
+    tkey = None if args.side else args.workload + ("-balance" if args.balance else "")
     traffic = traffic_record(f"k_reconstruct/{tune['chosen']}", tkey)
     roofline = {
         "bound": "alu",
