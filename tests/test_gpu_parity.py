@@ -848,6 +848,19 @@ def test_numeric_check():
     assert e.value.status == 6
     cell = int(str(e.value).split("cell ")[1].split(")")[0])
     assert m.n_cell <= cell < m.n_cell + cube.n_cell
+    # a one-dim batch stepped with per-mesh time steps
+    meshes, us = _batch("burgers", 3404)
+    wc = WLSENO(device=0)
+    for mm in meshes:
+        wc.batch_add_mesh(2, mm.verts, mm.cells)
+    wc.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers")
+    wc.set_numeric_check(True)
+    ubc = torch.tensor(np.concatenate(us, axis=1).reshape(-1), device="cuda")
+    wc.batch_step(ubc.clone(), [1e-4] * len(meshes), 2)
+    ubc[meshes[0].n_cell + 3] = float("nan")
+    with pytest.raises(WLSENOError) as e:
+        wc.batch_step(ubc, [1e-4] * len(meshes), 2)
+    assert e.value.status == 6 and "input average" in str(e.value)
 
 
 @pytest.mark.parametrize("case", ["single", "batch", "balance", "characteristic", "cube-local-alpha"])

@@ -62,3 +62,28 @@ def test_rhs_noalloc_refuses_oversized_scratch():
     with pytest.raises(WLSENOError) as e:
         w.rhs_noalloc(u, out)
     assert e.value.status == 1 and "scratch" in str(e.value)
+
+
+def test_rhs_noalloc_mixed_batch():
+    """A batch of 2-D and 3-D meshes: the groups run one after another in the
+    same static array, and the result equals wlseno_rhs bit for bit."""
+    from paper_1602_02694_amd import WLSENO
+    from workloads import jittered_cube
+
+    torch = _torch()
+    sq = jittered_square(14, 0.3, 7305)
+    cube = jittered_cube(4, 0.15, 7306)
+    print(f"[case] noalloc mixed batch: {sq.n_cell} triangles + {cube.n_cell} tetrahedra", flush=True)
+    w = WLSENO(device=0)
+    w.batch_add_mesh(2, sq.verts, sq.cells)
+    w.batch_add_mesh(3, cube.verts, cube.cells)
+    w.batch_params(3, p=2, n_lo=8, n_hi=16, flux="burgers")
+    w.stencil_build(p=3, n_lo=12, n_hi=20, flux="burgers")
+    u = torch.tensor(np.concatenate([fields.cell_averages(sq, fields.gaussian_bump_with_step_2d),
+                                     fields.cell_averages(cube, fields.sine_with_sphere_3d)]), device="cuda")
+    for _ in range(2):
+        ref = w.rhs(u)
+        out = torch.full_like(u, float("nan"))
+        w.rhs_noalloc(u, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
