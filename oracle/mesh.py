@@ -288,6 +288,12 @@ class OracleMesh:
         return d
 
     def stencil(self, i, n_lo, n_hi):
+        """Stencil of cell i by the size rule of Sec. 3.2: rings of the
+        kinds ring_kinds() gives, grown until the set holds n_lo cells, then
+        the centre and its n_hi - 1 nearest members (squared centroid
+        distance, ties by index).  Parity unpinned beyond the cases the tests
+        enumerate by hand: on other meshes the sets are only checked equal to
+        the library's independent builder."""
         kinds = self.ring_kinds()
         frac = len(kinds)
         S = None
