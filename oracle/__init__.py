@@ -22,9 +22,10 @@ oracle to the paper and to mathematics (not to itself) live in
 "parity unpinned" where they are defined; at present that is the k-ring
 stencil *sets* beyond the cases the tests enumerate by hand and cells of real
 meshes whose numerical rank is truncated (the truncation rule is pinned on
-constructed matrices).  Which cells the Euler positivity fallback selects is
-pinned through its definition only: the unlimited reconstruction rebuilt from
-this oracle's own cell matrices, weights and solver.
+constructed matrices).  Which cells the Euler positivity fallback and the
+balanced refit select is pinned through their definitions only: the first
+(unlimited) fit rebuilt from this oracle's own cell matrices, weights and
+solver.
 """
 
 from .core import (Oracle, build, basis, num_coeffs, wls_qrcp_solve, simplex_avg_monomial, eval_taylor, from_workload,
